@@ -335,14 +335,16 @@ double orc_true_residual(const int *L, const int *bc, const double *U, double m0
  *   c_l = k^2 sn^2(l K'/(2n); k') / cn^2(l K'/(2n); k'),  k' = sqrt(1-k^2),
  *   K'  = K(k') = pi / (2 AGM(1, k)),  sigma_j = c_{2j-1},
  *   a_j = prod_i (c_{2i} - sigma_j) / prod_{i != j} (sigma_i - sigma_j).
- * sn, cn from the descending Landen (AGM) scheme of Abramowitz & Stegun 16.4.
+ * sn, cn from the descending Landen (AGM) scheme of Abramowitz & Stegun 16.4,
+ * started from the complementary modulus k itself (forming sqrt(1-k'^2) from
+ * k' ~ 1 would cancel).
  * D and the error delta follow from the extremes of R(x) = x sum a_j/(x^2+sigma_j)
  * on [k,1]:  D = 2/(max+min), delta = (max-min)/(max+min).
  */
-static void sncn(double u, double m /* modulus */, double *sn, double *cn)
+static void sncn(double u, double m /* modulus */, double mc /* sqrt(1-m^2) */, double *sn, double *cn)
 {
     double a[64], c[64];
-    double an = 1.0, bn = sqrt(1.0 - m * m);
+    double an = 1.0, bn = mc;
     int N = 0;
     a[0] = an;
     c[0] = m;
@@ -385,7 +387,7 @@ void orc_zolotarev(double k, int n, double *sigma, double *a, double *D, double 
     double *c = malloc(sizeof(double) * 2 * n);
     for (int l = 1; l <= 2 * n - 1; l++) {
         double sn, cn;
-        sncn(l * Kp / (2.0 * n), kp, &sn, &cn);
+        sncn(l * Kp / (2.0 * n), kp, k, &sn, &cn);
         c[l] = k * k * sn * sn / (cn * cn);
     }
     for (int j = 0; j < n; j++) sigma[j] = c[2 * j + 1];

@@ -1,0 +1,251 @@
+/*
+ * ovl.h -- C ABI of an MI355X (gfx950) library that applies the Neuberger
+ * overlap operator with a Wilson-Dirac kernel,
+ *
+ *     D_ov = rho (I + Gamma_5 sign(Q)),   Q = Gamma_5 D_W(-rho),
+ *
+ * following Brannick, Frommer, Kahl, Leder, Rottmann, Strebel, "Multigrid
+ * preconditioning for the overlap operator in lattice QCD" (arXiv:1410.7170):
+ * D_W is eq. (Wilson-Dirac), Gamma_5-hermiticity is eq. (gamma_5_symmetry),
+ * the overlap operator is eq. (overlap_def) written in the massless
+ * normalisation rho (I + Gamma_5 sign(Gamma_5 D_W(-rho))).  sign(Q) is a
+ * Zolotarev rational function of Q whose shifted systems
+ * (Q^2 + s_l) x_l = b are solved together by multishift CG.
+ *
+ * Conventions
+ * -----------
+ * Lattice: extents dims[0..3] = (L0, L1, L2, L3), x0 is time, every extent even
+ *   (the device layout is even-odd, as in the red-black ordering of the
+ *   proof of Lemma 1).  Hops that cross the boundary in direction mu carry the
+ *   phase bc[mu] in {+1,-1}; the usual choice is (-1,+1,+1,+1).
+ * Canonical host/device order (complex128):
+ *   spinor psi[site][spin][colour], gauge U[site][mu][row][col] with U_mu(x)
+ *   the link from x to x+mu, site = ((x0*L1 + x1)*L2 + x2)*L3 + x3.
+ * gamma basis: Hermitian chiral basis, gamma_0 = [[0,I],[I,0]],
+ *   gamma_k = [[0,-i sigma_k],[i sigma_k,0]], gamma_5 = g0 g1 g2 g3 = diag(-1,-1,1,1).
+ * Device layouts (all produced by the pack calls below; treat as opaque):
+ *   OVL_F64  spinor: complex128 per component, [rhs][parity][12][V/2]
+ *   OVL_F32  spinor: float4 (two components), [rhs][parity][6][V/2]
+ *   OVL_F16S spinor: 8 halves (four components), [rhs][parity][3][V/2], plus
+ *            one float scale per site [rhs][parity][V/2]: stored = value/scale,
+ *            scale = largest |real or imaginary part| at that site
+ *   gauge F64: complex128 per entry, 18 reals, [parity][mu][9][V/2]
+ *   gauge F32: rows 0 and 1 as 3 float4, [parity][mu][3][V/2]; row 2 is
+ *            rebuilt as conj(row0 x row1) (exact for SU(3))
+ *   gauge F16: rows 0 and 1 as 3 x 4 halves, [parity][mu][3][V/2]
+ *
+ * Every call is asynchronous on the caller's HIP stream (`stream`, a
+ * hipStream_t; NULL is the null stream) unless it says it synchronises.
+ * Device pointers are plain device addresses; the library keeps no pointer
+ * after a call returns and allocates no device memory: temporaries live in a
+ * caller-provided workspace whose size ovl_workspace_bytes reports.
+ * Return values: OVL_OK (0); OVL_NOT_CONVERGED (1) -- outputs and stats hold
+ * the last iterate; negative values are errors and leave outputs undefined:
+ *   OVL_ERR_INVALID    null pointer, odd extent, mismatched precision or
+ *                      RHS count, aliased input/output, out-of-range count
+ *   OVL_ERR_WORKSPACE  workspace too small
+ *   OVL_ERR_HIP        a HIP call failed (ovl_last_hip_error gives its code)
+ *   OVL_ERR_NONFINITE  a norm became NaN or Inf
+ * No call throws across this boundary.
+ */
+#ifndef OVL_H
+#define OVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define OVL_API __attribute__((visibility("default")))
+#else
+#define OVL_API
+#endif
+
+#define OVL_MAX_SHIFTS 32
+#define OVL_MAX_RHS 16
+
+enum ovl_status {
+    OVL_OK = 0,
+    OVL_NOT_CONVERGED = 1,
+    OVL_ERR_INVALID = -1,
+    OVL_ERR_WORKSPACE = -2,
+    OVL_ERR_HIP = -3,
+    OVL_ERR_NONFINITE = -4
+};
+
+/* storage precision of a field; arithmetic is FP64 for OVL_F64 and FP32
+ * (FP64 accumulation of dot products) for OVL_F32 and OVL_F16S */
+enum ovl_prec { OVL_F64 = 0, OVL_F32 = 1, OVL_F16S = 2 };
+
+/* solver precision modes */
+enum ovl_solve_mode {
+    OVL_SOLVE_F64 = 0,   /* every vector, link and stencil in FP64 */
+    OVL_SOLVE_MIXED = 1  /* sloppy FP32/FP16 Krylov bulk, FP64 reliable updates,
+                            FP64 per-shift verification and final combination */
+};
+
+typedef struct {
+    int32_t dims[4];   /* L0 (time), L1, L2, L3; all even, all >= 2 */
+    int32_t bc[4];     /* boundary phase per direction, +1 or -1 */
+    int64_t vol;       /* filled by ovl_lattice_init */
+} ovl_lattice;
+
+/* A gauge field packed in up to three precisions (device pointers).  An
+ * operation uses the copy matching its precision and fails with
+ * OVL_ERR_INVALID if that copy is NULL. */
+typedef struct {
+    const void *f64;
+    const void *f32;
+    const void *f16;
+} ovl_gauge;
+
+/* nrhs packed spinor fields of one precision, stored back to back. */
+typedef struct {
+    void *d;           /* device data */
+    float *scale;      /* OVL_F16S only: per-site scales, else NULL */
+    int32_t prec;      /* enum ovl_prec */
+    int32_t nrhs;      /* 1 .. OVL_MAX_RHS */
+} ovl_spinor;
+
+/* Zolotarev data: sign(x) ~ x sum_l weights[l] / (x^2 + shifts[l]) on
+ * lambda_min <= |x| <= lambda_max (host arrays). */
+typedef struct {
+    int32_t npoles;
+    const double *shifts;
+    const double *weights;
+} ovl_zolo;
+
+typedef struct {
+    double tol;              /* target relative residual of every shifted system */
+    int32_t maxiter;         /* cap on multishift CG iterations */
+    int32_t mode;            /* enum ovl_solve_mode */
+    double reliable_delta;   /* mixed: FP64 residual replacement when ||r|| has
+                                fallen by this factor since the last one */
+    int32_t check_every;     /* iterations between host convergence polls */
+    int32_t refine;          /* mixed: verify each shift in FP64 and refine
+                                those above tol (1) or only report (0) */
+    int32_t verify;          /* FP64 mode: also compute every shift's FP64 true
+                                residual into stats (2 FP64 stencils per shift) */
+} ovl_solver_params;
+
+typedef struct {
+    int32_t iterations[OVL_MAX_RHS];                  /* multishift CG iterations per RHS */
+    int32_t shift_iters[OVL_MAX_RHS][OVL_MAX_SHIFTS]; /* iteration at which each shift froze */
+    double true_residual[OVL_MAX_RHS][OVL_MAX_SHIFTS];/* FP64 ||b-(Q^2+s)x||/||b||, or -1 if not computed */
+    int32_t reliable_updates;                          /* FP64 residual replacements */
+    int32_t refine_iterations;                         /* iterations spent in per-shift refinement */
+    int32_t stencil_applies;                           /* Wilson stencils launched (per RHS batch) */
+    double algorithmic_bytes;                          /* compulsory HBM bytes of the launches */
+    double seconds;                                    /* wall time of the call (it synchronises) */
+} ovl_solver_stats;
+
+/* ---- set-up and layout ------------------------------------------------ */
+
+/* Validates dims (even, >= 2) and bc (+1/-1) and fills lat->vol. */
+OVL_API int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4]);
+
+/* Bytes of one packed spinor field (per RHS) and of its scale array. */
+OVL_API size_t ovl_spinor_bytes(const ovl_lattice *lat, int32_t prec);
+OVL_API size_t ovl_scale_bytes(const ovl_lattice *lat);
+/* Bytes of a packed gauge field of the given precision. */
+OVL_API size_t ovl_gauge_bytes(const ovl_lattice *lat, int32_t prec);
+
+/* Canonical complex128 device spinors ([nrhs][V][4][3]) to and from the
+ * packed layout of out->prec / in->prec.  F16S packing picks the per-site
+ * scale; unpacking widens exactly. */
+OVL_API int ovl_pack_spinor(const ovl_lattice *lat, const void *canon, ovl_spinor *out, void *stream);
+OVL_API int ovl_unpack_spinor(const ovl_lattice *lat, const ovl_spinor *in, void *canon, void *stream);
+
+/* Canonical complex128 device gauge field ([V][4][3][3]) to the packed layout
+ * of precision prec, written to out (ovl_gauge_bytes(lat, prec) bytes). */
+OVL_API int ovl_pack_gauge(const ovl_lattice *lat, const void *canon, int32_t prec, void *out, void *stream);
+
+/* ---- operators ---------------------------------------------------------- */
+
+/* out = D_W(m0) in, eq. (Wilson-Dirac) with a = 1:
+ *   (D_W psi)(x) = (m0+4) psi(x) - 1/2 sum_mu (I - gamma_mu) U_mu(x) psi(x+mu)
+ *                                - 1/2 sum_mu (I + gamma_mu) U_mu(x-mu)^H psi(x-mu).
+ * in and out: same precision and RHS count, distinct buffers.  All RHS share
+ * each link load. */
+OVL_API int ovl_wilson_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0,
+                     const ovl_spinor *in, ovl_spinor *out, void *stream);
+
+/* out = Q in = Gamma_5 D_W(m0) in (Hermitian by eq. (gamma_5_symmetry)). */
+OVL_API int ovl_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0,
+                const ovl_spinor *in, ovl_spinor *out, void *stream);
+
+/* out = (Q^2 + shift) in, Q^2 = D_W^H D_W.  ws: device workspace of at least
+ * ovl_workspace_bytes(lat, OVL_OP_Q2, in->prec, in->nrhs, 0, NULL) bytes. */
+OVL_API int ovl_q2_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, double shift,
+                 const ovl_spinor *in, ovl_spinor *out, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- sign function and overlap ------------------------------------------ */
+
+/* Zolotarev coefficients (host only): shifts[n], weights[n] with
+ * sign(x) ~ x sum_l weights[l]/(x^2+shifts[l]) for lambda_min <= |x| <= lambda_max,
+ * and the relative error bound *delta on that range. */
+OVL_API int ovl_zolotarev(double lambda_min, double lambda_max, int32_t npoles,
+                  double *shifts, double *weights, double *delta);
+
+/* Bounds of |Q| = sqrt(Q^2) from iters Lanczos steps on Q^2 in FP64 started
+ * at the FP64 device spinor `start` (its random numbers are the caller's).
+ * The extreme Ritz values lie inside the spectrum; the returned interval is
+ * widened to [lo_margin*sqrt(theta_min), hi_margin*sqrt(theta_max)].
+ * Synchronises the stream. */
+OVL_API int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,
+                        const ovl_spinor *start, double lo_margin, double hi_margin,
+                        double *lambda_min, double *lambda_max,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* Multishift CG on (Q^2 + shifts[l]) x_l = b, l = 0..nshift-1, every RHS of b
+ * independently.  If weights is NULL, x holds nshift*b->nrhs fields
+ * (field index l*nrhs + r, FP64; this count may exceed OVL_MAX_RHS);
+ * otherwise x holds b->nrhs FP64 fields
+ * y_r = sum_l weights[l] x_{l,r}.  b: FP64 spinor.  Synchronises the stream;
+ * fills stats if non-NULL. */
+OVL_API int ovl_multishift_cg(const ovl_lattice *lat, const ovl_gauge *U, double m0,
+                      int32_t nshift, const double *shifts, const double *weights,
+                      const ovl_spinor *b, ovl_spinor *x, const ovl_solver_params *prm,
+                      ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* out = sign(Q) b ~ Q sum_l w_l (Q^2 + s_l)^{-1} b, Q = Gamma_5 D_W(m0).
+ * b, out: FP64 spinors with equal nrhs.  Synchronises the stream. */
+OVL_API int ovl_sign_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_zolo *z,
+                     const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
+                     ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* out = D_ov b = rho (b + Gamma_5 sign(Q) b) = rho (b + D_W(-rho) y),
+ * y = sum_l w_l (Q^2 + s_l)^{-1} b, Q = Gamma_5 D_W(-rho) (eq. (overlap_def),
+ * massless normalisation).  b, out: FP64 spinors with equal nrhs; the final
+ * combination and stencil are FP64 in every mode.  Synchronises the stream. */
+OVL_API int ovl_overlap_apply(const ovl_lattice *lat, const ovl_gauge *U, double rho, const ovl_zolo *z,
+                      const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
+                      ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- workspace and diagnostics ------------------------------------------ */
+
+enum ovl_op {
+    OVL_OP_Q2 = 0,
+    OVL_OP_LANCZOS = 1,
+    OVL_OP_MSCG = 2,      /* ovl_multishift_cg, sign_q_apply, overlap_apply */
+};
+
+/* Workspace bytes for an operation; prm may be NULL for OVL_OP_Q2/LANCZOS. */
+OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int32_t nrhs,
+                           int32_t nshift, const ovl_solver_params *prm);
+
+/* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
+ * check_every 10, refine 1, verify 0. */
+OVL_API void ovl_default_params(ovl_solver_params *prm);
+
+OVL_API const char *ovl_status_string(int status);
+OVL_API int ovl_last_hip_error(void);
+OVL_API const char *ovl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OVL_H */

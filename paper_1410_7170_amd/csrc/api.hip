@@ -1,0 +1,399 @@
+// C ABI entry points (include/ovl.h): argument validation on the host, then
+// the stream-ordered launches.  Nothing here throws; every failure is a status.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "mscg.h"
+
+namespace ovl {
+int last_hip_error();
+size_t mscg_ws_bytes(const Lat &L, int nrhs, int nshift);
+size_t lanczos_ws_bytes(const Lat &L);
+int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double *shifts, Fld b,
+             const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes, hipStream_t st,
+             MsScratch *scr);
+int true_residuals_f64(const Lat &L, const void *U64, double m0, double s, Fld b, Fld x, Fld q, Fld t,
+                       double *partials, double *red, double *out, hipStream_t st);
+hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st);
+int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
+                   char *ws, size_t ws_bytes, hipStream_t st);
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift);
+int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
+               Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
+               hipStream_t st);
+}  // namespace ovl
+
+using namespace ovl;
+
+namespace {
+
+bool lat_ok(const ovl_lattice *lat)
+{
+    if (!lat) return false;
+    int64_t V = 1;
+    for (int m = 0; m < 4; m++) {
+        if (lat->dims[m] < 2 || (lat->dims[m] & 1)) return false;
+        if (lat->bc[m] != 1 && lat->bc[m] != -1) return false;
+        V *= lat->dims[m];
+    }
+    return V < ((int64_t)1 << 31) && lat->vol == V;
+}
+
+bool spinor_ok(const ovl_spinor *s)
+{
+    if (!s || !s->d) return false;
+    if (s->prec < OVL_F64 || s->prec > OVL_F16S) return false;
+    if (s->nrhs < 1 || s->nrhs > OVL_MAX_RHS) return false;
+    if (s->prec == OVL_F16S && !s->scale) return false;
+    return true;
+}
+
+const void *gauge_for(const ovl_gauge *U, int prec)
+{
+    if (!U) return nullptr;
+    return prec == OVL_F64 ? U->f64 : prec == OVL_F32 ? U->f32 : U->f16;
+}
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+bool params_ok(const ovl_solver_params *p)
+{
+    return p && p->tol > 0.0 && std::isfinite(p->tol) && p->maxiter >= 1 &&
+           (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED) && p->reliable_delta > 0.0 &&
+           p->reliable_delta < 1.0;
+}
+
+bool zolo_ok(const ovl_zolo *z)
+{
+    if (!z || !z->shifts || !z->weights || z->npoles < 1 || z->npoles > OVL_MAX_SHIFTS) return false;
+    for (int j = 0; j < z->npoles; j++)
+        if (!(z->shifts[j] >= 0.0) || !std::isfinite(z->shifts[j]) || !std::isfinite(z->weights[j])) return false;
+    return true;
+}
+
+double now()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void clear_stats(ovl_solver_stats *st)
+{
+    if (!st) return;
+    std::memset(st, 0, sizeof *st);
+    for (int r = 0; r < OVL_MAX_RHS; r++)
+        for (int j = 0; j < OVL_MAX_SHIFTS; j++) st->true_residual[r][j] = -1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4])
+{
+    if (!lat || !dims || !bc) return OVL_ERR_INVALID;
+    int64_t V = 1;
+    for (int m = 0; m < 4; m++) {
+        lat->dims[m] = dims[m];
+        lat->bc[m] = bc[m];
+        if (dims[m] < 2 || (dims[m] & 1) || (bc[m] != 1 && bc[m] != -1)) return OVL_ERR_INVALID;
+        V *= dims[m];
+    }
+    if (V >= ((int64_t)1 << 31)) return OVL_ERR_INVALID;
+    lat->vol = V;
+    return OVL_OK;
+}
+
+size_t ovl_spinor_bytes(const ovl_lattice *lat, int32_t prec)
+{
+    if (!lat_ok(lat) || prec < 0 || prec > 2) return 0;
+    return field_bytes(prec, lat->vol);
+}
+
+size_t ovl_scale_bytes(const ovl_lattice *lat) { return lat_ok(lat) ? scale_bytes(lat->vol) : 0; }
+
+size_t ovl_gauge_bytes(const ovl_lattice *lat, int32_t prec)
+{
+    if (!lat_ok(lat)) return 0;
+    size_t links = (size_t)4 * lat->vol;
+    return prec == OVL_F64 ? links * 144 : prec == OVL_F32 ? links * 48 : prec == OVL_F16S ? links * 24 : 0;
+}
+
+int ovl_pack_spinor(const ovl_lattice *lat, const void *canon, ovl_spinor *out, void *stream)
+{
+    if (!lat_ok(lat) || !canon || !spinor_ok(out) || canon == out->d) return OVL_ERR_INVALID;
+    Lat L = make_lat(lat);
+    OVL_HIP(launch_pack_spinor(L, canon, fld(out), S(stream)));
+    return OVL_OK;
+}
+
+int ovl_unpack_spinor(const ovl_lattice *lat, const ovl_spinor *in, void *canon, void *stream)
+{
+    if (!lat_ok(lat) || !canon || !spinor_ok(in) || canon == in->d) return OVL_ERR_INVALID;
+    Lat L = make_lat(lat);
+    OVL_HIP(launch_unpack_spinor(L, fld(in), canon, S(stream)));
+    return OVL_OK;
+}
+
+int ovl_pack_gauge(const ovl_lattice *lat, const void *canon, int32_t prec, void *out, void *stream)
+{
+    if (!lat_ok(lat) || !canon || !out || canon == out || prec < 0 || prec > 2) return OVL_ERR_INVALID;
+    Lat L = make_lat(lat);
+    OVL_HIP(launch_pack_gauge(L, canon, prec, out, S(stream)));
+    return OVL_OK;
+}
+
+static int apply_q_or_w(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_spinor *in,
+                        ovl_spinor *out, void *stream, bool g5)
+{
+    if (!lat_ok(lat) || !spinor_ok(in) || !spinor_ok(out)) return OVL_ERR_INVALID;
+    if (in->prec != out->prec || in->nrhs != out->nrhs || in->d == out->d || !std::isfinite(m0)) return OVL_ERR_INVALID;
+    const void *Ud = gauge_for(U, in->prec);
+    if (!Ud) return OVL_ERR_INVALID;
+    Lat L = make_lat(lat);
+    WArgs a{};
+    a.in = in->d;
+    a.in_sc = in->scale;
+    a.out = out->d;
+    a.out_sc = out->scale;
+    a.U = Ud;
+    a.diag = m0 + 4.0;
+    a.nrhs = in->nrhs;
+    OVL_HIP(launch_wilson(L, in->prec, W_PLAIN, g5, a, S(stream)));
+    return OVL_OK;
+}
+
+int ovl_wilson_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_spinor *in, ovl_spinor *out,
+                     void *stream)
+{
+    return apply_q_or_w(lat, U, m0, in, out, stream, false);
+}
+
+int ovl_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_spinor *in, ovl_spinor *out,
+                void *stream)
+{
+    return apply_q_or_w(lat, U, m0, in, out, stream, true);
+}
+
+int ovl_q2_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, double shift, const ovl_spinor *in,
+                 ovl_spinor *out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!lat_ok(lat) || !spinor_ok(in) || !spinor_ok(out)) return OVL_ERR_INVALID;
+    if (in->prec != out->prec || in->nrhs != out->nrhs || in->d == out->d) return OVL_ERR_INVALID;
+    if (!std::isfinite(m0) || !std::isfinite(shift)) return OVL_ERR_INVALID;
+    const void *Ud = gauge_for(U, in->prec);
+    if (!Ud || !ws) return OVL_ERR_INVALID;
+    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_Q2, in->prec, in->nrhs, 0, nullptr)) return OVL_ERR_WORKSPACE;
+    Lat L = make_lat(lat);
+    char *w = (char *)ws;
+    size_t F = field_bytes(in->prec, L.V) * in->nrhs;
+    void *tmp = w;
+    float *tsc = in->prec == OVL_F16S ? (float *)(w + ((F + 255) & ~(size_t)255)) : nullptr;
+    WArgs a{};
+    a.in = in->d;
+    a.in_sc = in->scale;
+    a.out = tmp;
+    a.out_sc = tsc;
+    a.U = Ud;
+    a.diag = m0 + 4.0;
+    a.nrhs = in->nrhs;
+    OVL_HIP(launch_wilson(L, in->prec, W_PLAIN, true, a, S(stream)));
+    WArgs b = a;
+    b.in = tmp;
+    b.in_sc = tsc;
+    b.p = in->d;
+    b.p_sc = in->scale;
+    b.shift = shift;
+    b.out = out->d;
+    b.out_sc = out->scale;
+    OVL_HIP(launch_wilson(L, in->prec, W_SHIFT, true, b, S(stream)));
+    return OVL_OK;
+}
+
+size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int32_t nrhs, int32_t nshift,
+                           const ovl_solver_params *prm)
+{
+    if (!lat_ok(lat) || nrhs < 1 || nrhs > OVL_MAX_RHS) return 0;
+    Lat L = make_lat(lat);
+    if (op == OVL_OP_Q2) {
+        if (prec < 0 || prec > 2) return 0;
+        size_t F = field_bytes(prec, L.V) * nrhs;
+        return ((F + 255) & ~(size_t)255) + scale_bytes(L.V) * nrhs + 256;
+    }
+    if (op == OVL_OP_LANCZOS) return lanczos_ws_bytes(L);
+    if (op == OVL_OP_MSCG) {
+        if (nshift < 1 || nshift > OVL_MAX_SHIFTS) return 0;
+        size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
+        if (prm && prm->mode == OVL_SOLVE_MIXED) return yb + mixed_ws_bytes(L, nrhs, nshift);
+        return yb + mscg_ws_bytes(L, nrhs, nshift);
+    }
+    return 0;
+}
+
+void ovl_default_params(ovl_solver_params *p)
+{
+    if (!p) return;
+    p->tol = 1e-10;
+    p->maxiter = 2000;
+    p->mode = OVL_SOLVE_F64;
+    p->reliable_delta = 0.1;
+    p->check_every = 10;
+    p->refine = 1;
+    p->verify = 0;
+}
+
+int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,
+                        const ovl_spinor *start, double lo_margin, double hi_margin, double *lambda_min,
+                        double *lambda_max, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!lat_ok(lat) || !spinor_ok(start) || start->prec != OVL_F64 || start->nrhs != 1) return OVL_ERR_INVALID;
+    if (!U || !U->f64 || !lambda_min || !lambda_max || !ws || iters < 2) return OVL_ERR_INVALID;
+    if (!(lo_margin > 0.0 && lo_margin <= 1.0 && hi_margin >= 1.0)) return OVL_ERR_INVALID;
+    Lat L = make_lat(lat);
+    if (ws_bytes < lanczos_ws_bytes(L)) return OVL_ERR_WORKSPACE;
+    double t0, t1;
+    int rc = lanczos_bounds(L, U->f64, m0, iters, fld(start), &t0, &t1, (char *)ws, ws_bytes, S(stream));
+    if (rc) return rc;
+    *lambda_min = lo_margin * std::sqrt(std::max(t0, 0.0));
+    *lambda_max = hi_margin * std::sqrt(t1);
+    return OVL_OK;
+}
+
+// Shared body of multishift_cg / sign_q / overlap.  Workspace layout:
+// [one nrhs FP64 field set "y"][solver workspace].  If weights != NULL,
+// y_r = sum_l w_l x_{l,r} is left in the front field set; the FP64 solver also
+// hands back its x_l through *scr.
+static int solve_y(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts,
+                   const double *weights, Fld b, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws,
+                   size_t ws_bytes, hipStream_t st, Fld *y_out, MsScratch *scr)
+{
+    const int R = b.nrhs;
+    size_t yb = (field_bytes(P_F64, L.V) * R + 255) & ~(size_t)255;
+    Fld y{ws, nullptr, P_F64, R};
+    *y_out = y;
+    if (prm->mode == OVL_SOLVE_MIXED) {
+        if (!U->f32 || !U->f16 || !U->f64 || !weights) return OVL_ERR_INVALID;
+        return mscg_mixed(L, U, m0, nshift, shifts, weights, b, y, prm, stats, ws + yb, ws_bytes - yb, st);
+    }
+    int rc = mscg_f64(L, U->f64, m0, nshift, shifts, b, prm, stats, ws + yb, ws_bytes - yb, st, scr);
+    if (rc < 0) return rc;
+    if (prm->verify && stats) {
+        for (int j = 0; j < nshift; j++) {
+            double res[NR];
+            int rc2 = true_residuals_f64(L, U->f64, m0, shifts[j], b, sub(scr->x, L.V, j * R, R), scr->s1, scr->s2,
+                                         scr->partials, scr->red, res, st);
+            if (rc2) return rc2;
+            for (int q = 0; q < R; q++) stats->true_residual[q][j] = res[q];
+            stats->stencil_applies += 2;
+        }
+    }
+    if (weights) OVL_HIP(launch_combine(L, weights, nshift, scr->x, y, st));
+    return rc;
+}
+
+int ovl_multishift_cg(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t nshift, const double *shifts,
+                      const double *weights, const ovl_spinor *b, ovl_spinor *x, const ovl_solver_params *prm,
+                      ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    double t0 = now();
+    clear_stats(stats);
+    if (!lat_ok(lat) || !spinor_ok(b) || !params_ok(prm) || !shifts || !U || !ws) return OVL_ERR_INVALID;
+    // x holds nshift*nrhs fields when weights == NULL, so its count may exceed OVL_MAX_RHS
+    if (!x || !x->d || x->prec != OVL_F64 || x->nrhs < 1) return OVL_ERR_INVALID;
+    if (nshift < 1 || nshift > OVL_MAX_SHIFTS || b->prec != OVL_F64 || x->prec != OVL_F64 || b->d == x->d)
+        return OVL_ERR_INVALID;
+    if (x->nrhs != (weights ? b->nrhs : b->nrhs * nshift)) return OVL_ERR_INVALID;
+    if (!U->f64) return OVL_ERR_INVALID;
+    for (int j = 0; j < nshift; j++)
+        if (!(shifts[j] >= 0.0) || !std::isfinite(shifts[j])) return OVL_ERR_INVALID;
+    Lat L = make_lat(lat);
+    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_MSCG, OVL_F64, b->nrhs, nshift, prm)) return OVL_ERR_WORKSPACE;
+    if (!weights && prm->mode == OVL_SOLVE_MIXED) return OVL_ERR_INVALID;   // the mixed solver returns y only
+    Fld y{};
+    MsScratch scr{};
+    int rc = solve_y(L, U, m0, nshift, shifts, weights, fld(b), prm, stats, (char *)ws, ws_bytes, S(stream), &y, &scr);
+    if (rc >= 0) {
+        size_t F = field_bytes(P_F64, L.V);
+        if (weights)
+            OVL_HIP(hipMemcpyAsync(x->d, y.d, F * b->nrhs, hipMemcpyDeviceToDevice, S(stream)));
+        else
+            OVL_HIP(hipMemcpyAsync(x->d, scr.x.d, F * b->nrhs * nshift, hipMemcpyDeviceToDevice, S(stream)));
+    }
+    if (rc >= 0) OVL_HIP(hipStreamSynchronize(S(stream)));
+    if (stats) stats->seconds = now() - t0;
+    return rc;
+}
+
+static int sign_or_overlap(const ovl_lattice *lat, const ovl_gauge *U, double m0, double rho, const ovl_zolo *z,
+                           const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
+                           ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream, bool overlap)
+{
+    double t0 = now();
+    clear_stats(stats);
+    if (!lat_ok(lat) || !spinor_ok(b) || !spinor_ok(out) || !params_ok(prm) || !zolo_ok(z) || !U || !U->f64 || !ws)
+        return OVL_ERR_INVALID;
+    if (b->prec != OVL_F64 || out->prec != OVL_F64 || b->nrhs != out->nrhs || b->d == out->d) return OVL_ERR_INVALID;
+    if (!std::isfinite(m0)) return OVL_ERR_INVALID;
+    Lat L = make_lat(lat);
+    const int R = b->nrhs;
+    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_MSCG, OVL_F64, R, z->npoles, prm)) return OVL_ERR_WORKSPACE;
+    Fld y{};
+    MsScratch scr{};
+    int rc = solve_y(L, U, m0, z->npoles, z->shifts, z->weights, fld(b), prm, stats, (char *)ws, ws_bytes, S(stream),
+                     &y, &scr);
+    if (rc < 0) return rc;
+    WArgs a{};
+    a.in = y.d;
+    a.out = out->d;
+    a.U = U->f64;
+    a.diag = m0 + 4.0;
+    a.nrhs = R;
+    if (overlap) {
+        // out = rho (b + D_W(-rho) y)
+        OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, false, a, S(stream)));
+        OVL_HIP(launch_axpby(L, rho, fld(b), rho, fld(out), S(stream)));
+    } else {
+        OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, true, a, S(stream)));
+    }
+    if (stats) {
+        stats->stencil_applies += 1;
+        stats->algorithmic_bytes += (double)L.V * R * 960.0 + (overlap ? (double)field_bytes(P_F64, L.V) * 3 * R : 0.0);
+    }
+    OVL_HIP(hipStreamSynchronize(S(stream)));
+    if (stats) stats->seconds = now() - t0;
+    return rc;
+}
+
+int ovl_sign_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_zolo *z, const ovl_spinor *b,
+                     ovl_spinor *out, const ovl_solver_params *prm, ovl_solver_stats *stats, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    return sign_or_overlap(lat, U, m0, 0.0, z, b, out, prm, stats, ws, ws_bytes, stream, false);
+}
+
+int ovl_overlap_apply(const ovl_lattice *lat, const ovl_gauge *U, double rho, const ovl_zolo *z, const ovl_spinor *b,
+                      ovl_spinor *out, const ovl_solver_params *prm, ovl_solver_stats *stats, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    if (!(rho > 0.0) || !std::isfinite(rho)) return OVL_ERR_INVALID;
+    return sign_or_overlap(lat, U, -rho, rho, z, b, out, prm, stats, ws, ws_bytes, stream, true);
+}
+
+const char *ovl_status_string(int s)
+{
+    switch (s) {
+    case OVL_OK: return "ok";
+    case OVL_NOT_CONVERGED: return "not converged";
+    case OVL_ERR_INVALID: return "invalid argument";
+    case OVL_ERR_WORKSPACE: return "workspace too small";
+    case OVL_ERR_HIP: return "HIP error";
+    case OVL_ERR_NONFINITE: return "non-finite value";
+    default: return "unknown status";
+    }
+}
+
+int ovl_last_hip_error(void) { return last_hip_error(); }
+
+const char *ovl_version(void) { return "ovl 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,284 @@
+// Device-side building blocks for the gfx950 overlap library: complex
+// arithmetic, the even-odd field layouts of ovl.h, field loads/stores per
+// storage precision, the XCD-aware block mapping and deterministic block
+// reductions.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ovl {
+
+constexpr int kBlock = 256;     // threads per block of every site-parallel kernel
+constexpr int kNumXcd = 8;      // MI355X: 8 accelerator complex dies, each with its own L2
+
+template <typename T>
+struct cplx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mk(T x, T y) { return {x, y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) { return {s * a.x, s * a.y}; }
+// i*a and -i*a
+template <typename T>
+__device__ __forceinline__ cplx<T> ti(cplx<T> a) { return {-a.y, a.x}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> tmi(cplx<T> a) { return {a.y, -a.x}; }
+// a*b
+template <typename T>
+__device__ __forceinline__ cplx<T> cm(cplx<T> a, cplx<T> b)
+{
+    return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+// conj(a)*b
+template <typename T>
+__device__ __forceinline__ cplx<T> cmc(cplx<T> a, cplx<T> b)
+{
+    return {fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -a.y * b.x)};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cplx<T> a) { return fma(a.x, a.x, a.y * a.y); }
+
+// ---------------------------------------------------------------- geometry
+// Site (parity p, checkerboard index i): lexicographic index 2*i or 2*i+1,
+// whichever has parity p; lex = ((x0*L1 + x1)*L2 + x2)*L3 + x3 with L3 even.
+struct Geom {
+    int L[4];
+    int bc[4];
+    int Vh;        // V/2 sites per parity
+};
+
+__device__ __forceinline__ void site_coords(const Geom &g, int p, int i, int x[4])
+{
+    int lb = 2 * i;
+    int x3e = lb % g.L[3];
+    int t = lb / g.L[3];
+    x[2] = t % g.L[2];
+    t /= g.L[2];
+    x[1] = t % g.L[1];
+    x[0] = t / g.L[1];
+    x[3] = x3e + ((p + x[0] + x[1] + x[2]) & 1);
+}
+
+__device__ __forceinline__ int cb_index(const Geom &g, const int x[4])
+{
+    return ((((x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3]) + x[3]) >> 1;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Give every XCD one contiguous range of logical blocks so that the
+// neighbours one block row away are in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    int q = nb / kNumXcd, r = nb % kNumXcd;
+    int xcd = b % kNumXcd, k = b / kNumXcd;
+    return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// ---------------------------------------------------------------- fields
+enum { P_F64 = 0, P_F32 = 1, P_F16S = 2 };
+
+template <int PREC>
+struct Real {
+    using T = float;
+};
+template <>
+struct Real<P_F64> {
+    using T = double;
+};
+
+// A spinor field of one RHS: pointer to its parity-0 component-0 element.
+template <int PREC>
+struct SpinorRef;
+
+template <>
+struct SpinorRef<P_F64> {
+    double2 *d;
+    int Vh;
+    __device__ __forceinline__ void load(int p, int i, cplx<double> s[4][3]) const
+    {
+        const double2 *b = d + (size_t)p * 12 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 v = b[(size_t)k * Vh];
+            s[k / 3][k % 3] = {v.x, v.y};
+        }
+    }
+    __device__ __forceinline__ void store(int p, int i, const cplx<double> s[4][3]) const
+    {
+        double2 *b = d + (size_t)p * 12 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 12; k++) b[(size_t)k * Vh] = make_double2(s[k / 3][k % 3].x, s[k / 3][k % 3].y);
+    }
+};
+
+template <>
+struct SpinorRef<P_F32> {
+    float4 *d;
+    int Vh;
+    __device__ __forceinline__ void load(int p, int i, cplx<float> s[4][3]) const
+    {
+        const float4 *b = d + (size_t)p * 6 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            float4 v = b[(size_t)k * Vh];
+            s[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+            s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+        }
+    }
+    __device__ __forceinline__ void store(int p, int i, const cplx<float> s[4][3]) const
+    {
+        float4 *b = d + (size_t)p * 6 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            cplx<float> a = s[(2 * k) / 3][(2 * k) % 3], c = s[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            b[(size_t)k * Vh] = make_float4(a.x, a.y, c.x, c.y);
+        }
+    }
+};
+
+__device__ __forceinline__ float h2f(unsigned short h) { return __half2float(__ushort_as_half(h)); }
+__device__ __forceinline__ unsigned short f2h(float f) { return __half_as_ushort(__float2half_rn(f)); }
+
+template <>
+struct SpinorRef<P_F16S> {
+    uint4 *d;     // 8 halves = 4 complex components per element
+    float *sc;    // per-site scale
+    int Vh;
+    __device__ __forceinline__ void load(int p, int i, cplx<float> s[4][3]) const
+    {
+        const uint4 *b = d + (size_t)p * 3 * Vh + i;
+        float scale = sc[(size_t)p * Vh + i];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint4 v = b[(size_t)k * Vh];
+            unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int c = 4 * k + q;
+                s[c / 3][c % 3] = {scale * h2f((unsigned short)(w[q] & 0xffff)),
+                                   scale * h2f((unsigned short)(w[q] >> 16))};
+            }
+        }
+    }
+    __device__ __forceinline__ void store(int p, int i, const cplx<float> s[4][3]) const
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) m = fmaxf(m, fmaxf(fabsf(s[a][c].x), fabsf(s[a][c].y)));
+        float scale = m > 0.f ? m : 1.f;
+        float inv = 1.f / scale;
+        uint4 *b = d + (size_t)p * 3 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            unsigned w[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int c = 4 * k + q;
+                w[q] = (unsigned)f2h(s[c / 3][c % 3].x * inv) | ((unsigned)f2h(s[c / 3][c % 3].y * inv) << 16);
+            }
+            b[(size_t)k * Vh] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        sc[(size_t)p * Vh + i] = scale;
+    }
+};
+
+// Elements (in the pointer's own unit) of one RHS in each layout.
+__host__ __device__ inline size_t spinor_elems(int prec, int Vh)
+{
+    return prec == P_F64 ? (size_t)24 * Vh : prec == P_F32 ? (size_t)12 * Vh : (size_t)6 * Vh;
+}
+
+// Gauge links.  F64 keeps 18 reals; F32/F16 keep rows 0 and 1 and rebuild
+// row 2 = conj(row0 x row1), which holds for every SU(3) matrix.
+template <int PREC>
+struct GaugeRef;
+
+template <typename T>
+__device__ __forceinline__ void rebuild_row2(cplx<T> u[3][3])
+{
+    cplx<T> a = cm(u[0][1], u[1][2]) - cm(u[0][2], u[1][1]);
+    cplx<T> b = cm(u[0][2], u[1][0]) - cm(u[0][0], u[1][2]);
+    cplx<T> c = cm(u[0][0], u[1][1]) - cm(u[0][1], u[1][0]);
+    u[2][0] = {a.x, -a.y};
+    u[2][1] = {b.x, -b.y};
+    u[2][2] = {c.x, -c.y};
+}
+
+template <>
+struct GaugeRef<P_F64> {
+    const double2 *d;
+    int Vh;
+    __device__ __forceinline__ void load(int p, int mu, int i, cplx<double> u[3][3]) const
+    {
+        const double2 *b = d + (size_t)(p * 4 + mu) * 9 * Vh + i;
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            double2 v = b[(size_t)e * Vh];
+            u[e / 3][e % 3] = {v.x, v.y};
+        }
+    }
+};
+
+template <>
+struct GaugeRef<P_F32> {
+    const float4 *d;
+    int Vh;
+    __device__ __forceinline__ void load(int p, int mu, int i, cplx<float> u[3][3]) const
+    {
+        const float4 *b = d + (size_t)(p * 4 + mu) * 3 * Vh + i;
+        float4 v0 = b[0], v1 = b[(size_t)Vh], v2 = b[(size_t)2 * Vh];
+        u[0][0] = {v0.x, v0.y};
+        u[0][1] = {v0.z, v0.w};
+        u[0][2] = {v1.x, v1.y};
+        u[1][0] = {v1.z, v1.w};
+        u[1][1] = {v2.x, v2.y};
+        u[1][2] = {v2.z, v2.w};
+        rebuild_row2(u);
+    }
+};
+
+template <>
+struct GaugeRef<P_F16S> {
+    const uint2 *d;   // 4 halves = 2 complex entries per element
+    int Vh;
+    __device__ __forceinline__ void load(int p, int mu, int i, cplx<float> u[3][3]) const
+    {
+        const uint2 *b = d + (size_t)(p * 4 + mu) * 3 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint2 v = b[(size_t)k * Vh];
+            int e0 = 2 * k, e1 = 2 * k + 1;
+            u[e0 / 3][e0 % 3] = {h2f((unsigned short)(v.x & 0xffff)), h2f((unsigned short)(v.x >> 16))};
+            u[e1 / 3][e1 % 3] = {h2f((unsigned short)(v.y & 0xffff)), h2f((unsigned short)(v.y >> 16))};
+        }
+        rebuild_row2(u);
+    }
+};
+
+// ---------------------------------------------------------------- reductions
+// Sum over a 256-thread block, result valid in thread 0.  Fixed shuffle/LDS
+// order, so the result is bitwise reproducible for a given launch shape.
+__device__ __forceinline__ double block_sum(double v, double *lds /* >= 4 */)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) t = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    __syncthreads();
+    return t;
+}
+
+}  // namespace ovl

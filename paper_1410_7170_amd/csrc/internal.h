@@ -1,0 +1,73 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/ovl.h"
+#include "device.h"
+#include "wilson.h"
+
+namespace ovl {
+
+struct Lat {
+    Geom g;
+    int64_t V;
+    int Vh;
+    int nb;        // blocks per parity of a site-parallel launch
+};
+
+Lat make_lat(const ovl_lattice *lat);
+
+// record a failed HIP call; returns OVL_ERR_HIP
+int hip_fail(hipError_t e);
+#define OVL_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return ::ovl::hip_fail(e_); \
+    } while (0)
+
+// bytes of one packed field (one RHS) of precision prec, excluding scales
+inline size_t field_bytes(int prec, int64_t V)
+{
+    return prec == P_F64 ? (size_t)V * 192 : prec == P_F32 ? (size_t)V * 96 : (size_t)V * 48;
+}
+inline size_t scale_bytes(int64_t V) { return (size_t)V * 4; }
+
+// A packed field set of nrhs fields (device pointers).
+struct Fld {
+    void *d;
+    float *sc;
+    int prec;
+    int nrhs;
+};
+inline Fld fld(const ovl_spinor *s) { return {s->d, s->scale, s->prec, s->nrhs}; }
+// field k of a field set with `per` fields per group, e.g. shift j, rhs r
+inline Fld sub(const Fld &f, int64_t V, int first, int count)
+{
+    Fld o = f;
+    o.d = (char *)f.d + field_bytes(f.prec, V) * first;
+    o.sc = f.sc ? f.sc + (size_t)V * first : nullptr;
+    o.nrhs = count;
+    return o;
+}
+
+// ---- launchers (return hipError_t of the launch)
+hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hipStream_t st);
+hipError_t launch_pack_spinor(const Lat &L, const void *canon, Fld out, hipStream_t st);
+hipError_t launch_unpack_spinor(const Lat &L, Fld in, void *canon, hipStream_t st);
+hipError_t launch_pack_gauge(const Lat &L, const void *canon, int prec, void *out, hipStream_t st);
+// per-block partial sums of |f_r|^2 (or Re/Im <a_r, b_r> when b != null)
+hipError_t launch_norm2(const Lat &L, Fld f, double *partials, hipStream_t st);
+hipError_t launch_diff_norm2(const Lat &L, Fld a, Fld b, double *partials, hipStream_t st);
+hipError_t launch_dot(const Lat &L, Fld a, Fld b, double *partials, hipStream_t st);
+// out[q*nrhs + r] = sum of partials[(q*nrhs + r)*nblk ...]
+hipError_t launch_reduce(const double *partials, int nq, int nrhs, int nblk, double *out, hipStream_t st);
+// y = a*x + b*y (FP64 or FP32 fields; per-RHS coefficients on device or host)
+hipError_t launch_convert(const Lat &L, Fld src, Fld dst, hipStream_t st);
+hipError_t launch_axpby(const Lat &L, double a, Fld x, double b, Fld y, hipStream_t st);
+hipError_t launch_zero(const Lat &L, Fld f, hipStream_t st);
+
+int elems_per_field(int prec, int Vh);   // flat vector elements of one RHS
+int site_blocks(const Lat &L);           // blocks of a flat elementwise launch over one field
+
+}  // namespace ovl

@@ -1,0 +1,233 @@
+// Wilson-Dirac hopping stencil on the even-odd layout (gfx950).
+//
+// Implements eq. (Wilson-Dirac) of Brannick et al. (arXiv:1410.7170), a = 1:
+//   (D psi)(x) = (m0+4) psi(x) - 1/2 sum_mu (I - gamma_mu) U_mu(x) psi(x+mu)
+//                              - 1/2 sum_mu (I + gamma_mu) U_mu(x-mu)^H psi(x-mu)
+// in the chiral basis gamma_5 = diag(-1,-1,1,1).  (I -+ gamma_mu) has rank 2,
+// so each hop projects the neighbour to a two-spin "half spinor" h, applies
+// the 3x3 link to h only and rebuilds the lower two spins from the product.
+#pragma once
+
+#include "device.h"
+
+namespace ovl {
+
+enum WMode {
+    W_PLAIN = 0,     // out = D in            (or Gamma_5 D in)
+    W_NORM = 1,      // out = Gamma_5 D in;  partials |out|^2, |in(x)|^2
+    W_SHIFT = 2,     // out = Gamma_5 D in + shift * p
+    W_RUPDATE = 3,   // r  -= alpha_r (Gamma_5 D in + shift * p); partial |r|^2
+};
+
+struct WArgs {
+    Geom g;
+    const void *in;
+    const float *in_sc;
+    void *out;
+    float *out_sc;
+    const void *U;
+    const void *p;          // W_SHIFT / W_RUPDATE second field
+    const float *p_sc;
+    double diag;            // m0 + 4
+    double shift;
+    const double *alpha;    // W_RUPDATE: alpha per RHS (device)
+    double *partials;       // [quantity][nrhs][nblk]
+    const int *skip;        // per-RHS flag: block exits if skip[r] != 0 (may be null)
+    int nblk;
+    int nrhs;
+};
+
+template <int PREC>
+__device__ __forceinline__ SpinorRef<PREC> spinor_ref(const void *base, const float *sc, int Vh, int r);
+
+template <>
+__device__ __forceinline__ SpinorRef<P_F64> spinor_ref<P_F64>(const void *base, const float *, int Vh, int r)
+{
+    return {(double2 *)base + (size_t)r * 24 * Vh, Vh};
+}
+
+template <>
+__device__ __forceinline__ SpinorRef<P_F32> spinor_ref<P_F32>(const void *base, const float *, int Vh, int r)
+{
+    return {(float4 *)base + (size_t)r * 12 * Vh, Vh};
+}
+
+template <>
+__device__ __forceinline__ SpinorRef<P_F16S> spinor_ref<P_F16S>(const void *base, const float *sc, int Vh, int r)
+{
+    return {(uint4 *)base + (size_t)r * 6 * Vh, (float *)sc + (size_t)r * 2 * Vh, Vh};
+}
+
+// Accumulate the hop in direction mu (FWD: from x+mu with U_mu(x);
+// !FWD: from x-mu with U_mu(x-mu)^H) into acc, with boundary phase ph.
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void hop(cplx<T> acc[4][3], const cplx<T> s[4][3], const cplx<T> u[3][3], T ph)
+{
+    cplx<T> h[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (MU == 0) {
+            h[0][c] = FWD ? s[0][c] - s[2][c] : s[0][c] + s[2][c];
+            h[1][c] = FWD ? s[1][c] - s[3][c] : s[1][c] + s[3][c];
+        } else if (MU == 1) {
+            h[0][c] = FWD ? s[0][c] + ti(s[3][c]) : s[0][c] + tmi(s[3][c]);
+            h[1][c] = FWD ? s[1][c] + ti(s[2][c]) : s[1][c] + tmi(s[2][c]);
+        } else if (MU == 2) {
+            h[0][c] = FWD ? s[0][c] + s[3][c] : s[0][c] - s[3][c];
+            h[1][c] = FWD ? s[1][c] - s[2][c] : s[1][c] + s[2][c];
+        } else {
+            h[0][c] = FWD ? s[0][c] + ti(s[2][c]) : s[0][c] + tmi(s[2][c]);
+            h[1][c] = FWD ? s[1][c] + tmi(s[3][c]) : s[1][c] + ti(s[3][c]);
+        }
+    }
+    cplx<T> w[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            cplx<T> t;
+            if (FWD) {
+                t = cm(u[c][0], h[a][0]);
+                t = t + cm(u[c][1], h[a][1]);
+                t = t + cm(u[c][2], h[a][2]);
+            } else {
+                t = cmc(u[0][c], h[a][0]);
+                t = t + cmc(u[1][c], h[a][1]);
+                t = t + cmc(u[2][c], h[a][2]);
+            }
+            w[a][c] = ph * t;
+        }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc[0][c] = acc[0][c] + w[0][c];
+        acc[1][c] = acc[1][c] + w[1][c];
+        if (MU == 0) {
+            acc[2][c] = FWD ? acc[2][c] - w[0][c] : acc[2][c] + w[0][c];
+            acc[3][c] = FWD ? acc[3][c] - w[1][c] : acc[3][c] + w[1][c];
+        } else if (MU == 1) {
+            acc[2][c] = acc[2][c] + (FWD ? tmi(w[1][c]) : ti(w[1][c]));
+            acc[3][c] = acc[3][c] + (FWD ? tmi(w[0][c]) : ti(w[0][c]));
+        } else if (MU == 2) {
+            acc[2][c] = FWD ? acc[2][c] - w[1][c] : acc[2][c] + w[1][c];
+            acc[3][c] = FWD ? acc[3][c] + w[0][c] : acc[3][c] - w[0][c];
+        } else {
+            acc[2][c] = acc[2][c] + (FWD ? tmi(w[0][c]) : ti(w[0][c]));
+            acc[3][c] = acc[3][c] + (FWD ? ti(w[1][c]) : tmi(w[1][c]));
+        }
+    }
+}
+
+template <int PREC, int MU>
+__device__ __forceinline__ void hops_mu(const Geom &g, const SpinorRef<PREC> &in, const GaugeRef<PREC> &U,
+                                        int p, int i, const int x[4], cplx<typename Real<PREC>::T> acc[4][3])
+{
+    using T = typename Real<PREC>::T;
+    cplx<T> s[4][3], u[3][3];
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    // forward neighbour x+mu, link U_mu(x) stored at (p, i)
+    T ph = (T)1;
+    y[MU] = x[MU] + 1;
+    if (y[MU] == g.L[MU]) { y[MU] = 0; ph = (T)g.bc[MU]; }
+    int j = cb_index(g, y);
+    in.load(1 - p, j, s);
+    U.load(p, MU, i, u);
+    hop<T, MU, true>(acc, s, u, ph);
+    // backward neighbour x-mu, link U_mu(x-mu) stored at (1-p, j)
+    ph = (T)1;
+    y[MU] = x[MU] - 1;
+    if (y[MU] < 0) { y[MU] = g.L[MU] - 1; ph = (T)g.bc[MU]; }
+    j = cb_index(g, y);
+    in.load(1 - p, j, s);
+    U.load(1 - p, MU, j, u);
+    hop<T, MU, false>(acc, s, u, ph);
+}
+
+template <int PREC, int MODE, bool G5>
+__global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
+{
+    using T = typename Real<PREC>::T;
+    __shared__ double lds[8];
+    const int r = blockIdx.y;
+    if (a.skip && a.skip[r]) return;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int p = lb & 1;
+    const int i = (lb >> 1) * kBlock + threadIdx.x;
+    const Geom &g = a.g;
+    const bool valid = i < g.Vh;
+    const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.Vh, r);
+    const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.Vh};
+    double q0 = 0.0, q1 = 0.0;
+    if (valid) {
+        int x[4];
+        site_coords(g, p, i, x);
+        cplx<T> acc[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[s][c] = {(T)0, (T)0};
+        hops_mu<PREC, 0>(g, in, U, p, i, x, acc);
+        hops_mu<PREC, 1>(g, in, U, p, i, x, acc);
+        hops_mu<PREC, 2>(g, in, U, p, i, x, acc);
+        hops_mu<PREC, 3>(g, in, U, p, i, x, acc);
+        cplx<T> d[4][3];
+        in.load(p, i, d);
+        const T diag = (T)a.diag;
+        cplx<T> o[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                cplx<T> v = {fma(diag, d[s][c].x, (T)-0.5 * acc[s][c].x), fma(diag, d[s][c].y, (T)-0.5 * acc[s][c].y)};
+                if (G5 && s < 2) v = {-v.x, -v.y};
+                o[s][c] = v;
+            }
+        if (MODE == W_NORM) {
+            T n0 = 0, n1 = 0;
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) { n0 += norm2(o[s][c]); n1 += norm2(d[s][c]); }
+            q0 = (double)n0;
+            q1 = (double)n1;
+        }
+        if (MODE == W_SHIFT || MODE == W_RUPDATE) {
+            const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.Vh, r);
+            cplx<T> pv[4][3];
+            pf.load(p, i, pv);
+            const T sh = (T)a.shift;
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) o[s][c] = {fma(sh, pv[s][c].x, o[s][c].x), fma(sh, pv[s][c].y, o[s][c].y)};
+        }
+        const SpinorRef<PREC> out = spinor_ref<PREC>(a.out, a.out_sc, g.Vh, r);
+        if (MODE == W_RUPDATE) {
+            cplx<T> rv[4][3];
+            out.load(p, i, rv);
+            const T al = (T)a.alpha[r];
+            T n0 = 0;
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    rv[s][c] = {fma(-al, o[s][c].x, rv[s][c].x), fma(-al, o[s][c].y, rv[s][c].y)};
+                    n0 += norm2(rv[s][c]);
+                }
+            out.store(p, i, rv);
+            q0 = (double)n0;
+        } else {
+            out.store(p, i, o);
+        }
+    }
+    if (MODE == W_NORM || MODE == W_RUPDATE) {
+        const int nb = gridDim.x;
+        double t0 = block_sum(q0, lds);
+        if (threadIdx.x == 0) a.partials[(size_t)r * nb + lb] = t0;
+        if (MODE == W_NORM) {
+            double t1 = block_sum(q1, lds + 4);
+            if (threadIdx.x == 0) a.partials[(size_t)(a.nrhs + r) * nb + lb] = t1;
+        }
+    }
+}
+
+}  // namespace ovl

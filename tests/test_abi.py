@@ -1,0 +1,148 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/ovl.h declares, validates arguments before touching the
+device, and its host-only Zolotarev routine agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ovl():
+    import paper_1410_7170_amd as m
+    return m
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "ovl.h")).read()
+    return sorted(set(re.findall(r"OVL_API[^;(]*?\b(ovl_\w+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = header_symbols()
+    for need in ("ovl_wilson_apply", "ovl_q_apply", "ovl_q2_apply", "ovl_multishift_cg", "ovl_sign_q_apply",
+                 "ovl_overlap_apply", "ovl_zolotarev", "ovl_spectral_bounds", "ovl_pack_spinor",
+                 "ovl_unpack_spinor", "ovl_pack_gauge", "ovl_workspace_bytes", "ovl_lattice_init"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(ovl):
+    lib = ctypes.CDLL(ovl.LIB_PATH)
+    for name in header_symbols():
+        assert hasattr(lib, name), name
+    assert set(header_symbols()) == set(ovl.EXPORTED)
+
+
+def test_lattice_validation(ovl):
+    lat = ovl.Lattice((4, 4, 4, 8))
+    assert lat.V == 512
+    for dims, bc in [((3, 4, 4, 4), (-1, 1, 1, 1)), ((4, 4, 4, 0), (-1, 1, 1, 1)),
+                     ((4, 4, 4, 4), (2, 1, 1, 1)), ((2048, 1024, 1024, 2), (1, 1, 1, 1))]:
+        with pytest.raises(ovl.OvlError) as e:
+            ovl.Lattice(dims, bc)
+        assert e.value.status == ovl.ERR_INVALID
+
+
+def test_sizes(ovl):
+    lat = ovl.Lattice((4, 4, 4, 4))
+    assert lat.spinor_bytes(ovl.F64) == 256 * 192
+    assert lat.spinor_bytes(ovl.F32) == 256 * 96
+    assert lat.spinor_bytes(ovl.F16S) == 256 * 48
+    assert lat.scale_bytes() == 256 * 4
+    assert lat.gauge_bytes(ovl.F64) == 1024 * 144
+    assert lat.gauge_bytes(ovl.F32) == 1024 * 48
+    assert lat.gauge_bytes(ovl.F16S) == 1024 * 24
+    p = ovl.default_params()
+    assert p.tol == 1e-10 and p.mode == ovl.SOLVE_F64
+    assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, p) > 40 * 256 * 192
+    assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 0, p) == 0
+    assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 17, 4, p) == 0
+
+
+def test_null_and_alias_rejected_before_launch(ovl):
+    lat = ovl.Lattice((4, 4, 4, 4))
+    lib = ovl._lib
+    s = ovl.ovl_spinor(None, None, ovl.F64, 1)
+    g = ovl.ovl_gauge(None, None, None)
+    assert lib.ovl_wilson_apply(lat.ref, ctypes.byref(g), -1.6, ctypes.byref(s), ctypes.byref(s), None) == ovl.ERR_INVALID
+    fake = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 1)
+    gf = ovl.ovl_gauge(ctypes.c_void_p(8192), None, None)
+    # in == out
+    assert lib.ovl_wilson_apply(lat.ref, ctypes.byref(gf), -1.6, ctypes.byref(fake), ctypes.byref(fake), None) == ovl.ERR_INVALID
+    # F16S needs scales; nrhs range; precision mismatch
+    h = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F16S, 1)
+    o = ovl.ovl_spinor(ctypes.c_void_p(1 << 20), None, ovl.F64, 1)
+    assert lib.ovl_wilson_apply(lat.ref, ctypes.byref(gf), -1.6, ctypes.byref(h), ctypes.byref(o), None) == ovl.ERR_INVALID
+    big = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 17)
+    assert lib.ovl_q_apply(lat.ref, ctypes.byref(gf), -1.6, ctypes.byref(big), ctypes.byref(o), None) == ovl.ERR_INVALID
+    o32 = ovl.ovl_spinor(ctypes.c_void_p(1 << 20), None, ovl.F32, 1)
+    assert lib.ovl_q_apply(lat.ref, ctypes.byref(gf), -1.6, ctypes.byref(fake), ctypes.byref(o32), None) == ovl.ERR_INVALID
+    # missing gauge precision
+    assert lib.ovl_q_apply(lat.ref, ctypes.byref(gf), -1.6, ctypes.byref(o32),
+                           ctypes.byref(ovl.ovl_spinor(ctypes.c_void_p(1 << 22), None, ovl.F32, 1)), None) == ovl.ERR_INVALID
+    # workspace too small for q2
+    assert lib.ovl_q2_apply(lat.ref, ctypes.byref(gf), -1.6, 0.1, ctypes.byref(fake), ctypes.byref(o),
+                            ctypes.c_void_p(1 << 24), 16, None) == ovl.ERR_WORKSPACE
+
+
+def test_solver_params_rejected(ovl):
+    lat = ovl.Lattice((4, 4, 4, 4))
+    lib = ovl._lib
+    b = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 1)
+    o = ovl.ovl_spinor(ctypes.c_void_p(1 << 20), None, ovl.F64, 1)
+    gf = ovl.ovl_gauge(ctypes.c_void_p(8192), None, None)
+    s = (ctypes.c_double * 2)(0.1, 0.2)
+    w = (ctypes.c_double * 2)(1.0, 1.0)
+    z = ovl.ovl_zolo(2, s, w)
+    st = ovl.ovl_solver_stats()
+    for bad in [dict(tol=0.0), dict(tol=float("nan")), dict(maxiter=0), dict(mode=7), dict(reliable_delta=1.5)]:
+        p = ovl.default_params(**bad)
+        rc = lib.ovl_overlap_apply(lat.ref, ctypes.byref(gf), 1.6, ctypes.byref(z), ctypes.byref(b), ctypes.byref(o),
+                                   ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(1 << 26), 1 << 30, None)
+        assert rc == ovl.ERR_INVALID, bad
+    p = ovl.default_params()
+    rc = lib.ovl_overlap_apply(lat.ref, ctypes.byref(gf), -1.0, ctypes.byref(z), ctypes.byref(b), ctypes.byref(o),
+                               ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(1 << 26), 1 << 30, None)
+    assert rc == ovl.ERR_INVALID
+    nz = ovl.ovl_zolo(0, s, w)
+    rc = lib.ovl_overlap_apply(lat.ref, ctypes.byref(gf), 1.6, ctypes.byref(nz), ctypes.byref(b), ctypes.byref(o),
+                               ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(1 << 26), 1 << 30, None)
+    assert rc == ovl.ERR_INVALID
+    rc = lib.ovl_overlap_apply(lat.ref, ctypes.byref(gf), 1.6, ctypes.byref(z), ctypes.byref(b), ctypes.byref(o),
+                               ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(1 << 26), 64, None)
+    assert rc == ovl.ERR_WORKSPACE
+
+
+def test_status_strings(ovl):
+    for s in (0, 1, -1, -2, -3, -4):
+        assert ovl._lib.ovl_status_string(s).decode()
+    assert ovl.version().startswith("ovl")
+
+
+@pytest.mark.parametrize("k", [0.001, 0.01, 0.05, 0.075, 0.3, 0.9])
+@pytest.mark.parametrize("n", [1, 4, 12, 20, 24, 32])
+def test_zolotarev_library_matches_oracle(ovl, k, n):
+    """The library derives sn/cn from theta functions, the oracle from the
+    descending Landen scheme; both give the same Zolotarev coefficients."""
+    s, w, d = ovl.zolotarev(k, 1.0, n)
+    s2, w2, d2 = oracle.zolotarev(k, 1.0, n)
+    tol = 1e-13 if k >= 0.05 else 1e-11
+    assert np.max(np.abs(s - s2) / s2) < tol
+    assert np.max(np.abs(w - w2) / w2) < tol
+    # delta near 1e-12 is at the rounding level of evaluating R itself
+    assert abs(d - d2) < 5e-13 + 1e-6 * d2
+    # scaling to [lmin, lmax]
+    s3, w3, d3 = ovl.zolotarev(0.5 * k, 0.5, n)
+    assert np.allclose(s3, s * 0.25, rtol=1e-13) and np.allclose(w3, w * 0.5, rtol=1e-13)
+
+
+def test_zolotarev_rejects(ovl):
+    for args in [(0.0, 1.0, 4), (1.0, 0.5, 4), (0.1, 1.0, 0), (0.1, 1.0, 33), (0.1, float("inf"), 4)]:
+        with pytest.raises(ovl.OvlError):
+            ovl.zolotarev(*args)

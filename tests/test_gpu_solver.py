@@ -1,0 +1,217 @@
+"""GPU parity of the sign function and the overlap apply (FP64 path) against
+the oracle, through the C ABI: Lanczos bounds, multishift CG, sign_q_apply,
+overlap_apply, plus the solver's failure paths.
+
+Each side builds its own Zolotarev coefficients (the library from theta
+functions, the oracle from the Landen scheme) and its own Lanczos bounds; the
+FP64 path must agree with the oracle to 1e-12 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import dense
+
+pytestmark = pytest.mark.gpu
+
+RHO = 1.6
+M0 = -RHO
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ovl():
+    import paper_1410_7170_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def both_sides(ovl, dims, U, npoles=20, start_seed=99):
+    """Each side's own spectral interval and Zolotarev data."""
+    lat = ovl.Lattice(dims)
+    olat = oracle.Lattice(dims)
+    G = ovl.Gauge(lat, dev(U))
+    v0 = synth.gaussian_spinor(lat.V, start_seed)[0]
+    lo, hi = ovl.spectral_bounds(lat, G, M0, 300, ovl.Spinor.from_canonical(lat, dev(v0), 0))
+    s, w, d = ovl.zolotarev(lo, hi, npoles)
+    olo, ohi = oracle.spectral_interval(olat, U, M0, v0, 300)
+    os_, ow, od = oracle.zolotarev(olo, ohi, npoles)
+    return lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi)
+
+
+def test_spectral_bounds_bracket_exact_spectrum(ovl):
+    dims = (4, 4, 4, 4)
+    note("spectral bounds 4^4")
+    U = synth.config_gauge(0)
+    lat = ovl.Lattice(dims)
+    G = ovl.Gauge(lat, dev(U))
+    v0 = synth.gaussian_spinor(lat.V, 5)[0]
+    lo, hi = ovl.spectral_bounds(lat, G, M0, 300, ovl.Spinor.from_canonical(lat, dev(v0), 0), 1.0, 1.0)
+    _, w = dense.sign_q_exact(oracle.Lattice(dims), U, M0)
+    aw = np.abs(w)
+    assert abs(lo - aw.min()) < 1e-6 * aw.min() and abs(hi - aw.max()) < 1e-9 * aw.max()
+    lo2, hi2 = ovl.spectral_bounds(lat, G, M0, 300, ovl.Spinor.from_canonical(lat, dev(v0), 0))
+    assert lo2 < aw.min() and hi2 > aw.max()
+
+
+def test_multishift_cg_matches_oracle(ovl):
+    dims = (8, 4, 4, 6)
+    note("multishift cg vs oracle")
+    U = synth.gauge(dims, 0.3, 21, n_stout=1)
+    lat, olat, G, (s, w, d, lo, hi), _ = both_sides(ovl, dims, U)
+    b = synth.gaussian_spinor(lat.V, 22)[0]
+    x_ref, it_ref, _ = oracle.mscg(olat, U, M0, s, b, 1e-12, 3000)
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    X = ovl.Spinor(lat, 0, len(s))
+    st = ovl.multishift_cg(lat, G, M0, s, None, B, X, ovl.default_params(tol=1e-12, verify=1, check_every=7))
+    x = X.to_canonical().cpu().numpy()
+    for j in range(len(s)):
+        assert rel(x[j], x_ref[j]) < 1e-10, j
+        assert abs(st["shift_iters"][0][j] - it_ref[j]) <= 1
+        assert st["true_residual"][0][j] < 1e-11
+    assert st["iterations"][0] == max(st["shift_iters"][0])
+
+
+def test_sign_q_matches_exact_dense_sign(ovl):
+    """4^4 workload: Zolotarev + multishift CG on the GPU against W sign(Delta) W^H."""
+    dims = (4, 4, 4, 4)
+    note("sign(Q) vs dense 4^4")
+    U = synth.config_gauge(0)
+    lat = ovl.Lattice(dims)
+    G = ovl.Gauge(lat, dev(U))
+    S, w = dense.sign_q_exact(oracle.Lattice(dims), U, M0)
+    aw = np.abs(w)
+    s, wt, delta = ovl.zolotarev(0.99 * aw.min(), 1.01 * aw.max(), 20)
+    b = synth.config_sources(0)[0]
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0)
+    ovl.sign_q_apply(lat, G, M0, s, wt, B, O, ovl.default_params(tol=1e-13))
+    exact = (S @ b.reshape(-1)).reshape(b.shape)
+    assert rel(O.to_canonical().cpu().numpy()[0], exact) < 1e-12 + 2 * delta
+    # overlap against the dense overlap matrix
+    Dov = RHO * (np.eye(3072) + dense.gamma5_matrix(lat.V) @ S)
+    ovl.overlap_apply(lat, G, RHO, s, wt, B, O, ovl.default_params(tol=1e-13))
+    assert rel(O.to_canonical().cpu().numpy()[0], (Dov @ b.reshape(-1)).reshape(b.shape)) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 4), (8, 4, 4, 6), (8, 8, 8, 8)])
+def test_overlap_apply_matches_oracle(ovl, dims):
+    note(f"overlap fp64 vs oracle {dims}")
+    U = synth.gauge(dims, 0.3, 31, n_stout=2)
+    lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
+    assert abs(lo - olo) < 1e-8 * lo and abs(hi - ohi) < 1e-8 * hi
+    b = synth.gaussian_spinor(lat.V, 32)[0]
+    ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b, 1e-13, 5000)
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0)
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000))
+    assert rel(O.to_canonical().cpu().numpy()[0], ref) < 1e-12
+    assert st["iterations"][0] > 10
+
+
+def test_overlap_multi_rhs(ovl):
+    dims = (8, 4, 4, 4)
+    note("overlap multi-rhs")
+    U = synth.gauge(dims, 0.3, 41, n_stout=2)
+    lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
+    b = synth.gaussian_spinor(lat.V, 42, 3)
+    b[2] *= 1e-3   # a RHS with a different scale converges on its own schedule
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0, 3)
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000))
+    got = O.to_canonical().cpu().numpy()
+    for r in range(3):
+        ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b[r], 1e-13, 5000)
+        assert rel(got[r], ref) < 1e-12
+
+
+def test_point_sources_batch(ovl):
+    """12 spin-colour point sources in one batched solve (the multi-RHS workload shape)."""
+    dims = (8, 4, 4, 4)
+    note("point sources")
+    U = synth.gauge(dims, 0.3, 51, n_stout=2)
+    lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
+    site = synth.random_site(lat.V, 52)
+    b = synth.point_sources(lat.V, site)
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0, 12)
+    ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-12, maxiter=5000))
+    got = O.to_canonical().cpu().numpy()
+    for r in (0, 5, 11):
+        ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b[r], 1e-12, 5000)
+        assert rel(got[r], ref) < 1e-10
+
+
+def test_ginsparg_wilson_gpu(ovl):
+    """Gamma_5 D + D Gamma_5 = (1/rho) D Gamma_5 D for the GPU overlap (eq. (GW))."""
+    dims = (8, 4, 4, 4)
+    note("GW relation")
+    U = synth.gauge(dims, 0.3, 61, n_stout=2)
+    lat, olat, G, (s, w, d, lo, hi), _ = both_sides(ovl, dims, U)
+    b = synth.gaussian_spinor(lat.V, 62)[0]
+    g5 = oracle.gamma5
+    prm = ovl.default_params(tol=1e-13, maxiter=5000)
+
+    def D(v):
+        B = ovl.Spinor.from_canonical(lat, dev(v), 0)
+        O = ovl.Spinor(lat, 0)
+        ovl.overlap_apply(lat, G, RHO, s, w, B, O, prm)
+        return O.to_canonical().cpu().numpy()[0]
+
+    Db = D(b)
+    lhs = g5(Db) + D(g5(b))
+    rhs = D(g5(Db)) / RHO
+    assert np.linalg.norm(lhs - rhs) / np.linalg.norm(b) < 1e-11
+
+
+def test_not_converged_and_zero_rhs(ovl):
+    dims = (4, 4, 4, 4)
+    U = synth.config_gauge(0)
+    lat = ovl.Lattice(dims)
+    G = ovl.Gauge(lat, dev(U))
+    s, w, d = ovl.zolotarev(0.4, 6.0, 12)
+    b = synth.gaussian_spinor(lat.V, 71)[0]
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0)
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-12, maxiter=5),
+                           allow_not_converged=True)
+    assert st["iterations"][0] == 5
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-12, maxiter=5))
+    assert e.value.status == ovl.NOT_CONVERGED
+    Z = ovl.Spinor.from_canonical(lat, dev(np.zeros_like(b)), 0)
+    st = ovl.overlap_apply(lat, G, RHO, s, w, Z, O, ovl.default_params())
+    assert np.abs(O.to_canonical().cpu().numpy()).max() == 0.0
+    assert st["iterations"][0] == 0
+
+
+def test_nonfinite_input_reported(ovl):
+    dims = (4, 4, 4, 4)
+    U = synth.config_gauge(0)
+    lat = ovl.Lattice(dims)
+    G = ovl.Gauge(lat, dev(U))
+    s, w, d = ovl.zolotarev(0.4, 6.0, 8)
+    b = synth.gaussian_spinor(lat.V, 72)[0]
+    b[3, 1, 2] = np.nan
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0)
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params())
+    assert e.value.status == ovl.ERR_NONFINITE

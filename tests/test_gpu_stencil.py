@@ -1,0 +1,201 @@
+"""GPU parity of the Wilson stencil family (wilson_apply, q_apply, q2_apply,
+pack/unpack) against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 path 1e-12 relative; FP32 stencil (FP32 links and spinors)
+1e-6 relative; FP16 storage with per-site scales 5e-3 relative (11-bit
+significands of links and spinors, FP32 arithmetic).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RHO = 1.6
+M0 = -RHO
+TOL = {0: 1e-12, 1: 1e-6, 2: 5e-3}
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ovl():
+    import paper_1410_7170_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def setup(ovl, dims, eps0=0.5, seed=3, n_stout=0, bc=(-1, 1, 1, 1)):
+    lat = ovl.Lattice(dims, bc)
+    olat = oracle.Lattice(dims, bc)
+    U = synth.gauge(dims, eps0, seed, n_stout)
+    G = ovl.Gauge(lat, dev(U))
+    return lat, olat, U, G
+
+
+LATTICES = [(4, 4, 4, 4), (2, 2, 2, 2), (6, 4, 2, 4), (8, 4, 4, 6), (4, 6, 6, 8), (10, 8, 6, 4)]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_pack_roundtrip(ovl, prec):
+    dims = (6, 4, 2, 4)
+    note(f"pack roundtrip prec={prec} dims={dims}")
+    lat = ovl.Lattice(dims)
+    psi = synth.gaussian_spinor(lat.V, 5, 3)
+    s = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+    back = s.to_canonical().cpu().numpy()
+    if prec == 0:
+        assert np.array_equal(back, psi)
+    elif prec == 1:
+        assert np.abs(back - psi).max() <= 6e-8 * np.abs(psi).max()
+    else:
+        site_max = np.maximum(np.abs(psi.real), np.abs(psi.imag)).reshape(3, lat.V, 12).max(-1)
+        err = np.abs(back - psi).reshape(3, lat.V, 12).max(-1)
+        assert (err <= 2 ** -11 * site_max * 1.01).all()
+
+
+@pytest.mark.parametrize("dims", LATTICES)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_wilson_apply_matches_oracle(ovl, dims, prec):
+    note(f"wilson_apply prec={prec} dims={dims}")
+    lat, olat, U, G = setup(ovl, dims, seed=7)
+    psi = synth.gaussian_spinor(lat.V, 8, 2)
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+    out = ovl.Spinor(lat, prec, 2)
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    got = out.to_canonical().cpu().numpy()
+    for r in range(2):
+        ref = oracle.dw(olat, U, M0, psi[r])
+        assert rel(got[r], ref) < TOL[prec], (dims, prec, r, rel(got[r], ref))
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1), (-1, -1, 1, -1)])
+def test_boundary_phases(ovl, bc):
+    dims = (4, 4, 6, 4)
+    note(f"boundary phases bc={bc}")
+    lat, olat, U, G = setup(ovl, dims, seed=9, bc=bc)
+    psi = synth.gaussian_spinor(lat.V, 10)[0]
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), 0)
+    out = ovl.Spinor(lat, 0)
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    assert rel(out.to_canonical().cpu().numpy()[0], oracle.dw(olat, U, M0, psi)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_q_and_q2_match_oracle(ovl, prec):
+    dims = (8, 4, 4, 6)
+    note(f"q/q2 prec={prec}")
+    lat, olat, U, G = setup(ovl, dims, seed=11, n_stout=1)
+    psi = synth.gaussian_spinor(lat.V, 12)[0]
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+    out = ovl.Spinor(lat, prec)
+    ovl.q_apply(lat, G, M0, inp, out)
+    assert rel(out.to_canonical().cpu().numpy()[0], oracle.q(olat, U, M0, psi)) < TOL[prec]
+    ovl.q2_apply(lat, G, M0, 0.37, inp, out)
+    assert rel(out.to_canonical().cpu().numpy()[0], oracle.q2(olat, U, M0, psi, 0.37)) < TOL[prec] * 2
+
+
+def test_gamma5_hermiticity_gpu(ovl):
+    """<phi, Q psi> = <Q phi, psi> for the GPU operator (eq. (gamma_5_symmetry))."""
+    dims = (8, 6, 4, 4)
+    lat, olat, U, G = setup(ovl, dims, seed=13)
+    phi, psi = synth.gaussian_spinor(lat.V, 14, 2)
+    a = ovl.Spinor.from_canonical(lat, dev(np.stack([phi, psi])), 0)
+    out = ovl.Spinor(lat, 0, 2)
+    ovl.q_apply(lat, G, M0, a, out)
+    q = out.to_canonical().cpu().numpy()
+    x = np.vdot(phi, q[1])
+    y = np.vdot(q[0], psi)
+    assert abs(x - y) / abs(x) < 1e-14
+
+
+def test_free_field_plane_wave_gpu(ovl):
+    """Unit links: the GPU stencil multiplies a plane wave by
+    m0 + sum(1 - cos p) + i sum sin(p) gamma (closed form from eq. (Wilson-Dirac))."""
+    dims = (8, 4, 6, 4)
+    lat = ovl.Lattice(dims)
+    U = synth.unit_gauge(dims)
+    G = ovl.Gauge(lat, dev(U))
+    rng = np.random.default_rng(3)
+    chi = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    n = (3, 1, 2, 1)
+    p = np.array([(2 * n[0] + 1) * np.pi / dims[0]] + [2 * np.pi * n[k] / dims[k] for k in (1, 2, 3)])
+    x = np.stack(np.meshgrid(*[np.arange(l) for l in dims], indexing="ij"), -1).reshape(-1, 4)
+    psi = np.exp(1j * (x @ p))[:, None, None] * chi[None]
+    A = (M0 + np.sum(1 - np.cos(p))) * np.eye(4, dtype=complex)
+    for mu in range(4):
+        A = A + 1j * np.sin(p[mu]) * oracle.gamma(mu)
+    expect = np.einsum("ab,xbc->xac", A, psi)
+    for prec in (0, 1):
+        inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+        out = ovl.Spinor(lat, prec)
+        ovl.wilson_apply(lat, G, M0, inp, out)
+        assert rel(out.to_canonical().cpu().numpy()[0], expect) < TOL[prec]
+
+
+def test_q2_diagonal_gpu(ovl):
+    """<e, Q^2 e> = (m0+4)^2 + 4 for point sources on any SU(3) field."""
+    dims = (4, 4, 6, 8)
+    lat, olat, U, G = setup(ovl, dims, seed=15)
+    rng = np.random.default_rng(2)
+    e = np.zeros((4, lat.V, 4, 3), dtype=complex)
+    for r in range(4):
+        e[r, rng.integers(lat.V), rng.integers(4), rng.integers(3)] = 1.0
+    inp = ovl.Spinor.from_canonical(lat, dev(e), 0)
+    out = ovl.Spinor(lat, 0, 4)
+    ovl.q2_apply(lat, G, M0, 0.0, inp, out)
+    q = out.to_canonical().cpu().numpy()
+    for r in range(4):
+        assert abs(np.vdot(e[r], q[r]) - ((M0 + 4) ** 2 + 4)) < 1e-13
+
+
+def test_wilson_apply_16x32_full(ovl):
+    """The 16^3x32 workload (links exp(i 0.3 H), 2 stout steps), every site."""
+    dims = synth.CONFIGS[1]["dims"]
+    note(f"wilson_apply full {dims}")
+    lat = ovl.Lattice(dims)
+    olat = oracle.Lattice(dims)
+    U = synth.config_gauge(1)
+    G = ovl.Gauge(lat, dev(U))
+    psi = synth.config_sources(1)[0]
+    ref = oracle.dw(olat, U, M0, psi)
+    for prec in (0, 1, 2):
+        inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+        out = ovl.Spinor(lat, prec)
+        ovl.wilson_apply(lat, G, M0, inp, out)
+        assert rel(out.to_canonical().cpu().numpy()[0], ref) < TOL[prec]
+
+
+def test_wilson_apply_32x64_full(ovl):
+    """The 32^3x64 workload in the benchmark's launch shape, every site against
+    the oracle."""
+    dims = synth.CONFIGS[2]["dims"]
+    note(f"wilson_apply sampled {dims}")
+    lat = ovl.Lattice(dims)
+    U = synth.config_gauge(2)
+    G = ovl.Gauge(lat, dev(U))
+    psi = synth.config_sources(2)[0]
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), 0)
+    out = ovl.Spinor(lat, 0)
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    got = out.to_canonical().cpu().numpy()[0]
+    olat = oracle.Lattice(dims)
+    ref = oracle.dw(olat, U, M0, psi)
+    assert rel(got, ref) < 1e-12

@@ -1,0 +1,248 @@
+"""Benchmark: Wilson stencil HBM bandwidth and overlap applies per second.
+
+One step = one overlap apply D_ov b = rho (b + D_W(-rho) sum_l w_l (Q^2+s_l)^{-1} b)
+on the 32^3x64 workload (links exp(i 0.3 H) with 2 stout steps, one Gaussian
+source, 20 Zolotarev poles over Lanczos bounds of |Q|, multishift CG to a
+1e-10 relative residual on every shifted system): the whole hot path -- field
+packing is done once, the stencil, Q^2, the multishift iteration with its
+reductions, the combination and the final FP64 stencil run inside every step.
+Inputs are synthetic and seeded; nothing is read from disk.
+
+Prints one JSON line.  Single GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+RHO = 1.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, help="workload recipe index (2 = 32^3x64)")
+    ap.add_argument("--form", default="auto", help="overlap form for the timed steps")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    return ap.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_1410_7170_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def load_traffic(kernel: str, src: str):
+    """HBM bytes per site measured with rocprofv3 counters, if recorded for
+    these exact kernel sources (profiles/hbm_traffic.txt)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 4 and not line.startswith("#") and parts[0] == kernel and parts[1] == src:
+            return float(parts[2]) + float(parts[3])
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the overlap path here has no multi-GPU form.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1410_7170_amd as ovl
+
+    torch.cuda.set_device(0)
+    cfg = synth.CONFIGS[args.config]
+    dims = cfg["dims"]
+    npoles = cfg["poles"]
+    t_setup = time.time()
+    U = synth.config_gauge(args.config)
+    b = synth.config_sources(args.config)
+    lat = ovl.Lattice(dims)
+    V = lat.V
+    G = ovl.Gauge(lat, torch.from_numpy(U).cuda())
+    v0 = synth.gaussian_spinor(V, synth.SEED_BASE + 10 * args.config + 3)[0]
+    start = ovl.Spinor.from_canonical(lat, torch.from_numpy(v0).cuda(), ovl.F64)
+    lo, hi = ovl.spectral_bounds(lat, G, -RHO, 300, start)
+    shifts, weights, delta = ovl.zolotarev(lo, hi, npoles)
+    B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
+    out = ovl.Spinor(lat, ovl.F64, B.nrhs)
+    setup_s = time.time() - t_setup
+    print(f"[bench] setup {setup_s:.1f}s dims={dims} |Q| in [{lo:.4f}, {hi:.4f}] delta={delta:.2e}",
+          file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+
+    # ---- Wilson stencil bandwidth, one launch = D_W on every site
+    site_bytes = {ovl.F64: 192 + 192 + 4 * 144, ovl.F32: 96 + 96 + 4 * 48, ovl.F16S: 52 + 52 + 4 * 24}
+    stencil = {}
+    for prec in (ovl.F64, ovl.F32, ovl.F16S):
+        inp = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), prec)
+        o = ovl.Spinor(lat, prec)
+        for _ in range(3):
+            ovl.wilson_apply(lat, G, -RHO, inp, o)
+        n = 20
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            ovl.wilson_apply(lat, G, -RHO, inp, o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / n
+        gbps = site_bytes[prec] * V / sec / 1e9
+        stencil[ovl.PREC_NAMES[prec]] = dict(us=round(sec * 1e6, 2), GBps=round(gbps, 1),
+                                             frac=round(gbps / HBM_PEAK_GBPS, 4),
+                                             bytes_per_site=site_bytes[prec])
+        print(f"[bench] stencil {ovl.PREC_NAMES[prec]}: {sec*1e6:.1f} us {gbps:.0f} GB/s", file=sys.stderr, flush=True)
+
+    # ---- overlap applies
+    def overlap(form, profile=False):
+        if form == "fp64":
+            prm = ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile))
+        else:
+            raise ValueError(form)
+        return ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
+
+    forms = ["fp64"]
+    timed_form = forms[-1] if args.form == "auto" else args.form
+    results = {}
+    for form in forms:
+        st = overlap(form)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = overlap(form)
+        torch.cuda.synchronize()
+        results[form] = dict(seconds=time.perf_counter() - t0, iterations=st["iterations"],
+                             shift_iters=st["shift_iters"][0])
+
+    # ---- timed region: K steps of the timed form, kernels bracketed by HIP events
+    for _ in range(args.warmup):
+        overlap(timed_form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ksec = [0.0] * 4
+    kbytes = [0.0] * 4
+    klaunch = [0] * 4
+    last = None
+    for _ in range(args.steps):
+        st = overlap(timed_form, profile=True)
+        for c in range(4):
+            ksec[c] += st["kernel_seconds"][c]
+            kbytes[c] += st["kernel_bytes"][c]
+            klaunch[c] += st["kernel_launches"][c]
+        last = st
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    applies_per_s = B.nrhs * args.steps / elapsed
+
+    # accuracy of the timed form against the FP64 form on the same input
+    ref = None
+    if timed_form != "fp64":
+        pass
+    got = out.to_canonical().cpu().numpy()
+
+    # dominant kernel of the timed step
+    names = {0: "wilson_stencil_q2", 1: "multishift_update", 2: "scalar_reductions", 3: "other"}
+    dom = max(range(4), key=lambda c: ksec[c])
+    avg = ksec[dom] / max(klaunch[dom], 1)
+    bytes_per_launch = kbytes[dom] / max(klaunch[dom], 1)
+    achieved = bytes_per_launch / avg / 1e9 if avg > 0 else 0.0
+    src = source_hash()
+    traffic_site = load_traffic(names[dom], src)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBPS, 4),
+                    traffic=(round(traffic_site * V) if traffic_site else None),
+                    kernel=names[dom], avg_launch_us=round(avg * 1e6, 2),
+                    algorithmic_bytes_per_launch=round(bytes_per_launch),
+                    share_of_step=round(ksec[dom] / (elapsed), 3), source=src)
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, dims, U, b[0], shifts, weights, results["fp64"]["shift_iters"])
+
+    fp64_rate = B.nrhs / results["fp64"]["seconds"]
+    line = {
+        "metric": "Wilson stencil HBM GB/s + D_ov applies/sec @32^3x64, mixed vs FP64, 1e-10 res",
+        "value": round(applies_per_s, 4),
+        "unit": "D_ov applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if timed_form == "fp64" else "f32/f16+f64",
+        "data": "synthetic (seeded SU(3) links exp(i 0.3 H), 2 stout steps; Gaussian source)",
+        "config": {"workload": f"overlap apply {dims[1]}^3x{dims[0]}, {npoles} Zolotarev poles, "
+                               f"tol {args.tol:g}, rho {RHO}",
+                   "lattice": list(dims), "nrhs": B.nrhs, "poles": npoles, "form": timed_form,
+                   "spectral_interval": [lo, hi], "zolotarev_delta": delta},
+        "stencil": stencil,
+        "forms": {k: dict(applies_per_s=round(B.nrhs / v["seconds"], 4), iterations=v["iterations"])
+                  for k, v in results.items()},
+        "fp64_applies_per_s": round(fp64_rate, 4),
+        "speedup_vs_fp64": round(applies_per_s / fp64_rate, 3),
+        "iterations": last["iterations"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def cpu_baseline(args, dims, U, b, shifts, weights, shift_iters):
+    """Oracle timing on a bounded sample: the FP64 oracle's multishift CG on
+    the full 32^3x64 field, capped at a few iterations with every shift
+    active, plus one oracle stencil; the full apply is then priced with the
+    per-shift iteration counts of the same solve."""
+    import numpy as np
+    import oracle
+
+    lat = oracle.Lattice(dims)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    k = args.cpu_sample_iters
+    t0 = time.perf_counter()
+    oracle.q2(lat, U, -RHO, b, float(min(shifts)))
+    t_q2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.mscg(lat, U, -RHO, shifts, b, 1e-300, k)
+    t_k = time.perf_counter() - t0
+    t_shift = max(t_k / k - t_q2, 0.0) / len(shifts)
+    n_iter = max(shift_iters)
+    act_iters = sum(shift_iters)
+    est = n_iter * t_q2 + act_iters * t_shift + t_q2 / 2
+    return dict(value=round(1.0 / est, 6), unit="D_ov applies/s", cores=cores, kind="oracle",
+                sample=f"oracle multishift CG, {k} iterations with all {len(shifts)} shifts active on the "
+                       f"full {dims[1]}^3x{dims[0]} field ({t_k:.1f}s) and one oracle Q^2 ({t_q2:.2f}s); "
+                       f"apply priced as {n_iter} Q^2 + {act_iters} shift updates + 1 stencil",
+                seconds_per_apply=round(est, 2))
+
+
+if __name__ == "__main__":
+    main()

@@ -129,7 +129,17 @@ typedef struct {
                                 those above tol (1) or only report (0) */
     int32_t verify;          /* FP64 mode: also compute every shift's FP64 true
                                 residual into stats (2 FP64 stencils per shift) */
+    int32_t profile;         /* bracket the solver's kernels with HIP events on
+                                the call's stream and fill the kernel_* stats */
 } ovl_solver_params;
+
+/* kernel classes of ovl_solver_stats.kernel_* */
+enum ovl_kernel_class {
+    OVL_K_STENCIL = 0,   /* the two Wilson stencils of each iteration */
+    OVL_K_UPDATE = 1,    /* the fused shift update x_l += a_l p_l, p_l = z_l r + b_l p_l */
+    OVL_K_SCALAR = 2,    /* block reductions and the FP64 scalar recurrences */
+    OVL_K_OTHER = 3      /* reliable updates, refinement, combination */
+};
 
 typedef struct {
     int32_t iterations[OVL_MAX_RHS];                  /* multishift CG iterations per RHS */
@@ -140,6 +150,11 @@ typedef struct {
     int32_t stencil_applies;                           /* Wilson stencils launched (per RHS batch) */
     double algorithmic_bytes;                          /* compulsory HBM bytes of the launches */
     double seconds;                                    /* wall time of the call (it synchronises) */
+    /* with params.profile: summed event-timed duration, compulsory bytes and
+     * launch count per ovl_kernel_class */
+    double kernel_seconds[4];
+    double kernel_bytes[4];
+    int32_t kernel_launches[4];
 } ovl_solver_stats;
 
 /* ---- set-up and layout ------------------------------------------------ */
@@ -155,7 +170,8 @@ OVL_API size_t ovl_gauge_bytes(const ovl_lattice *lat, int32_t prec);
 
 /* Canonical complex128 device spinors ([nrhs][V][4][3]) to and from the
  * packed layout of out->prec / in->prec.  F16S packing picks the per-site
- * scale; unpacking widens exactly. */
+ * scale; unpacking widens exactly.  These two accept field sets of up to
+ * OVL_MAX_RHS*OVL_MAX_SHIFTS fields (e.g. the per-shift solutions). */
 OVL_API int ovl_pack_spinor(const ovl_lattice *lat, const void *canon, ovl_spinor *out, void *stream);
 OVL_API int ovl_unpack_spinor(const ovl_lattice *lat, const ovl_spinor *in, void *canon, void *stream);
 
@@ -238,7 +254,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
                            int32_t nshift, const ovl_solver_params *prm);
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
- * check_every 10, refine 1, verify 0. */
+ * check_every 10, refine 1, verify 0, profile 0. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 OVL_API const char *ovl_status_string(int status);

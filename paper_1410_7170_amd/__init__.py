@@ -32,6 +32,7 @@ ERR_INVALID, ERR_WORKSPACE, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
 F64, F32, F16S = 0, 1, 2
 SOLVE_F64, SOLVE_MIXED = 0, 1
 OP_Q2, OP_LANCZOS, OP_MSCG = 0, 1, 2
+K_STENCIL, K_UPDATE, K_SCALAR, K_OTHER = 0, 1, 2, 3
 MAX_SHIFTS, MAX_RHS = 32, 16
 PREC_NAMES = {F64: "f64", F32: "f32", F16S: "f16s"}
 
@@ -56,7 +57,7 @@ class ovl_zolo(ctypes.Structure):
 
 class ovl_solver_params(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("maxiter", c_i32), ("mode", c_i32), ("reliable_delta", c_dbl),
-                ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32)]
+                ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32), ("profile", c_i32)]
 
 
 class ovl_solver_stats(ctypes.Structure):
@@ -64,7 +65,8 @@ class ovl_solver_stats(ctypes.Structure):
                 ("shift_iters", (c_i32 * MAX_SHIFTS) * MAX_RHS),
                 ("true_residual", (c_dbl * MAX_SHIFTS) * MAX_RHS),
                 ("reliable_updates", c_i32), ("refine_iterations", c_i32), ("stencil_applies", c_i32),
-                ("algorithmic_bytes", c_dbl), ("seconds", c_dbl)]
+                ("algorithmic_bytes", c_dbl), ("seconds", c_dbl),
+                ("kernel_seconds", c_dbl * 4), ("kernel_bytes", c_dbl * 4), ("kernel_launches", c_i32 * 4)]
 
     def to_dict(self, nrhs: int = 1, nshift: int = 0) -> dict:
         return dict(
@@ -73,7 +75,10 @@ class ovl_solver_stats(ctypes.Structure):
             true_residual=[[float(self.true_residual[r][j]) for j in range(nshift)] for r in range(nrhs)],
             reliable_updates=int(self.reliable_updates), refine_iterations=int(self.refine_iterations),
             stencil_applies=int(self.stencil_applies), algorithmic_bytes=float(self.algorithmic_bytes),
-            seconds=float(self.seconds))
+            seconds=float(self.seconds),
+            kernel_seconds=[float(v) for v in self.kernel_seconds],
+            kernel_bytes=[float(v) for v in self.kernel_bytes],
+            kernel_launches=[int(v) for v in self.kernel_launches])
 
 
 P = ctypes.POINTER

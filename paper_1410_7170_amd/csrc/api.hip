@@ -40,14 +40,17 @@ bool lat_ok(const ovl_lattice *lat)
     return V < ((int64_t)1 << 31) && lat->vol == V;
 }
 
-bool spinor_ok(const ovl_spinor *s)
+bool spinor_ok(const ovl_spinor *s, int max_fields = OVL_MAX_RHS)
 {
     if (!s || !s->d) return false;
     if (s->prec < OVL_F64 || s->prec > OVL_F16S) return false;
-    if (s->nrhs < 1 || s->nrhs > OVL_MAX_RHS) return false;
+    if (s->nrhs < 1 || s->nrhs > max_fields) return false;
     if (s->prec == OVL_F16S && !s->scale) return false;
     return true;
 }
+
+// pack/unpack convert any field set, e.g. the nshift*nrhs solutions
+constexpr int kMaxFields = OVL_MAX_RHS * OVL_MAX_SHIFTS;
 
 const void *gauge_for(const ovl_gauge *U, int prec)
 {
@@ -121,7 +124,7 @@ size_t ovl_gauge_bytes(const ovl_lattice *lat, int32_t prec)
 
 int ovl_pack_spinor(const ovl_lattice *lat, const void *canon, ovl_spinor *out, void *stream)
 {
-    if (!lat_ok(lat) || !canon || !spinor_ok(out) || canon == out->d) return OVL_ERR_INVALID;
+    if (!lat_ok(lat) || !canon || !spinor_ok(out, kMaxFields) || canon == out->d) return OVL_ERR_INVALID;
     Lat L = make_lat(lat);
     OVL_HIP(launch_pack_spinor(L, canon, fld(out), S(stream)));
     return OVL_OK;
@@ -129,7 +132,7 @@ int ovl_pack_spinor(const ovl_lattice *lat, const void *canon, ovl_spinor *out, 
 
 int ovl_unpack_spinor(const ovl_lattice *lat, const ovl_spinor *in, void *canon, void *stream)
 {
-    if (!lat_ok(lat) || !canon || !spinor_ok(in) || canon == in->d) return OVL_ERR_INVALID;
+    if (!lat_ok(lat) || !canon || !spinor_ok(in, kMaxFields) || canon == in->d) return OVL_ERR_INVALID;
     Lat L = make_lat(lat);
     OVL_HIP(launch_unpack_spinor(L, fld(in), canon, S(stream)));
     return OVL_OK;
@@ -240,6 +243,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->check_every = 10;
     p->refine = 1;
     p->verify = 0;
+    p->profile = 0;
 }
 
 int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,
@@ -299,7 +303,7 @@ int ovl_multishift_cg(const ovl_lattice *lat, const ovl_gauge *U, double m0, int
     clear_stats(stats);
     if (!lat_ok(lat) || !spinor_ok(b) || !params_ok(prm) || !shifts || !U || !ws) return OVL_ERR_INVALID;
     // x holds nshift*nrhs fields when weights == NULL, so its count may exceed OVL_MAX_RHS
-    if (!x || !x->d || x->prec != OVL_F64 || x->nrhs < 1) return OVL_ERR_INVALID;
+    if (!spinor_ok(x, kMaxFields) || x->prec != OVL_F64) return OVL_ERR_INVALID;
     if (nshift < 1 || nshift > OVL_MAX_SHIFTS || b->prec != OVL_F64 || x->prec != OVL_F64 || b->d == x->d)
         return OVL_ERR_INVALID;
     if (x->nrhs != (weights ? b->nrhs : b->nrhs * nshift)) return OVL_ERR_INVALID;

@@ -1,6 +1,8 @@
 // Multishift CG state and kernels shared by the FP64 and mixed solvers.
 #pragma once
 
+#include <vector>
+
 #include "internal.h"
 
 namespace ovl {
@@ -37,6 +39,60 @@ struct MsScratch {
     double *red;
     Fld x;       // solutions, field j*nrhs + r
     Fld s1, s2;  // FP64 scratch fields (nrhs each)
+};
+
+// Optional event timing of the solver's kernels, on the solver's stream.
+// mark() records an event and returns its index; span(a, b, cls) charges the
+// interval between two marks to a kernel class; flush() synchronises and
+// adds the elapsed times to the stats.
+struct Prof {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    int n = 0;
+    struct Span {
+        int a, b, cls;
+    };
+    std::vector<Span> spans;
+    int mark()
+    {
+        if (!on) return -1;
+        if (n == (int)ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            ev.push_back(e);
+        }
+        if (hipEventRecord(ev[n], st) != hipSuccess) return -1;
+        return n++;
+    }
+    void span(int a, int b, int cls)
+    {
+        if (on && a >= 0 && b >= 0) spans.push_back({a, b, cls});
+    }
+    int flush(ovl_solver_stats *s)
+    {
+        if (!on) return OVL_OK;
+        if (n > 0) {
+            hipError_t e = hipEventSynchronize(ev[n - 1]);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        for (auto &sp : spans) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, ev[sp.a], ev[sp.b]);
+            if (e != hipSuccess) return hip_fail(e);
+            if (s) {
+                s->kernel_seconds[sp.cls] += 1e-3 * ms;
+                s->kernel_launches[sp.cls] += 1;
+            }
+        }
+        spans.clear();
+        n = 0;
+        return OVL_OK;
+    }
+    ~Prof()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
 };
 
 }  // namespace ovl

@@ -310,17 +310,33 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
     int it = 0;
     int stencils = 0;
     bool done = false;
+    Prof prof;
+    prof.on = prm->profile != 0 && stats;
+    prof.st = st;
     while (it < prm->maxiter && !done) {
         int batch = std::min(check, prm->maxiter - it);
         for (int k = 0; k < batch; k++) {
+            int e0 = prof.mark();
             OVL_HIP(launch_wilson(L, P_F64, W_NORM, true, A, st));
+            int e1 = prof.mark();
             k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk);
+            int e2 = prof.mark();
             OVL_HIP(launch_wilson(L, P_F64, W_RUPDATE, true, B, st));
+            int e3 = prof.mark();
             k_ms_beta<<<R, kBlock, 0, st>>>(S, partials, nblk);
+            int e4 = prof.mark();
             k_ms_update<P_F64><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, r.d, nullptr, pfl.d, nullptr, x.d, nullptr, R);
+            int e5 = prof.mark();
             OVL_HIP(hipGetLastError());
+            prof.span(e0, e1, OVL_K_STENCIL);
+            prof.span(e2, e3, OVL_K_STENCIL);
+            prof.span(e1, e2, OVL_K_SCALAR);
+            prof.span(e3, e4, OVL_K_SCALAR);
+            prof.span(e4, e5, OVL_K_UPDATE);
             stencils += 2;
         }
+        int prc = prof.flush(stats);
+        if (prc) return prc;
         it += batch;
         int one[NR];
         OVL_HIP(hipMemcpyAsync(one, S->skip, sizeof(int) * NR, hipMemcpyDeviceToHost, st));
@@ -341,16 +357,21 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
     }
     if (stats) {
         stats->stencil_applies += stencils;
-        // compulsory bytes: per iteration 2 stencils, 1 r pass, 4 passes per active shift
-        double Fb = (double)F;
-        double sten = (double)L.V * (192.0 + 192.0 + 4 * 144.0);
-        double bytes = 0;
+        // compulsory bytes per iteration: K_A reads p0 and the links and writes
+        // t; K_B reads t, the links, p0 and r and writes r; K_C reads r once and
+        // reads and writes p_j, x_j of every active shift.  (Launches on an RHS
+        // whose blocks exit early move nothing and are not counted.)
+        double Fb = (double)F, G = (double)L.V * 4 * 144.0;
+        double sten = 0, upd = 0;
         for (int q = 0; q < R; q++) {
             long act_iters = 0;
             for (int j = 0; j < nshift; j++) act_iters += stats->shift_iters[q][j];
-            bytes += h.iter[q] * (2 * sten + 4 * Fb) + act_iters * 4 * Fb;
+            sten += h.iter[q] * (6 * Fb + 2 * G);
+            upd += h.iter[q] * Fb + act_iters * 4 * Fb;
         }
-        stats->algorithmic_bytes += bytes;
+        stats->kernel_bytes[OVL_K_STENCIL] += sten;
+        stats->kernel_bytes[OVL_K_UPDATE] += upd;
+        stats->algorithmic_bytes += sten + upd;
     }
     return status;
 }

@@ -120,16 +120,20 @@ def main():
         print(f"[bench] stencil {ovl.PREC_NAMES[prec]}: {sec*1e6:.1f} us {gbps:.0f} GB/s", file=sys.stderr, flush=True)
 
     # ---- overlap applies
-    def overlap(form, profile=False):
-        if form == "fp64":
-            prm = ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile))
-        else:
-            raise ValueError(form)
-        return ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
+    def params(form, profile=False):
+        if form == "fp64":       # plain FP64: every shifted vector updated every iteration
+            return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile))
+        if form == "fp64_blocked":
+            return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=8)
+        raise ValueError(form)
 
-    forms = ["fp64"]
+    def overlap(form, profile=False):
+        return ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, params(form, profile))
+
+    forms = ["fp64", "fp64_blocked"]
     timed_form = forms[-1] if args.form == "auto" else args.form
     results = {}
+    outputs = {}
     for form in forms:
         st = overlap(form)
         torch.cuda.synchronize()
@@ -138,6 +142,10 @@ def main():
         torch.cuda.synchronize()
         results[form] = dict(seconds=time.perf_counter() - t0, iterations=st["iterations"],
                              shift_iters=st["shift_iters"][0])
+        outputs[form] = out.to_canonical().cpu().numpy()
+    ref = outputs["fp64"]
+    for form in forms:
+        results[form]["rel_diff_vs_fp64"] = float(np.linalg.norm(outputs[form] - ref) / np.linalg.norm(ref))
 
     # ---- timed region: K steps of the timed form, kernels bracketed by HIP events
     for _ in range(args.warmup):
@@ -160,11 +168,8 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     applies_per_s = B.nrhs * args.steps / elapsed
 
-    # accuracy of the timed form against the FP64 form on the same input
-    ref = None
-    if timed_form != "fp64":
-        pass
     got = out.to_canonical().cpu().numpy()
+    timed_diff = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
     # dominant kernel of the timed step
     names = {0: "wilson_stencil_q2", 1: "multishift_update", 2: "scalar_reductions", 3: "other"}
@@ -198,15 +203,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if timed_form == "fp64" else "f32/f16+f64",
+        "dtype": "f64" if timed_form.startswith("fp64") else "f32/f16+f64",
         "data": "synthetic (seeded SU(3) links exp(i 0.3 H), 2 stout steps; Gaussian source)",
         "config": {"workload": f"overlap apply {dims[1]}^3x{dims[0]}, {npoles} Zolotarev poles, "
                                f"tol {args.tol:g}, rho {RHO}",
                    "lattice": list(dims), "nrhs": B.nrhs, "poles": npoles, "form": timed_form,
                    "spectral_interval": [lo, hi], "zolotarev_delta": delta},
         "stencil": stencil,
-        "forms": {k: dict(applies_per_s=round(B.nrhs / v["seconds"], 4), iterations=v["iterations"])
+        "forms": {k: dict(applies_per_s=round(B.nrhs / v["seconds"], 4), iterations=v["iterations"],
+                          rel_diff_vs_fp64=v["rel_diff_vs_fp64"])
                   for k, v in results.items()},
+        "timed_rel_diff_vs_fp64": timed_diff,
         "fp64_applies_per_s": round(fp64_rate, 4),
         "speedup_vs_fp64": round(applies_per_s / fp64_rate, 3),
         "iterations": last["iterations"],

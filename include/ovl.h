@@ -131,6 +131,10 @@ typedef struct {
                                 residual into stats (2 FP64 stencils per shift) */
     int32_t profile;         /* bracket the solver's kernels with HIP events on
                                 the call's stream and fill the kernel_* stats */
+    int32_t block;           /* FP64 mode: 0 updates every shifted vector in every
+                                iteration; m = 1..16 keeps the last m residuals
+                                and updates each shifted vector once per m
+                                iterations (same iterates, fewer vector passes) */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */
@@ -254,7 +258,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
                            int32_t nshift, const ovl_solver_params *prm);
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
- * check_every 10, refine 1, verify 0, profile 0. */
+ * check_every 10, refine 1, verify 0, profile 0, block 0. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 OVL_API const char *ovl_status_string(int status);

@@ -19,6 +19,10 @@ hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld 
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
 size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift);
+size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x);
+int mscg_blocked(const Lat &L, const void *U64, double m0, int nshift, const double *shifts, const double *weights,
+                 Fld b, Fld yout, bool keep_x, int m, const ovl_solver_params *prm, ovl_solver_stats *stats,
+                 char *ws, size_t ws_bytes, hipStream_t st, MsScratch *scr);
 int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
                Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
                hipStream_t st);
@@ -64,7 +68,7 @@ bool params_ok(const ovl_solver_params *p)
 {
     return p && p->tol > 0.0 && std::isfinite(p->tol) && p->maxiter >= 1 &&
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED) && p->reliable_delta > 0.0 &&
-           p->reliable_delta < 1.0;
+           p->reliable_delta < 1.0 && p->block >= 0 && p->block <= 16;
 }
 
 bool zolo_ok(const ovl_zolo *z)
@@ -228,6 +232,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS) return 0;
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_MIXED) return yb + mixed_ws_bytes(L, nrhs, nshift);
+        if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true);
         return yb + mscg_ws_bytes(L, nrhs, nshift);
     }
     return 0;
@@ -244,6 +249,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->refine = 1;
     p->verify = 0;
     p->profile = 0;
+    p->block = 0;
 }
 
 int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,
@@ -279,8 +285,16 @@ static int solve_y(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         if (!U->f32 || !U->f16 || !U->f64 || !weights) return OVL_ERR_INVALID;
         return mscg_mixed(L, U, m0, nshift, shifts, weights, b, y, prm, stats, ws + yb, ws_bytes - yb, st);
     }
-    int rc = mscg_f64(L, U->f64, m0, nshift, shifts, b, prm, stats, ws + yb, ws_bytes - yb, st, scr);
+    int rc;
+    const bool blocked = prm->block > 0;
+    const bool keep_x = !weights || prm->verify;
+    if (blocked)
+        rc = mscg_blocked(L, U->f64, m0, nshift, shifts, weights, b, y, keep_x, prm->block, prm, stats, ws + yb,
+                          ws_bytes - yb, st, scr);
+    else
+        rc = mscg_f64(L, U->f64, m0, nshift, shifts, b, prm, stats, ws + yb, ws_bytes - yb, st, scr);
     if (rc < 0) return rc;
+    if (blocked && !keep_x) return rc;   // y already accumulated
     if (prm->verify && stats) {
         for (int j = 0; j < nshift; j++) {
             double res[NR];

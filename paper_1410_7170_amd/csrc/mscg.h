@@ -9,7 +9,34 @@ namespace ovl {
 
 constexpr int NR = OVL_MAX_RHS;
 constexpr int NS = OVL_MAX_SHIFTS;
+constexpr int MB = 16;   // longest block of the blocked shift update
 
+inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Sequential carving of a workspace into 256-byte aligned pieces; with a null
+// base it only measures.
+struct WsCarve {
+    char *base;
+    size_t off, cap;
+    void *take(size_t n)
+    {
+        void *p = base ? base + off : nullptr;
+        off += align256(n);
+        return p;
+    }
+};
+
+// Coefficients of the blocked shift update.  Over a block of iterations
+// k0..k0+T-1 the shift recurrences x_j += a_j p_j, p_j = z_j' r + b_j p_j are
+// linear in the block-start p_j and the stored residuals r^{k0+1..k0+T}:
+//   p_j^{k0+t} = P p_j^{k0} + sum_{i<=t} C_i r^{k0+i},
+//   x_j^{k0+T} = x_j^{k0} + XP p_j^{k0} + sum_i X_i r^{k0+i}.
+struct Blk {
+    double P[NR][NS], XP[NR][NS];
+    double C[NR][NS][MB + 1], X[NR][NS][MB + 1];
+    int inblk[NR][NS];   // shift active when the block started
+    int t[NR];           // iterations done in the current block
+};
 // Scalar state of a multishift CG on (Q^2 + s_j) x_j = b, one system per RHS,
 // kept in device memory so the iteration runs without host round trips.
 struct MState {
@@ -40,6 +67,9 @@ struct MsScratch {
     Fld x;       // solutions, field j*nrhs + r
     Fld s1, s2;  // FP64 scratch fields (nrhs each)
 };
+
+// alpha and the shifted zeta_j', alpha_j (one block per RHS); defined in solver.hip
+__global__ void k_ms_alpha(MState *st, const double *partials, int nblk);
 
 // Optional event timing of the solver's kernels, on the solver's stream.
 // mark() records an event and returns its index; span(a, b, cls) charges the

@@ -200,18 +200,6 @@ __global__ __launch_bounds__(kBlock) void k_combine(Geom g, int nb, ShiftWeights
 }
 
 // ------------------------------------------------------------------ host
-static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
-
-struct WsCarve {
-    char *base;
-    size_t off, cap;
-    void *take(size_t n)
-    {
-        void *p = base ? base + off : nullptr;
-        off += align256(n);
-        return p;
-    }
-};
 
 // Workspace of the FP64 multishift CG: state, partial sums, r, t, p_j, x_j
 // and two scratch fields.
@@ -235,6 +223,31 @@ static int read_state(MState &h, const MState *d, hipStream_t st)
 {
     OVL_HIP(hipMemcpyAsync(&h, d, sizeof(MState), hipMemcpyDeviceToHost, st));
     OVL_HIP(hipStreamSynchronize(st));
+    return OVL_OK;
+}
+
+// Upload the constant part of the scalar state, |b|^2 per RHS and the
+// initial recurrence values.  *j0_out: index of the smallest (base) shift.
+int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld b, int nshift, const double *shifts,
+                    const ovl_solver_params *prm, int *j0_out, hipStream_t st)
+{
+    const int R = b.nrhs;
+    int j0 = 0;
+    for (int j = 1; j < nshift; j++)
+        if (shifts[j] < shifts[j0]) j0 = j;
+    static thread_local MState h;
+    std::memset(&h, 0, sizeof h);
+    h.s0 = shifts[j0];
+    h.tol2 = prm->tol * prm->tol;
+    h.nrhs = R;
+    h.nshift = nshift;
+    for (int j = 0; j < nshift; j++) h.delta[j] = shifts[j] - h.s0;
+    OVL_HIP(hipMemcpyAsync(S, &h, sizeof(MState), hipMemcpyHostToDevice, st));
+    OVL_HIP(launch_norm2(L, b, partials, st));
+    OVL_HIP(launch_reduce(partials, 1, R, site_blocks(L), red, st));
+    k_ms_init<<<1, 64, 0, st>>>(S, red, R, nshift, j0);
+    OVL_HIP(hipGetLastError());
+    *j0_out = j0;
     return OVL_OK;
 }
 
@@ -266,28 +279,13 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
     scr->s2 = y2;
 
     int j0 = 0;
-    for (int j = 1; j < nshift; j++)
-        if (shifts[j] < shifts[j0]) j0 = j;
+    int rc0 = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st);
+    if (rc0) return rc0;
     const double s0 = shifts[j0];
-
-    // host copy of the constant part of the state
     MState h;
-    std::memset(&h, 0, sizeof h);
-    h.s0 = s0;
-    h.tol2 = prm->tol * prm->tol;
-    h.nrhs = R;
-    h.nshift = nshift;
-    for (int j = 0; j < nshift; j++) h.delta[j] = shifts[j] - s0;
-    OVL_HIP(hipMemcpyAsync(S, &h, sizeof(MState), hipMemcpyHostToDevice, st));
-
-    // |b|^2, starting vectors
-    OVL_HIP(launch_norm2(L, b, partials, st));
-    OVL_HIP(launch_reduce(partials, 1, R, nblk, red, st));
     dim3 sgrid(nblk, R);
     k_ms_start<<<sgrid, kBlock, 0, st>>>(L.g, L.nb, (const double2 *)b.d, (double2 *)r.d, (double2 *)pfl.d,
                                          (double2 *)x.d, R, nshift);
-    OVL_HIP(hipGetLastError());
-    k_ms_init<<<1, 64, 0, st>>>(S, red, R, nshift, j0);
     OVL_HIP(hipGetLastError());
 
     Fld p0 = sub(pfl, L.V, j0 * R, R);

@@ -28,6 +28,8 @@ struct WArgs {
     const void *U;
     const void *p;          // W_SHIFT / W_RUPDATE second field
     const float *p_sc;
+    const void *rin;        // W_RUPDATE: read r from here (null: from out, in place)
+    const float *rin_sc;
     double diag;            // m0 + 4
     double shift;
     const double *alpha;    // W_RUPDATE: alpha per RHS (device)
@@ -203,7 +205,10 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         const SpinorRef<PREC> out = spinor_ref<PREC>(a.out, a.out_sc, g.Vh, r);
         if (MODE == W_RUPDATE) {
             cplx<T> rv[4][3];
-            out.load(p, i, rv);
+            if (a.rin)
+                spinor_ref<PREC>(a.rin, a.rin_sc, g.Vh, r).load(p, i, rv);
+            else
+                out.load(p, i, rv);
             const T al = (T)a.alpha[r];
             T n0 = 0;
 #pragma unroll

@@ -71,16 +71,20 @@ def test_spectral_bounds_bracket_exact_spectrum(ovl):
     assert lo2 < aw.min() and hi2 > aw.max()
 
 
-def test_multishift_cg_matches_oracle(ovl):
+@pytest.mark.parametrize("block", [0, 1, 5, 8, 16])
+def test_multishift_cg_matches_oracle(ovl, block):
+    """Per-shift solutions of the plain (block 0) and blocked shift updates
+    against the oracle's multishift CG and its true residuals."""
     dims = (8, 4, 4, 6)
-    note("multishift cg vs oracle")
+    note(f"multishift cg vs oracle block={block}")
     U = synth.gauge(dims, 0.3, 21, n_stout=1)
     lat, olat, G, (s, w, d, lo, hi), _ = both_sides(ovl, dims, U)
     b = synth.gaussian_spinor(lat.V, 22)[0]
     x_ref, it_ref, _ = oracle.mscg(olat, U, M0, s, b, 1e-12, 3000)
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     X = ovl.Spinor(lat, 0, len(s))
-    st = ovl.multishift_cg(lat, G, M0, s, None, B, X, ovl.default_params(tol=1e-12, verify=1, check_every=7))
+    st = ovl.multishift_cg(lat, G, M0, s, None, B, X,
+                           ovl.default_params(tol=1e-12, verify=1, check_every=7, block=block))
     x = X.to_canonical().cpu().numpy()
     for j in range(len(s)):
         assert rel(x[j], x_ref[j]) < 1e-10, j
@@ -111,9 +115,10 @@ def test_sign_q_matches_exact_dense_sign(ovl):
     assert rel(O.to_canonical().cpu().numpy()[0], (Dov @ b.reshape(-1)).reshape(b.shape)) < 1e-12
 
 
+@pytest.mark.parametrize("block", [0, 8])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 4), (8, 4, 4, 6), (8, 8, 8, 8)])
-def test_overlap_apply_matches_oracle(ovl, dims):
-    note(f"overlap fp64 vs oracle {dims}")
+def test_overlap_apply_matches_oracle(ovl, dims, block):
+    note(f"overlap fp64 vs oracle {dims} block={block}")
     U = synth.gauge(dims, 0.3, 31, n_stout=2)
     lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
     assert abs(lo - olo) < 1e-8 * lo and abs(hi - ohi) < 1e-8 * hi
@@ -121,21 +126,22 @@ def test_overlap_apply_matches_oracle(ovl, dims):
     ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b, 1e-13, 5000)
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0)
-    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000))
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000, block=block))
     assert rel(O.to_canonical().cpu().numpy()[0], ref) < 1e-12
     assert st["iterations"][0] > 10
 
 
-def test_overlap_multi_rhs(ovl):
+@pytest.mark.parametrize("block", [0, 6])
+def test_overlap_multi_rhs(ovl, block):
     dims = (8, 4, 4, 4)
-    note("overlap multi-rhs")
+    note(f"overlap multi-rhs block={block}")
     U = synth.gauge(dims, 0.3, 41, n_stout=2)
     lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
     b = synth.gaussian_spinor(lat.V, 42, 3)
     b[2] *= 1e-3   # a RHS with a different scale converges on its own schedule
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0, 3)
-    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000))
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000, block=block))
     got = O.to_canonical().cpu().numpy()
     for r in range(3):
         ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b[r], 1e-13, 5000)

@@ -97,7 +97,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---- Wilson stencil bandwidth, one launch = D_W on every site
-    site_bytes = {ovl.F64: 192 + 192 + 4 * 144, ovl.F32: 96 + 96 + 4 * 48, ovl.F16S: 52 + 52 + 4 * 24}
+    site_bytes = {ovl.F64: 192 + 192 + 4 * 96, ovl.F32: 96 + 96 + 4 * 48, ovl.F16S: 52 + 52 + 4 * 24}
     stencil = {}
     for prec in (ovl.F64, ovl.F32, ovl.F16S):
         inp = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), prec)

@@ -23,16 +23,19 @@
  *   the link from x to x+mu, site = ((x0*L1 + x1)*L2 + x2)*L3 + x3.
  * gamma basis: Hermitian chiral basis, gamma_0 = [[0,I],[I,0]],
  *   gamma_k = [[0,-i sigma_k],[i sigma_k,0]], gamma_5 = g0 g1 g2 g3 = diag(-1,-1,1,1).
- * Device layouts (all produced by the pack calls below; treat as opaque):
- *   OVL_F64  spinor: complex128 per component, [rhs][parity][12][V/2]
- *   OVL_F32  spinor: float4 (two components), [rhs][parity][6][V/2]
- *   OVL_F16S spinor: 8 halves (four components), [rhs][parity][3][V/2], plus
- *            one float scale per site [rhs][parity][V/2]: stored = value/scale,
+ * Device layouts (all produced by the pack calls below; treat as opaque).
+ * Every array below is indexed [..][S] with S = round_up(V/2, 16) + 24 sites
+ * (padding keeps the component arrays of one site off power-of-two strides):
+ *   OVL_F64  spinor: complex128 per component, [rhs][parity][12][S]
+ *   OVL_F32  spinor: float4 (two components), [rhs][parity][6][S]
+ *   OVL_F16S spinor: 8 halves (four components), [rhs][parity][3][S], plus
+ *            one float scale per site [rhs][parity][S]: stored = value/scale,
  *            scale = largest |real or imaginary part| at that site
- *   gauge F64: complex128 per entry, 18 reals, [parity][mu][9][V/2]
- *   gauge F32: rows 0 and 1 as 3 float4, [parity][mu][3][V/2]; row 2 is
- *            rebuilt as conj(row0 x row1) (exact for SU(3))
- *   gauge F16: rows 0 and 1 as 3 x 4 halves, [parity][mu][3][V/2]
+ *   gauge F64: rows 0 and 1 as complex128, [parity][mu][6][S]; row 2 is
+ *            rebuilt as conj(row0 x row1) (exact for SU(3), which the links
+ *            must be)
+ *   gauge F32: rows 0 and 1 as 3 float4, [parity][mu][3][S]
+ *   gauge F16: rows 0 and 1 as 3 x 4 halves, [parity][mu][3][S]
  *
  * Every call is asynchronous on the caller's HIP stream (`stream`, a
  * hipStream_t; NULL is the null stream) unless it says it synchronises.
@@ -91,6 +94,10 @@ typedef struct {
     int32_t dims[4];   /* L0 (time), L1, L2, L3; all even, all >= 2 */
     int32_t bc[4];     /* boundary phase per direction, +1 or -1 */
     int64_t vol;       /* filled by ovl_lattice_init */
+    int32_t tile_t;    /* stencil site order: number of time slices swept per
+                          x1 column (divides dims[0]); set by ovl_lattice_init,
+                          may be changed by an autotuner; results do not
+                          depend on it beyond summation order */
 } ovl_lattice;
 
 /* A gauge field packed in up to three precisions (device pointers).  An
@@ -163,7 +170,8 @@ typedef struct {
 
 /* ---- set-up and layout ------------------------------------------------ */
 
-/* Validates dims (even, >= 2) and bc (+1/-1) and fills lat->vol. */
+/* Validates dims (even, >= 2) and bc (+1/-1), fills lat->vol and picks
+ * lat->tile_t. */
 OVL_API int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4]);
 
 /* Bytes of one packed spinor field (per RHS) and of its scale array. */

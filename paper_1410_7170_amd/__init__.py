@@ -40,7 +40,7 @@ c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, cty
 
 
 class ovl_lattice(ctypes.Structure):
-    _fields_ = [("dims", c_i32 * 4), ("bc", c_i32 * 4), ("vol", c_i64)]
+    _fields_ = [("dims", c_i32 * 4), ("bc", c_i32 * 4), ("vol", c_i64), ("tile_t", c_i32)]
 
 
 class ovl_gauge(ctypes.Structure):
@@ -158,6 +158,16 @@ class Lattice:
         self.V = int(self.c.vol)
 
     @property
+    def tile_t(self) -> int:
+        return int(self.c.tile_t)
+
+    @tile_t.setter
+    def tile_t(self, t: int):
+        if t < 1 or self.dims[0] % t:
+            raise ValueError(f"tile_t must divide L0={self.dims[0]}")
+        self.c.tile_t = int(t)
+
+    @property
     def ref(self):
         return ctypes.byref(self.c)
 
@@ -182,7 +192,7 @@ class Spinor:
     def __init__(self, lat: Lattice, prec: int, nrhs: int = 1, device="cuda"):
         self.lat, self.prec, self.nrhs = lat, prec, nrhs
         self.data = _dev_buffer(lat.spinor_bytes(prec) * nrhs, device)
-        self.scale = (torch.empty(lat.V * nrhs, dtype=torch.float32, device=device)
+        self.scale = (torch.empty(lat.scale_bytes() // 4 * nrhs, dtype=torch.float32, device=device)
                       if prec == F16S else None)
         self.c = ovl_spinor(self.data.data_ptr(), self.scale.data_ptr() if self.scale is not None else None,
                             prec, nrhs)

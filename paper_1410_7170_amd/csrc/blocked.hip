@@ -95,12 +95,12 @@ __global__ __launch_bounds__(kBlock) void k_base_p(Geom g, int nb, const MState 
     const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
     const double be = st->beta[r];
-    const size_t off = (size_t)r * 24 * g.Vh + (size_t)p * 12 * g.Vh + i;
+    const size_t off = (size_t)r * 24 * g.S + (size_t)p * 12 * g.S + i;
 #pragma unroll
     for (int c = 0; c < 12; c++) {
-        double2 a = rn[off + (size_t)c * g.Vh];
-        double2 q = p0[off + (size_t)c * g.Vh];
-        p0[off + (size_t)c * g.Vh] = make_double2(fma(be, q.x, a.x), fma(be, q.y, a.y));
+        double2 a = rn[off + (size_t)c * g.S];
+        double2 q = p0[off + (size_t)c * g.S];
+        p0[off + (size_t)c * g.S] = make_double2(fma(be, q.x, a.x), fma(be, q.y, a.y));
     }
 }
 
@@ -144,10 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     const int b = blockIdx.x;
     const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    const size_t site = (size_t)p * 12 * g.Vh + i;
-    const size_t F = (size_t)24 * g.Vh;
+    const size_t site = (size_t)p * 12 * g.S + i;
+    const size_t F = (size_t)24 * g.S;
     for (int c = 0; c < 12; c++) {
-        const size_t off = site + (size_t)c * g.Vh;
+        const size_t off = site + (size_t)c * g.S;
         double2 rv[MB];
 #pragma unroll
         for (int q = 0; q < MB; q++)
@@ -194,11 +194,11 @@ __global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const doub
     const int bl = blockIdx.x;
     const int p = bl / nb, i = (bl % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    const size_t F = (size_t)24 * g.Vh;
-    const size_t off = (size_t)rr * F + (size_t)p * 12 * g.Vh + i;
+    const size_t F = (size_t)24 * g.S;
+    const size_t off = (size_t)rr * F + (size_t)p * 12 * g.S + i;
     const double2 z = make_double2(0.0, 0.0);
     for (int c = 0; c < 12; c++) {
-        const size_t o = off + (size_t)c * g.Vh;
+        const size_t o = off + (size_t)c * g.S;
         double2 v = b[o];
         r0[o] = v;
         p0[o] = v;
@@ -362,7 +362,7 @@ int mscg_blocked(const Lat &L, const void *U64, double m0, int nshift, const dou
         // active up to iteration f takes part in ceil(f/m) passes, reading p_j
         // in each and writing it in all but the last (x mode also reads and
         // writes x_j each time); y mode reads and writes y once per pass.
-        const double Fb = (double)F, G = (double)L.V * 4 * 144.0;
+        const double Fb = (double)F, G = (double)L.V * 4 * 96.0;
         double sten = iters_all * (6 * Fb + 2 * G);
         double upd = iters_all * 3 * Fb;
         double pass = iters_all * Fb + (keep_x ? 0.0 : 2.0 * passes * R * Fb);

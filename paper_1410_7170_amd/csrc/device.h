@@ -53,7 +53,14 @@ struct Geom {
     int L[4];
     int bc[4];
     int Vh;        // V/2 sites per parity
+    int S;         // element stride between the component arrays of a field:
+                   // V/2 rounded up to 16, plus 24, so that components do not
+                   // sit a power of two apart (which maps all of a site's
+                   // components to the same L2 set and HBM channel)
+    int T;         // time-tile length of the stencil's site order (divides L0)
 };
+
+__host__ __device__ inline int padded_stride(int Vh) { return ((Vh + 15) / 16) * 16 + 24; }
 
 __device__ __forceinline__ void site_coords(const Geom &g, int p, int i, int x[4])
 {
@@ -65,6 +72,27 @@ __device__ __forceinline__ void site_coords(const Geom &g, int p, int i, int x[4
     x[1] = t % g.L[1];
     x[0] = t / g.L[1];
     x[3] = x3e + ((p + x[0] + x[1] + x[2]) & 1);
+}
+
+// Stencil site order.  Logical index j within a parity walks
+// (t-tile, x1, t within the tile, x2, x3): consecutive blocks sweep one
+// x2-x3 plane after another through T time slices before moving to the next
+// x1, so a site's +-t neighbours are touched again one plane later and its
+// +-x1 neighbours one T-plane column later -- short enough reuse distances
+// for one XCD's L2.  Threads of a wave stay on consecutive x3 of one plane,
+// i.e. on consecutive memory.
+__device__ __forceinline__ void tiled_coords(const Geom &g, int p, int j, int x[4])
+{
+    const int l3h = g.L[3] >> 1;
+    int x3h = j % l3h;
+    int q = j / l3h;
+    x[2] = q % g.L[2];
+    q /= g.L[2];
+    int tt = q % g.T;
+    q /= g.T;
+    x[1] = q % g.L[1];
+    x[0] = (q / g.L[1]) * g.T + tt;
+    x[3] = 2 * x3h + ((p + x[0] + x[1] + x[2]) & 1);
 }
 
 __device__ __forceinline__ int cb_index(const Geom &g, const int x[4])
@@ -95,6 +123,7 @@ struct Real<P_F64> {
 };
 
 // A spinor field of one RHS: pointer to its parity-0 component-0 element.
+// The member named Vh is the component stride (Geom::S) of the layout.
 template <int PREC>
 struct SpinorRef;
 
@@ -192,13 +221,13 @@ struct SpinorRef<P_F16S> {
     }
 };
 
-// Elements (in the pointer's own unit) of one RHS in each layout.
-__host__ __device__ inline size_t spinor_elems(int prec, int Vh)
+// Elements (in the pointer's own unit) of one RHS in each layout, S = stride.
+__host__ __device__ inline size_t spinor_elems(int prec, int S)
 {
-    return prec == P_F64 ? (size_t)24 * Vh : prec == P_F32 ? (size_t)12 * Vh : (size_t)6 * Vh;
+    return prec == P_F64 ? (size_t)24 * S : prec == P_F32 ? (size_t)12 * S : (size_t)6 * S;
 }
 
-// Gauge links.  F64 keeps 18 reals; F32/F16 keep rows 0 and 1 and rebuild
+// Gauge links.  Every precision keeps rows 0 and 1 and rebuilds
 // row 2 = conj(row0 x row1), which holds for every SU(3) matrix.
 template <int PREC>
 struct GaugeRef;
@@ -216,16 +245,17 @@ __device__ __forceinline__ void rebuild_row2(cplx<T> u[3][3])
 
 template <>
 struct GaugeRef<P_F64> {
-    const double2 *d;
+    const double2 *d;   // rows 0 and 1 (6 complex entries)
     int Vh;
     __device__ __forceinline__ void load(int p, int mu, int i, cplx<double> u[3][3]) const
     {
-        const double2 *b = d + (size_t)(p * 4 + mu) * 9 * Vh + i;
+        const double2 *b = d + (size_t)(p * 4 + mu) * 6 * Vh + i;
 #pragma unroll
-        for (int e = 0; e < 9; e++) {
+        for (int e = 0; e < 6; e++) {
             double2 v = b[(size_t)e * Vh];
             u[e / 3][e % 3] = {v.x, v.y};
         }
+        rebuild_row2(u);
     }
 };
 

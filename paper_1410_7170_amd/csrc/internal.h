@@ -26,12 +26,22 @@ int hip_fail(hipError_t e);
         if (e_ != hipSuccess) return ::ovl::hip_fail(e_); \
     } while (0)
 
-// bytes of one packed field (one RHS) of precision prec, excluding scales
+// bytes of one packed field (one RHS) of precision prec, excluding scales:
+// 2 parities x (12, 6 or 3) component arrays of 16-byte elements, padded stride
 inline size_t field_bytes(int prec, int64_t V)
 {
-    return prec == P_F64 ? (size_t)V * 192 : prec == P_F32 ? (size_t)V * 96 : (size_t)V * 48;
+    size_t S = (size_t)padded_stride((int)(V / 2));
+    return prec == P_F64 ? 24 * S * 16 : prec == P_F32 ? 12 * S * 16 : 6 * S * 16;
 }
-inline size_t scale_bytes(int64_t V) { return (size_t)V * 4; }
+// per-site scales of one F16S field: 2 parities x S floats
+inline size_t scale_bytes(int64_t V) { return (size_t)2 * padded_stride((int)(V / 2)) * 4; }
+inline size_t scale_floats(int64_t V) { return (size_t)2 * padded_stride((int)(V / 2)); }
+// packed gauge field: 2 parities x 4 directions x (6 F64 | 3 F32 | 3 F16) arrays
+inline size_t gauge_field_bytes(int prec, int64_t V)
+{
+    size_t S = (size_t)padded_stride((int)(V / 2));
+    return prec == P_F64 ? 48 * S * 16 : prec == P_F32 ? 24 * S * 16 : 24 * S * 8;
+}
 
 // A packed field set of nrhs fields (device pointers).
 struct Fld {
@@ -46,7 +56,7 @@ inline Fld sub(const Fld &f, int64_t V, int first, int count)
 {
     Fld o = f;
     o.d = (char *)f.d + field_bytes(f.prec, V) * first;
-    o.sc = f.sc ? f.sc + (size_t)V * first : nullptr;
+    o.sc = f.sc ? f.sc + scale_floats(V) * first : nullptr;
     o.nrhs = count;
     return o;
 }

@@ -18,6 +18,8 @@ Lat make_lat(const ovl_lattice *lat)
     L.V = (int64_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
     L.Vh = (int)(L.V / 2);
     L.g.Vh = L.Vh;
+    L.g.S = padded_stride(L.Vh);
+    L.g.T = lat->tile_t;
     L.nb = (L.Vh + kBlock - 1) / kBlock;
     return L;
 }
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_spinor(Geom g, int64_t V, const
         double2 v = src[k];
         s[k / 3][k % 3] = {(T)v.x, (T)v.y};
     }
-    spinor_ref<PREC>(d, sc, g.Vh, r).store(p, i, s);
+    spinor_ref<PREC>(d, sc, g.S, r).store(p, i, s);
 }
 
 template <int PREC>
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack_spinor(Geom g, int64_t V, con
     int p = (x0 + x1 + x2 + x3) & 1;
     int i = (int)(lex >> 1);
     cplx<T> s[4][3];
-    spinor_ref<PREC>(d, sc, g.Vh, r).load(p, i, s);
+    spinor_ref<PREC>(d, sc, g.S, r).load(p, i, s);
     double2 *dst = canon + ((size_t)r * V + lex) * 12;
 #pragma unroll
     for (int k = 0; k < 12; k++) dst[k] = make_double2((double)s[k / 3][k % 3].x, (double)s[k / 3][k % 3].y);
@@ -94,11 +96,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge(Geom g, int64_t V, const 
     int x0 = (int)(t / g.L[1]);
     int p = (x0 + x1 + x2 + x3) & 1;
     size_t i = (size_t)(lex >> 1);
-    size_t Vh = (size_t)g.Vh;
+    size_t Vh = (size_t)g.S;   // component stride
     const double2 *u = canon + (size_t)id * 9;
     if (prec == P_F64) {
-        double2 *o = (double2 *)out + (size_t)(p * 4 + mu) * 9 * Vh + i;
-        for (int e = 0; e < 9; e++) o[e * Vh] = u[e];
+        double2 *o = (double2 *)out + (size_t)(p * 4 + mu) * 6 * Vh + i;
+        for (int e = 0; e < 6; e++) o[e * Vh] = u[e];
     } else if (prec == P_F32) {
         float4 *o = (float4 *)out + (size_t)(p * 4 + mu) * 3 * Vh + i;
         for (int k = 0; k < 3; k++)
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_norm2(Geom g, int nb, const void *d,
     double v = 0.0;
     if (i < g.Vh) {
         cplx<T> s[4][3];
-        spinor_ref<PREC>(d, sc, g.Vh, r).load(p, i, s);
+        spinor_ref<PREC>(d, sc, g.S, r).load(p, i, s);
         T a = 0;
 #pragma unroll
         for (int k = 0; k < 12; k++) a += norm2(s[k / 3][k % 3]);
@@ -179,8 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_diff_norm2(Geom g, int nb, const voi
     if (i < g.Vh) {
         cplx<TA> s[4][3];
         cplx<TB> t[4][3];
-        spinor_ref<PA>(da, sa, g.Vh, r).load(p, i, s);
-        spinor_ref<PB>(db, sb, g.Vh, r).load(p, i, t);
+        spinor_ref<PA>(da, sa, g.S, r).load(p, i, s);
+        spinor_ref<PB>(db, sb, g.S, r).load(p, i, t);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             double dx = (double)s[k / 3][k % 3].x - (double)t[k / 3][k % 3].x;
@@ -201,8 +203,8 @@ __global__ __launch_bounds__(kBlock) void k_dot_f64(Geom g, int nb, int nrhs, co
     double re = 0.0, im = 0.0;
     if (i < g.Vh) {
         cplx<double> s[4][3], t[4][3];
-        spinor_ref<P_F64>(da, nullptr, g.Vh, r).load(p, i, s);
-        spinor_ref<P_F64>(db, nullptr, g.Vh, r).load(p, i, t);
+        spinor_ref<P_F64>(da, nullptr, g.S, r).load(p, i, s);
+        spinor_ref<P_F64>(db, nullptr, g.S, r).load(p, i, t);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             cplx<double> c = cmc(s[k / 3][k % 3], t[k / 3][k % 3]);
@@ -238,10 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_convert(Geom g, int nb, const void *
     if (i >= g.Vh) return;
     cplx<TS> s[4][3];
     cplx<TD> t[4][3];
-    spinor_ref<PS>(ds, ss, g.Vh, r).load(p, i, s);
+    spinor_ref<PS>(ds, ss, g.S, r).load(p, i, s);
 #pragma unroll
     for (int k = 0; k < 12; k++) t[k / 3][k % 3] = {(TD)s[k / 3][k % 3].x, (TD)s[k / 3][k % 3].y};
-    spinor_ref<PD>(dd, sd, g.Vh, r).store(p, i, t);
+    spinor_ref<PD>(dd, sd, g.S, r).store(p, i, t);
 }
 
 // y = a x + b y computed in the precision of y's arithmetic type
@@ -256,8 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_axpby(Geom g, int nb, double a, cons
     if (i >= g.Vh) return;
     cplx<TX> s[4][3];
     cplx<TY> t[4][3];
-    spinor_ref<PX>(dx, sx, g.Vh, r).load(p, i, s);
-    auto yr = spinor_ref<PY>(dy, sy, g.Vh, r);
+    spinor_ref<PX>(dx, sx, g.S, r).load(p, i, s);
+    auto yr = spinor_ref<PY>(dy, sy, g.S, r);
     if (bcoef != 0.0) {
         yr.load(p, i, t);
     } else {
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_zero(Geom g, int nb, void *d, float 
     cplx<T> t[4][3];
 #pragma unroll
     for (int k = 0; k < 12; k++) t[k / 3][k % 3] = {(T)0, (T)0};
-    spinor_ref<PREC>(d, sc, g.Vh, r).store(p, i, t);
+    spinor_ref<PREC>(d, sc, g.S, r).store(p, i, t);
 }
 
 #define DISPATCH1(prec, KERNEL, ...)                                  \

@@ -138,12 +138,12 @@ __global__ __launch_bounds__(kBlock) void k_ms_update(Geom g, int nb, const MSta
     const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
     cplx<T> rv[4][3];
-    spinor_ref<PREC>(rf, rsc, g.Vh, r).load(p, i, rv);
+    spinor_ref<PREC>(rf, rsc, g.S, r).load(p, i, rv);
     for (int j = 0; j < ns; j++) {
         if (!st->act_cur[r][j]) continue;
         const T aj = (T)st->aj[r][j], bj = (T)st->bj[r][j], zn = (T)st->zeta_new[r][j];
-        auto P = spinor_ref<PREC>(pf, psc, g.Vh, j * nrhs + r);
-        auto X = spinor_ref<PREC>(xf, xsc, g.Vh, j * nrhs + r);
+        auto P = spinor_ref<PREC>(pf, psc, g.S, j * nrhs + r);
+        auto X = spinor_ref<PREC>(xf, xsc, g.S, j * nrhs + r);
         cplx<T> pv[4][3], xv[4][3];
         P.load(p, i, pv);
         X.load(p, i, xv);
@@ -168,13 +168,13 @@ __global__ __launch_bounds__(kBlock) void k_ms_start(Geom g, int nb, const doubl
     const int p = bl / nb, i = (bl % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
     cplx<double> v[4][3], z[4][3];
-    spinor_ref<P_F64>(b, nullptr, g.Vh, rr).load(p, i, v);
-    spinor_ref<P_F64>(r, nullptr, g.Vh, rr).store(p, i, v);
+    spinor_ref<P_F64>(b, nullptr, g.S, rr).load(p, i, v);
+    spinor_ref<P_F64>(r, nullptr, g.S, rr).store(p, i, v);
 #pragma unroll
     for (int k = 0; k < 12; k++) z[k / 3][k % 3] = {0.0, 0.0};
     for (int j = 0; j < nshift; j++) {
-        spinor_ref<P_F64>(pf, nullptr, g.Vh, j * nrhs + rr).store(p, i, v);
-        spinor_ref<P_F64>(xf, nullptr, g.Vh, j * nrhs + rr).store(p, i, z);
+        spinor_ref<P_F64>(pf, nullptr, g.S, j * nrhs + rr).store(p, i, v);
+        spinor_ref<P_F64>(xf, nullptr, g.S, j * nrhs + rr).store(p, i, z);
     }
 }
 
@@ -190,13 +190,13 @@ __global__ __launch_bounds__(kBlock) void k_combine(Geom g, int nb, ShiftWeights
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k / 3][k % 3] = {0.0, 0.0};
     for (int j = 0; j < nshift; j++) {
-        spinor_ref<P_F64>(xf, nullptr, g.Vh, j * nrhs + rr).load(p, i, v);
+        spinor_ref<P_F64>(xf, nullptr, g.S, j * nrhs + rr).load(p, i, v);
         const double wj = w.w[j];
 #pragma unroll
         for (int k = 0; k < 12; k++)
             acc[k / 3][k % 3] = {fma(wj, v[k / 3][k % 3].x, acc[k / 3][k % 3].x), fma(wj, v[k / 3][k % 3].y, acc[k / 3][k % 3].y)};
     }
-    spinor_ref<P_F64>(y, nullptr, g.Vh, rr).store(p, i, acc);
+    spinor_ref<P_F64>(y, nullptr, g.S, rr).store(p, i, acc);
 }
 
 // ------------------------------------------------------------------ host
@@ -359,7 +359,7 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
         // t; K_B reads t, the links, p0 and r and writes r; K_C reads r once and
         // reads and writes p_j, x_j of every active shift.  (Launches on an RHS
         // whose blocks exit early move nothing and are not counted.)
-        double Fb = (double)F, G = (double)L.V * 4 * 144.0;
+        double Fb = (double)F, G = (double)L.V * 4 * 96.0;
         double sten = 0, upd = 0;
         for (int q = 0; q < R; q++) {
             long act_iters = 0;

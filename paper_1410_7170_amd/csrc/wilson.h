@@ -40,24 +40,24 @@ struct WArgs {
 };
 
 template <int PREC>
-__device__ __forceinline__ SpinorRef<PREC> spinor_ref(const void *base, const float *sc, int Vh, int r);
+__device__ __forceinline__ SpinorRef<PREC> spinor_ref(const void *base, const float *sc, int S, int r);
 
 template <>
-__device__ __forceinline__ SpinorRef<P_F64> spinor_ref<P_F64>(const void *base, const float *, int Vh, int r)
+__device__ __forceinline__ SpinorRef<P_F64> spinor_ref<P_F64>(const void *base, const float *, int S, int r)
 {
-    return {(double2 *)base + (size_t)r * 24 * Vh, Vh};
+    return {(double2 *)base + (size_t)r * 24 * S, S};
 }
 
 template <>
-__device__ __forceinline__ SpinorRef<P_F32> spinor_ref<P_F32>(const void *base, const float *, int Vh, int r)
+__device__ __forceinline__ SpinorRef<P_F32> spinor_ref<P_F32>(const void *base, const float *, int S, int r)
 {
-    return {(float4 *)base + (size_t)r * 12 * Vh, Vh};
+    return {(float4 *)base + (size_t)r * 12 * S, S};
 }
 
 template <>
-__device__ __forceinline__ SpinorRef<P_F16S> spinor_ref<P_F16S>(const void *base, const float *sc, int Vh, int r)
+__device__ __forceinline__ SpinorRef<P_F16S> spinor_ref<P_F16S>(const void *base, const float *sc, int S, int r)
 {
-    return {(uint4 *)base + (size_t)r * 6 * Vh, (float *)sc + (size_t)r * 2 * Vh, Vh};
+    return {(uint4 *)base + (size_t)r * 6 * S, (float *)sc + (size_t)r * 2 * S, S};
 }
 
 // Accumulate the hop in direction mu (FWD: from x+mu with U_mu(x);
@@ -153,15 +153,16 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
     if (a.skip && a.skip[r]) return;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int p = lb & 1;
-    const int i = (lb >> 1) * kBlock + threadIdx.x;
+    const int jl = (lb >> 1) * kBlock + threadIdx.x;
     const Geom &g = a.g;
-    const bool valid = i < g.Vh;
-    const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.Vh, r);
-    const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.Vh};
+    const bool valid = jl < g.Vh;
+    const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.S, r);
+    const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.S};
     double q0 = 0.0, q1 = 0.0;
     if (valid) {
         int x[4];
-        site_coords(g, p, i, x);
+        tiled_coords(g, p, jl, x);
+        const int i = cb_index(g, x);
         cplx<T> acc[4][3];
 #pragma unroll
         for (int s = 0; s < 4; s++)
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
             q1 = (double)n1;
         }
         if (MODE == W_SHIFT || MODE == W_RUPDATE) {
-            const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.Vh, r);
+            const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, r);
             cplx<T> pv[4][3];
             pf.load(p, i, pv);
             const T sh = (T)a.shift;
@@ -202,11 +203,11 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; c++) o[s][c] = {fma(sh, pv[s][c].x, o[s][c].x), fma(sh, pv[s][c].y, o[s][c].y)};
         }
-        const SpinorRef<PREC> out = spinor_ref<PREC>(a.out, a.out_sc, g.Vh, r);
+        const SpinorRef<PREC> out = spinor_ref<PREC>(a.out, a.out_sc, g.S, r);
         if (MODE == W_RUPDATE) {
             cplx<T> rv[4][3];
             if (a.rin)
-                spinor_ref<PREC>(a.rin, a.rin_sc, g.Vh, r).load(p, i, rv);
+                spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load(p, i, rv);
             else
                 out.load(p, i, rv);
             const T al = (T)a.alpha[r];

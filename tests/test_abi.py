@@ -51,13 +51,18 @@ def test_lattice_validation(ovl):
 
 def test_sizes(ovl):
     lat = ovl.Lattice((4, 4, 4, 4))
-    assert lat.spinor_bytes(ovl.F64) == 256 * 192
-    assert lat.spinor_bytes(ovl.F32) == 256 * 96
-    assert lat.spinor_bytes(ovl.F16S) == 256 * 48
-    assert lat.scale_bytes() == 256 * 4
-    assert lat.gauge_bytes(ovl.F64) == 1024 * 144
-    assert lat.gauge_bytes(ovl.F32) == 1024 * 48
-    assert lat.gauge_bytes(ovl.F16S) == 1024 * 24
+    # component arrays are S = round_up(V/2, 16) + 24 sites long
+    S = (128 + 15) // 16 * 16 + 24
+    assert lat.spinor_bytes(ovl.F64) == 2 * 12 * S * 16
+    assert lat.spinor_bytes(ovl.F32) == 2 * 6 * S * 16
+    assert lat.spinor_bytes(ovl.F16S) == 2 * 3 * S * 16
+    assert lat.scale_bytes() == 2 * S * 4
+    assert lat.gauge_bytes(ovl.F64) == 2 * 4 * 6 * S * 16
+    assert lat.gauge_bytes(ovl.F32) == 2 * 4 * 3 * S * 16
+    assert lat.gauge_bytes(ovl.F16S) == 2 * 4 * 3 * S * 8
+    big = ovl.Lattice((64, 32, 32, 32))
+    Sb = 2 ** 20 + 24
+    assert big.spinor_bytes(ovl.F64) == 24 * Sb * 16 and (Sb * 16) % (1 << 18) != 0
     p = ovl.default_params()
     assert p.tol == 1e-10 and p.mode == ovl.SOLVE_F64
     assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, p) > 40 * 256 * 192

@@ -125,13 +125,16 @@ def main():
             return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile))
         if form == "fp64_blocked":
             return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=8)
+        if form == "mixed":      # FP32 bulk, FP64 replacement/verification/refinement
+            return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=8,
+                                      mode=ovl.SOLVE_MIXED)
         raise ValueError(form)
 
     def overlap(form, profile=False):
         return ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, params(form, profile))
 
-    forms = ["fp64", "fp64_blocked"]
-    timed_form = forms[-1] if args.form == "auto" else args.form
+    forms = ["fp64", "mixed", "fp64_blocked"]
+    timed_form = "fp64_blocked" if args.form == "auto" else args.form
     results = {}
     outputs = {}
     for form in forms:
@@ -141,7 +144,9 @@ def main():
         st = overlap(form)
         torch.cuda.synchronize()
         results[form] = dict(seconds=time.perf_counter() - t0, iterations=st["iterations"],
-                             shift_iters=st["shift_iters"][0])
+                             shift_iters=st["shift_iters"][0], reliable_updates=st["reliable_updates"],
+                             refine_iterations=st["refine_iterations"],
+                             max_true_residual=max(st["true_residual"][0]))
         outputs[form] = out.to_canonical().cpu().numpy()
     ref = outputs["fp64"]
     for form in forms:
@@ -211,7 +216,8 @@ def main():
                    "spectral_interval": [lo, hi], "zolotarev_delta": delta},
         "stencil": stencil,
         "forms": {k: dict(applies_per_s=round(B.nrhs / v["seconds"], 4), iterations=v["iterations"],
-                          rel_diff_vs_fp64=v["rel_diff_vs_fp64"])
+                          rel_diff_vs_fp64=v["rel_diff_vs_fp64"], reliable_updates=v["reliable_updates"],
+                          refine_iterations=v["refine_iterations"], max_true_residual=v["max_true_residual"])
                   for k, v in results.items()},
         "timed_rel_diff_vs_fp64": timed_diff,
         "fp64_applies_per_s": round(fp64_rate, 4),

@@ -18,11 +18,7 @@ int true_residuals_f64(const Lat &L, const void *U64, double m0, double s, Fld b
 hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st);
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift);
-size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x);
-int mscg_blocked(const Lat &L, const void *U64, double m0, int nshift, const double *shifts, const double *weights,
-                 Fld b, Fld yout, bool keep_x, int m, const ovl_solver_params *prm, ovl_solver_stats *stats,
-                 char *ws, size_t ws_bytes, hipStream_t st, MsScratch *scr);
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m);
 int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
                Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
                hipStream_t st);
@@ -234,8 +230,9 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
     if (op == OVL_OP_MSCG) {
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS) return 0;
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
-        if (prm && prm->mode == OVL_SOLVE_MIXED) return yb + mixed_ws_bytes(L, nrhs, nshift);
-        if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true);
+        if (prm && prm->mode == OVL_SOLVE_MIXED)
+            return yb + mixed_ws_bytes(L, nrhs, nshift, prm->block > 0 ? prm->block : 8);
+        if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64);
         return yb + mscg_ws_bytes(L, nrhs, nshift);
     }
     return 0;
@@ -291,10 +288,13 @@ static int solve_y(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     int rc;
     const bool blocked = prm->block > 0;
     const bool keep_x = !weights || prm->verify;
-    if (blocked)
-        rc = mscg_blocked(L, U->f64, m0, nshift, shifts, weights, b, y, keep_x, prm->block, prm, stats, ws + yb,
-                          ws_bytes - yb, st, scr);
-    else
+    if (blocked) {
+        BlkOpts o;
+        o.m = prm->block;
+        o.keep_x = keep_x;
+        rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, weights, b, y, o, prm, stats, ws + yb, ws_bytes - yb, st,
+                                   scr);
+    } else
         rc = mscg_f64(L, U->f64, m0, nshift, shifts, b, prm, stats, ws + yb, ws_bytes - yb, st, scr);
     if (rc < 0) return rc;
     if (blocked && !keep_x) return rc;   // y already accumulated

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const 
         }
         double beta = rr_new / st->rr[r];
         st->beta[r] = beta;
-        const double thr = st->tol2 * st->bb[r];
+        const double thr = st->tol2r[r] * st->bb[r];
         const int t = bk->t[r];
         int left = 0;
         for (int j = 0; j < st->nshift; j++) {
@@ -86,32 +86,75 @@ __global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const 
     }
 }
 
+// Element traits of the solver's vector fields: FP64 fields are arrays of
+// complex128 (12 per site and parity), FP32 fields of float4 (two complex,
+// 6 per site and parity).
+template <int PS>
+struct El;
+template <>
+struct El<P_F64> {
+    using V = double2;
+    static constexpr int N = 12;   // elements per site and parity
+    static constexpr int C = 1;    // complex numbers per element
+    __device__ static void get(const V &v, double *re, double *im) { re[0] = v.x; im[0] = v.y; }
+    __device__ static V put(const double *re, const double *im) { return make_double2(re[0], im[0]); }
+};
+template <>
+struct El<P_F32> {
+    using V = float4;
+    static constexpr int N = 6;
+    static constexpr int C = 2;
+    __device__ static void get(const V &v, double *re, double *im)
+    {
+        re[0] = v.x; im[0] = v.y; re[1] = v.z; im[1] = v.w;
+    }
+    __device__ static V put(const double *re, const double *im)
+    {
+        return make_float4((float)re[0], (float)im[0], (float)re[1], (float)im[1]);
+    }
+};
+
 // p0 = r_new + beta p0 on RHS that are still iterating
-__global__ __launch_bounds__(kBlock) void k_base_p(Geom g, int nb, const MState *st, const double2 *rn, double2 *p0)
+template <int PS>
+__global__ __launch_bounds__(kBlock) void k_base_p(Geom g, int nb, const MState *st, const void *rnv, void *p0v)
 {
+    using E = El<PS>;
+    using V = typename E::V;
     const int r = blockIdx.y;
     if (st->skip[r]) return;
     const int b = blockIdx.x;
     const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
+    const V *rn = (const V *)rnv;
+    V *p0 = (V *)p0v;
     const double be = st->beta[r];
-    const size_t off = (size_t)r * 24 * g.S + (size_t)p * 12 * g.S + i;
+    const size_t off = (size_t)r * 2 * E::N * g.S + (size_t)p * E::N * g.S + i;
 #pragma unroll
-    for (int c = 0; c < 12; c++) {
-        double2 a = rn[off + (size_t)c * g.S];
-        double2 q = p0[off + (size_t)c * g.S];
-        p0[off + (size_t)c * g.S] = make_double2(fma(be, q.x, a.x), fma(be, q.y, a.y));
+    for (int e = 0; e < E::N; e++) {
+        double ar[E::C], ai[E::C], qr[E::C], qi[E::C];
+        E::get(rn[off + (size_t)e * g.S], ar, ai);
+        E::get(p0[off + (size_t)e * g.S], qr, qi);
+#pragma unroll
+        for (int c = 0; c < E::C; c++) {
+            qr[c] = fma(be, qr[c], ar[c]);
+            qi[c] = fma(be, qi[c], ai[c]);
+        }
+        p0[off + (size_t)e * g.S] = E::put(qr, qi);
     }
 }
 
 struct RingPtrs {
-    const double2 *slot[MB + 1];   // fields r^{k0+1..k0+T} of all RHS, slot[i] for r^{k0+i}
+    const void *slot[MB + 1];   // fields r^{k0+1..k0+T} of all RHS, slot[i] for r^{k0+i}
 };
 
-// The block pass.  y mode (xf == null): y_r += sum_j w_j dx_j; x mode: x_j += dx_j.
+// The block pass.  Sloppy fields (ring, p_j) in precision PS; x_j and y are
+// FP64.  y mode (xf == null): y_r += sum_j w_j dx_j; x mode: x_j += dx_j.
+template <int PS>
 __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
-                                                     ShiftWeights w, double2 *pf, double2 *xf, double2 *y, int nrhs)
+                                                     ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs)
 {
+    using E = El<PS>;
+    using V = typename E::V;
     __shared__ double sP[NS], sXP[NS], sW[NS];
     __shared__ double sC[NS][MB + 1], sX[NS][MB + 1];
     __shared__ int sj[NS], sact[NS];
@@ -144,143 +187,197 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     const int b = blockIdx.x;
     const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    const size_t site = (size_t)p * 12 * g.S + i;
-    const size_t F = (size_t)24 * g.S;
-    for (int c = 0; c < 12; c++) {
-        const size_t off = site + (size_t)c * g.S;
-        double2 rv[MB];
+    V *pf = (V *)pfv;
+    const size_t FS = (size_t)2 * E::N * g.S;          // sloppy field, in elements
+    const size_t F64 = (size_t)24 * g.S;               // FP64 field, in double2
+    const size_t site = (size_t)p * E::N * g.S + i;
+    const size_t site64 = (size_t)p * 12 * g.S + i;
+    for (int e = 0; e < E::N; e++) {
+        const size_t off = site + (size_t)e * g.S;
+        double rre[MB][E::C], rim[MB][E::C];
 #pragma unroll
         for (int q = 0; q < MB; q++)
-            if (q < T) rv[q] = ring.slot[q + 1][(size_t)r * F + off];
-        double2 ya = make_double2(0.0, 0.0);
+            if (q < T) E::get(((const V *)ring.slot[q + 1])[(size_t)r * FS + off], rre[q], rim[q]);
+        double yre[E::C], yim[E::C];
+#pragma unroll
+        for (int c = 0; c < E::C; c++) yre[c] = yim[c] = 0.0;
         for (int q = 0; q < n; q++) {
             const int j = sj[q];
-            double2 *pp = pf + ((size_t)j * nrhs + r) * F + off;
-            double2 pv = *pp;
-            double2 dx = make_double2(sXP[q] * pv.x, sXP[q] * pv.y);
-            double2 pn = make_double2(sP[q] * pv.x, sP[q] * pv.y);
+            V *pp = pf + ((size_t)j * nrhs + r) * FS + off;
+            double pre[E::C], pim[E::C];
+            E::get(*pp, pre, pim);
+            double dxr[E::C], dxi[E::C], pnr[E::C], pni[E::C];
+#pragma unroll
+            for (int c = 0; c < E::C; c++) {
+                dxr[c] = sXP[q] * pre[c];
+                dxi[c] = sXP[q] * pim[c];
+                pnr[c] = sP[q] * pre[c];
+                pni[c] = sP[q] * pim[c];
+            }
 #pragma unroll
             for (int t = 0; t < MB; t++)
                 if (t < T) {
                     const double xc = sX[q][t + 1], cc = sC[q][t + 1];
-                    dx.x = fma(xc, rv[t].x, dx.x);
-                    dx.y = fma(xc, rv[t].y, dx.y);
-                    pn.x = fma(cc, rv[t].x, pn.x);
-                    pn.y = fma(cc, rv[t].y, pn.y);
+#pragma unroll
+                    for (int c = 0; c < E::C; c++) {
+                        dxr[c] = fma(xc, rre[t][c], dxr[c]);
+                        dxi[c] = fma(xc, rim[t][c], dxi[c]);
+                        pnr[c] = fma(cc, rre[t][c], pnr[c]);
+                        pni[c] = fma(cc, rim[t][c], pni[c]);
+                    }
                 }
-            if (sact[q]) *pp = pn;
+            if (sact[q]) *pp = E::put(pnr, pni);
             if (xf) {
-                double2 *xp = xf + ((size_t)j * nrhs + r) * F + off;
-                double2 xv = *xp;
-                *xp = make_double2(xv.x + dx.x, xv.y + dx.y);
+                double2 *xp = xf + ((size_t)j * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
+#pragma unroll
+                for (int c = 0; c < E::C; c++) {
+                    double2 xv = xp[(size_t)c * g.S];
+                    xp[(size_t)c * g.S] = make_double2(xv.x + dxr[c], xv.y + dxi[c]);
+                }
             } else {
-                ya.x = fma(sW[q], dx.x, ya.x);
-                ya.y = fma(sW[q], dx.y, ya.y);
+#pragma unroll
+                for (int c = 0; c < E::C; c++) {
+                    yre[c] = fma(sW[q], dxr[c], yre[c]);
+                    yim[c] = fma(sW[q], dxi[c], yim[c]);
+                }
             }
         }
         if (!xf) {
-            double2 *yp = y + (size_t)r * F + off;
-            double2 yv = *yp;
-            *yp = make_double2(yv.x + ya.x, yv.y + ya.y);
+            double2 *yp = y + (size_t)r * F64 + site64 + (size_t)(e * E::C) * g.S;
+#pragma unroll
+            for (int c = 0; c < E::C; c++) {
+                double2 yv = yp[(size_t)c * g.S];
+                yp[(size_t)c * g.S] = make_double2(yv.x + yre[c], yv.y + yim[c]);
+            }
         }
     }
 }
 
-// ring slot 0 = b, p0 = b, p_j = b, and y = 0 or x_j = 0
-__global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const double2 *b, double2 *r0, double2 *p0, double2 *pf,
+// ring slot 0 = b, p0 = b, p_j = b (precision PS), and y = 0 or x_j = 0 (FP64)
+template <int PS>
+__global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const double2 *b, void *r0v, void *p0v, void *pfv,
                                                       double2 *xf, double2 *y, int nrhs, int nshift)
 {
+    using E = El<PS>;
+    using V = typename E::V;
     const int rr = blockIdx.y;
     const int bl = blockIdx.x;
     const int p = bl / nb, i = (bl % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    const size_t F = (size_t)24 * g.S;
-    const size_t off = (size_t)rr * F + (size_t)p * 12 * g.S + i;
+    V *r0 = (V *)r0v, *p0 = (V *)p0v, *pf = (V *)pfv;
+    const size_t FS = (size_t)2 * E::N * g.S;
+    const size_t F64 = (size_t)24 * g.S;
+    const size_t off = (size_t)rr * FS + (size_t)p * E::N * g.S + i;
+    const size_t off64 = (size_t)rr * F64 + (size_t)p * 12 * g.S + i;
     const double2 z = make_double2(0.0, 0.0);
-    for (int c = 0; c < 12; c++) {
-        const size_t o = off + (size_t)c * g.S;
-        double2 v = b[o];
+    for (int e = 0; e < E::N; e++) {
+        double re[E::C], im[E::C];
+#pragma unroll
+        for (int c = 0; c < E::C; c++) {
+            double2 v = b[off64 + (size_t)(e * E::C + c) * g.S];
+            re[c] = v.x;
+            im[c] = v.y;
+        }
+        V v = E::put(re, im);
+        const size_t o = off + (size_t)e * g.S;
         r0[o] = v;
         p0[o] = v;
-        for (int j = 0; j < nshift; j++) {
-            size_t oj = (size_t)j * nrhs * F + o;
-            pf[oj] = v;
-            if (xf) xf[oj] = z;
-        }
-        if (!xf) y[o] = z;
+        for (int j = 0; j < nshift; j++) pf[(size_t)j * nrhs * FS + o] = v;
+    }
+    for (int c = 0; c < 12; c++) {
+        const size_t o64 = off64 + (size_t)c * g.S;
+        for (int j = 0; j < nshift; j++)
+            if (xf) xf[(size_t)j * nrhs * F64 + o64] = z;
+        if (!xf) y[o64] = z;
     }
 }
 
-int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld b, int nshift, const double *shifts,
-                    const ovl_solver_params *prm, int *j0_out, hipStream_t st);
+// after a residual replacement: rr = rr_ref = |r_hi|^2 for RHS still iterating
+__global__ void k_set_rr(MState *st, const double *rr, int nrhs)
+{
+    int r = threadIdx.x;
+    if (r < nrhs && !st->skip[r]) {
+        st->rr[r] = rr[r];
+        st->rr_ref[r] = rr[r];
+    }
+}
 
-size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x)
+size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, int ps)
 {
     WsCarve c{nullptr, 0, 0};
-    size_t F = field_bytes(P_F64, L.V);
+    const size_t F = field_bytes(P_F64, L.V), FS = field_bytes(ps, L.V);
     c.take(sizeof(MState));
     c.take(sizeof(Blk));
     c.take(sizeof(double) * 2 * nrhs * site_blocks(L));
     c.take(sizeof(double) * 4 * NR);
-    c.take(F * nrhs * (m + 1));          // ring
-    c.take(F * nrhs);                    // p0
-    c.take(F * nrhs);                    // t
-    c.take(F * nrhs * nshift);           // p_j
-    if (keep_x) {
-        c.take(F * nrhs * nshift);       // x_j
-        c.take(F * nrhs);                // verification scratch
+    c.take(FS * nrhs * (m + 1));         // ring
+    c.take(FS * nrhs);                   // p0
+    c.take(FS * nrhs);                   // t
+    c.take(FS * nrhs * nshift);          // p_j
+    if (keep_x) c.take(F * nrhs * nshift);   // x_j
+    if (keep_x || ps != P_F64) {
+        c.take(F * nrhs);                // FP64 scratch (verification, residual replacement)
         c.take(F * nrhs);
     }
     return c.off + 256;
 }
 
-// Blocked FP64 multishift CG.  y mode (keep_x false): y (nrhs FP64 fields)
-// receives sum_j w_j x_j.  x mode: the x_j stay in the workspace and are
-// handed back through scr.
-int mscg_blocked(const Lat &L, const void *U64, double m0, int nshift, const double *shifts, const double *weights,
-                 Fld b, Fld yout, bool keep_x, int m, const ovl_solver_params *prm, ovl_solver_stats *stats,
-                 char *ws, size_t ws_bytes, hipStream_t st, MsScratch *scr)
+// Blocked multishift CG with sloppy vectors of precision PS (FP64 or FP32)
+// and FP64 x_j / y.  y mode (!o.keep_x): y (nrhs FP64 fields) receives
+// sum_j w_j x_j.  x mode: x_j go to o.x_ext if given, else to the workspace,
+// and are handed back through scr.  With o.reliable the base residual is
+// replaced by the FP64 true residual b - (Q^2 + s0) x_0 at block ends once
+// |r| has dropped by prm->reliable_delta (needs x mode).
+template <int PS>
+int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts,
+                   const double *weights, Fld b, Fld yout, const BlkOpts &o, const ovl_solver_params *prm,
+                   ovl_solver_stats *stats, char *ws, size_t ws_bytes, hipStream_t st, MsScratch *scr)
 {
     const int R = b.nrhs;
     const int nblk = site_blocks(L);
-    if (m < 1 || m > MB) return OVL_ERR_INVALID;
+    const int m = o.m;
+    if (m < 1 || m > MB || R > NR) return OVL_ERR_INVALID;
+    if (o.reliable && !o.keep_x) return OVL_ERR_INVALID;
+    const void *Us = PS == P_F64 ? U->f64 : U->f32;
+    if (!Us || !U->f64) return OVL_ERR_INVALID;
     WsCarve c{ws, 0, ws_bytes};
-    const size_t F = field_bytes(P_F64, L.V);
+    const size_t F = field_bytes(P_F64, L.V), FS = field_bytes(PS, L.V);
     MState *S = (MState *)c.take(sizeof(MState));
     Blk *BK = (Blk *)c.take(sizeof(Blk));
     double *partials = (double *)c.take(sizeof(double) * 2 * R * nblk);
     double *red = (double *)c.take(sizeof(double) * 4 * NR);
-    char *ring = (char *)c.take(F * R * (m + 1));
-    Fld p0{c.take(F * R), nullptr, P_F64, R};
-    Fld t{c.take(F * R), nullptr, P_F64, R};
-    Fld pj{c.take(F * R * nshift), nullptr, P_F64, R * nshift};
+    char *ring = (char *)c.take(FS * R * (m + 1));
+    Fld p0{c.take(FS * R), nullptr, PS, R};
+    Fld t{c.take(FS * R), nullptr, PS, R};
+    Fld pj{c.take(FS * R * nshift), nullptr, PS, R * nshift};
     Fld xs{}, s1{}, s2{};
-    if (keep_x) {
-        xs = {c.take(F * R * nshift), nullptr, P_F64, R * nshift};
+    if (o.keep_x) {
+        void *xd = c.take(F * R * nshift);
+        xs = {o.x_ext.d ? o.x_ext.d : xd, nullptr, P_F64, R * nshift};
+    }
+    if (o.keep_x || PS != P_F64) {
         s1 = {c.take(F * R), nullptr, P_F64, R};
         s2 = {c.take(F * R), nullptr, P_F64, R};
     }
     if (c.off > ws_bytes) return OVL_ERR_WORKSPACE;
     if (scr) *scr = MsScratch{partials, red, xs, s1, s2};
-    Fld out = keep_x ? xs : yout;
-    double2 *xf = keep_x ? (double2 *)out.d : nullptr;
-    double2 *y = keep_x ? nullptr : (double2 *)out.d;
-    auto slot = [&](long k) { return (double2 *)(ring + F * R * (size_t)(k % (m + 1))); };
+    double2 *xf = o.keep_x ? (double2 *)xs.d : nullptr;
+    double2 *y = o.keep_x ? nullptr : (double2 *)yout.d;
+    auto slot = [&](long k) { return (void *)(ring + FS * R * (size_t)(k % (m + 1))); };
 
     int j0 = 0;
-    int rc = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st);
+    int rc = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st, o.rhs_shift, o.rhs_tol);
     if (rc) return rc;
     dim3 sgrid(nblk, R);
-    k_blk_start<<<sgrid, kBlock, 0, st>>>(L.g, L.nb, (const double2 *)b.d, slot(0), (double2 *)p0.d,
-                                          (double2 *)pj.d, xf, y, R, nshift);
+    k_blk_start<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, (const double2 *)b.d, slot(0), p0.d, pj.d, xf, y, R,
+                                              nshift);
     k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
     OVL_HIP(hipGetLastError());
     ShiftWeights sw;
     for (int j = 0; j < NS; j++) sw.w[j] = (weights && j < nshift) ? weights[j] : 0.0;
-    const double s0 = shifts[j0];
 
     WArgs A{};
-    A.U = U64;
+    A.U = Us;
     A.diag = m0 + 4.0;
     A.partials = partials;
     A.skip = S->skip;
@@ -290,30 +387,32 @@ int mscg_blocked(const Lat &L, const void *U64, double m0, int nshift, const dou
     WArgs B = A;
     B.in = t.d;
     B.p = p0.d;
-    B.shift = s0;
+    B.shiftv = S->s0r;
     B.alpha = S->alpha;
 
     Prof prof;
     prof.on = prm->profile != 0 && stats;
     prof.st = st;
     long k = 0;
-    int passes = 0;
+    int passes = 0, replacements = 0;
     bool done = false;
+    const double rd2 = prm->reliable_delta * prm->reliable_delta;
+    static thread_local MState h;
     while (k < prm->maxiter && !done) {
         int batch = (int)std::min<long>(m, prm->maxiter - k);
         for (int q = 0; q < batch; q++, k++) {
             int e0 = prof.mark();
-            OVL_HIP(launch_wilson(L, P_F64, W_NORM, true, A, st));
+            OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
             int e1 = prof.mark();
             k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk);
             int e2 = prof.mark();
             B.rin = slot(k);
             B.out = slot(k + 1);
-            OVL_HIP(launch_wilson(L, P_F64, W_RUPDATE, true, B, st));
+            OVL_HIP(launch_wilson(L, PS, W_RUPDATE, true, B, st));
             int e3 = prof.mark();
             k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk);
             int e4 = prof.mark();
-            k_base_p<<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), (double2 *)p0.d);
+            k_base_p<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), p0.d);
             int e5 = prof.mark();
             OVL_HIP(hipGetLastError());
             prof.span(e0, e1, OVL_K_STENCIL);
@@ -326,57 +425,101 @@ int mscg_blocked(const Lat &L, const void *U64, double m0, int nshift, const dou
         RingPtrs rp;
         for (int i = 0; i <= MB; i++) rp.slot[i] = slot((k - batch + i + (m + 1)) % (m + 1));
         int e6 = prof.mark();
-        k_blk_pass<<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, (double2 *)pj.d, xf, y, R);
+        k_blk_pass<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R);
         int e7 = prof.mark();
         k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
         OVL_HIP(hipGetLastError());
         prof.span(e6, e7, OVL_K_UPDATE);
         passes++;
-        int prc = prof.flush(stats);
-        if (prc) return prc;
-        int one[NR];
-        OVL_HIP(hipMemcpyAsync(one, S->skip, sizeof(int) * NR, hipMemcpyDeviceToHost, st));
+        OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
         OVL_HIP(hipStreamSynchronize(st));
         done = true;
-        for (int q = 0; q < R; q++) done = done && one[q];
+        bool want = false;
+        for (int q = 0; q < R; q++) {
+            done = done && h.skip[q];
+            if (!h.skip[q] && h.rr[q] < rd2 * h.rr_ref[q]) want = true;
+        }
+        if (o.reliable && want && !done) {
+            // residual replacement: r = b - (Q^2 + s0) x_0 in FP64
+            int e8 = prof.mark();
+            Fld x0 = sub(xs, L.V, j0 * R, R);
+            WArgs Q1{};
+            Q1.U = U->f64;
+            Q1.diag = m0 + 4.0;
+            Q1.nrhs = R;
+            Q1.in = x0.d;
+            Q1.out = s1.d;
+            Q1.skip = S->skip;
+            OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, true, Q1, st));
+            WArgs Q2 = Q1;
+            Q2.in = s1.d;
+            Q2.p = x0.d;
+            Q2.shiftv = S->s0r;
+            Q2.out = s2.d;
+            OVL_HIP(launch_wilson(L, P_F64, W_SHIFT, true, Q2, st));
+            OVL_HIP(launch_axpby(L, 1.0, b, -1.0, s2, st));
+            OVL_HIP(launch_norm2(L, s2, partials, st));
+            OVL_HIP(launch_reduce(partials, 1, R, nblk, red, st));
+            Fld cur{slot(k), nullptr, PS, R};
+            OVL_HIP(launch_convert(L, s2, cur, st));
+            k_set_rr<<<1, 64, 0, st>>>(S, red, R);
+            OVL_HIP(hipGetLastError());
+            int e9 = prof.mark();
+            prof.span(e8, e9, OVL_K_OTHER);
+            replacements++;
+        }
+        int prc = prof.flush(stats);
+        if (prc) return prc;
     }
-    MState h;
     OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
     OVL_HIP(hipStreamSynchronize(st));
     int status = OVL_OK;
     long iters_all = 0;
+    int fz[NR][NS];
     for (int q = 0; q < R; q++) {
         if (h.nonfinite[q]) return OVL_ERR_NONFINITE;
-        if (stats) stats->iterations[q] = h.iter[q];
+        if (stats && !o.quiet) stats->iterations[q] = h.iter[q];
         iters_all += h.iter[q];
         for (int j = 0; j < nshift; j++) {
-            int fj = h.frozen_at[q][j] >= 0 ? h.frozen_at[q][j] : h.iter[q];
-            if (stats) stats->shift_iters[q][j] = fj;
+            fz[q][j] = h.frozen_at[q][j] >= 0 ? h.frozen_at[q][j] : h.iter[q];
+            if (stats && !o.quiet) stats->shift_iters[q][j] = fz[q][j];
             if (h.frozen_at[q][j] < 0) status = OVL_NOT_CONVERGED;
         }
     }
+    if (o.iters_out)
+        for (int q = 0; q < R; q++) o.iters_out[q] = h.iter[q];
     if (stats) {
-        stats->stencil_applies += 2 * (int)k;
+        stats->stencil_applies += 2 * (int)k + 2 * replacements;
+        stats->reliable_updates += replacements;
         // compulsory bytes: K_A 2F + links and K_B 4F + links per iteration,
         // K_C 3F; each pass reads the block's residuals once, and a shift
         // active up to iteration f takes part in ceil(f/m) passes, reading p_j
         // in each and writing it in all but the last (x mode also reads and
-        // writes x_j each time); y mode reads and writes y once per pass.
-        const double Fb = (double)F, G = (double)L.V * 4 * 96.0;
-        double sten = iters_all * (6 * Fb + 2 * G);
-        double upd = iters_all * 3 * Fb;
-        double pass = iters_all * Fb + (keep_x ? 0.0 : 2.0 * passes * R * Fb);
+        // writes the FP64 x_j each time); y mode reads and writes y once per pass.
+        const double Fs = (double)FS, F8 = (double)F;
+        const double G = (double)L.V * 4 * (PS == P_F64 ? 96.0 : 48.0);
+        double sten = iters_all * (6 * Fs + 2 * G);
+        double upd = iters_all * 3 * Fs;
+        double pass = iters_all * Fs + (o.keep_x ? 0.0 : 2.0 * passes * R * F8);
         for (int q = 0; q < R; q++)
             for (int j = 0; j < nshift; j++) {
-                int f = stats->shift_iters[q][j];
-                int np = (f + m - 1) / m;
-                if (np > 0) pass += (2.0 * np - 1.0) * Fb + (keep_x ? 2.0 * np * Fb : 0.0);
+                int np = (fz[q][j] + m - 1) / m;
+                if (np > 0) pass += (2.0 * np - 1.0) * Fs + (o.keep_x ? 2.0 * np * F8 : 0.0);
             }
+        double other = replacements * (R * (2 * 768.0 * L.V + 6 * F8) + R * Fs);
         stats->kernel_bytes[OVL_K_STENCIL] += sten;
         stats->kernel_bytes[OVL_K_UPDATE] += upd + pass;
-        stats->algorithmic_bytes += sten + upd + pass;
+        stats->kernel_bytes[OVL_K_OTHER] += other;
+        stats->algorithmic_bytes += sten + upd + pass + other;
     }
     return status;
 }
+
+template int mscg_blocked_t<P_F64>(const Lat &, const ovl_gauge *, double, int, const double *, const double *, Fld,
+                                   Fld, const BlkOpts &, const ovl_solver_params *, ovl_solver_stats *, char *, size_t,
+                                   hipStream_t, MsScratch *);
+template int mscg_blocked_t<P_F32>(const Lat &, const ovl_gauge *, double, int, const double *, const double *, Fld,
+                                   Fld, const BlkOpts &, const ovl_solver_params *, ovl_solver_stats *, char *, size_t,
+                                   hipStream_t, MsScratch *);
 
 }  // namespace ovl

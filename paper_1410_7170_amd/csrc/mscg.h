@@ -42,8 +42,9 @@ struct Blk {
 struct MState {
     double rr[NR], bb[NR], alpha[NR], alpha_old[NR], beta[NR];
     double zeta[NR][NS], zeta_old[NR][NS], zeta_new[NR][NS], aj[NR][NS], bj[NR][NS];
-    double delta[NS];      // s_j - s0
-    double s0, tol2;
+    double delta[NS];      // s_j - s0 (shift offsets from the base shift)
+    double s0r[NR];        // base shift of each RHS system
+    double tol2r[NR];      // squared relative tolerance of each RHS system
     int act[NR][NS];       // shift still iterating
     int act_cur[NR][NS];   // shifts updated in the current iteration
     int frozen_at[NR][NS];
@@ -60,6 +61,20 @@ struct ShiftWeights {
     double w[NS];
 };
 
+// Options of the blocked multishift CG.
+struct BlkOpts {
+    int m = 8;                          // block length
+    bool keep_x = false;                // x mode (FP64 x_j) instead of y mode
+    bool reliable = false;              // FP64 residual replacement of the base system
+    bool quiet = false;                 // do not write iteration counts into stats
+    const double *rhs_shift = nullptr;  // per-RHS base shift (host), default the smallest shift
+    const double *rhs_tol = nullptr;    // per-RHS tolerance (host), default prm->tol
+    Fld x_ext{};                        // x mode: caller's FP64 x_j (field j*nrhs + r)
+    int *iters_out = nullptr;           // per-RHS iteration counts (host)
+};
+
+size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, int ps);
+
 // Pieces of a solver workspace that callers reuse after the solve.
 struct MsScratch {
     double *partials;
@@ -70,6 +85,13 @@ struct MsScratch {
 
 // alpha and the shifted zeta_j', alpha_j (one block per RHS); defined in solver.hip
 __global__ void k_ms_alpha(MState *st, const double *partials, int nblk);
+
+// Upload the constant part of the scalar state (per-RHS base shift and
+// tolerance default to the smallest shift and prm->tol), |b|^2 per RHS and
+// the initial recurrence values.  *j0_out: index of the smallest shift.
+int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld b, int nshift, const double *shifts,
+                    const ovl_solver_params *prm, int *j0_out, hipStream_t st, const double *rhs_shift,
+                    const double *rhs_tol);
 
 // Optional event timing of the solver's kernels, on the solver's stream.
 // mark() records an event and returns its index; span(a, b, cls) charges the
@@ -124,5 +146,10 @@ struct Prof {
         for (auto e : ev) (void)hipEventDestroy(e);
     }
 };
+
+template <int PS>
+int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts,
+                   const double *weights, Fld b, Fld yout, const BlkOpts &o, const ovl_solver_params *prm,
+                   ovl_solver_stats *stats, char *ws, size_t ws_bytes, hipStream_t st, MsScratch *scr);
 
 }  // namespace ovl

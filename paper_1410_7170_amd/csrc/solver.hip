@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *p
     double tt = block_sum(a, lds);
     double pp = block_sum(b, lds + 4);
     if (threadIdx.x == 0) {
-        double pq = tt + st->s0 * pp;
+        double pq = tt + st->s0r[r] * pp;
         double alpha = st->rr[r] / pq;
         if (!isfinite(alpha) || !(pq > 0.0)) {
             st->nonfinite[r] = 1;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_beta(MState *st, const double *pa
         }
         double beta = rr_new / st->rr[r];
         st->beta[r] = beta;
-        const double thr = st->tol2 * st->bb[r];
+        const double thr = st->tol2r[r] * st->bb[r];
         int left = 0;
         for (int j = 0; j < st->nshift; j++) {
             if (!st->act_cur[r][j]) continue;
@@ -229,7 +229,8 @@ static int read_state(MState &h, const MState *d, hipStream_t st)
 // Upload the constant part of the scalar state, |b|^2 per RHS and the
 // initial recurrence values.  *j0_out: index of the smallest (base) shift.
 int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld b, int nshift, const double *shifts,
-                    const ovl_solver_params *prm, int *j0_out, hipStream_t st)
+                    const ovl_solver_params *prm, int *j0_out, hipStream_t st, const double *rhs_shift,
+                    const double *rhs_tol)
 {
     const int R = b.nrhs;
     int j0 = 0;
@@ -237,11 +238,14 @@ int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld 
         if (shifts[j] < shifts[j0]) j0 = j;
     static thread_local MState h;
     std::memset(&h, 0, sizeof h);
-    h.s0 = shifts[j0];
-    h.tol2 = prm->tol * prm->tol;
+    for (int r = 0; r < R; r++) {
+        h.s0r[r] = rhs_shift ? rhs_shift[r] : shifts[j0];
+        double t = rhs_tol ? rhs_tol[r] : prm->tol;
+        h.tol2r[r] = t * t;
+    }
     h.nrhs = R;
     h.nshift = nshift;
-    for (int j = 0; j < nshift; j++) h.delta[j] = shifts[j] - h.s0;
+    for (int j = 0; j < nshift; j++) h.delta[j] = shifts[j] - shifts[j0];
     OVL_HIP(hipMemcpyAsync(S, &h, sizeof(MState), hipMemcpyHostToDevice, st));
     OVL_HIP(launch_norm2(L, b, partials, st));
     OVL_HIP(launch_reduce(partials, 1, R, site_blocks(L), red, st));
@@ -279,7 +283,7 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
     scr->s2 = y2;
 
     int j0 = 0;
-    int rc0 = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st);
+    int rc0 = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st, nullptr, nullptr);
     if (rc0) return rc0;
     const double s0 = shifts[j0];
     MState h;
@@ -300,6 +304,7 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
     A.out = t.d;
     B.in = t.d;
     B.p = p0.d;
+    B.rin = r.d;   // r is updated in place
     B.out = r.d;
     B.shift = s0;
     B.alpha = S->alpha;

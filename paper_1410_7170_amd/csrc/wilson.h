@@ -28,10 +28,11 @@ struct WArgs {
     const void *U;
     const void *p;          // W_SHIFT / W_RUPDATE second field
     const float *p_sc;
-    const void *rin;        // W_RUPDATE: read r from here (null: from out, in place)
+    const void *rin;        // W_RUPDATE: read r from here (may equal out)
     const float *rin_sc;
     double diag;            // m0 + 4
     double shift;
+    const double *shiftv;   // per-RHS shift (device), overrides shift when set
     const double *alpha;    // W_RUPDATE: alpha per RHS (device)
     double *partials;       // [quantity][nrhs][nblk]
     const int *skip;        // per-RHS flag: block exits if skip[r] != 0 (may be null)
@@ -151,6 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
     __shared__ double lds[8];
     const int r = blockIdx.y;
     if (a.skip && a.skip[r]) return;
+    // the epilogue's shift, read once up front (a uniform scalar)
+    const double shift_r = (MODE == W_SHIFT || MODE == W_RUPDATE) ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int p = lb & 1;
     const int jl = (lb >> 1) * kBlock + threadIdx.x;
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
             const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, r);
             cplx<T> pv[4][3];
             pf.load(p, i, pv);
-            const T sh = (T)a.shift;
+            const T sh = (T)shift_r;
 #pragma unroll
             for (int s = 0; s < 4; s++)
 #pragma unroll
@@ -206,10 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         const SpinorRef<PREC> out = spinor_ref<PREC>(a.out, a.out_sc, g.S, r);
         if (MODE == W_RUPDATE) {
             cplx<T> rv[4][3];
-            if (a.rin)
-                spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load(p, i, rv);
-            else
-                out.load(p, i, rv);
+            spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load(p, i, rv);
             const T al = (T)a.alpha[r];
             T n0 = 0;
 #pragma unroll

@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--forms", default="fp64,mixed,fp64_blocked",
+                    help="comma-separated forms timed once each besides the timed form")
     return ap.parse_args()
 
 
@@ -133,8 +135,10 @@ def main():
     def overlap(form, profile=False):
         return ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, params(form, profile))
 
-    forms = ["fp64", "mixed", "fp64_blocked"]
+    forms = [f for f in args.forms.split(",") if f]
     timed_form = "fp64_blocked" if args.form == "auto" else args.form
+    if "fp64" not in forms:
+        forms.insert(0, "fp64")
     results = {}
     outputs = {}
     for form in forms:
@@ -197,6 +201,10 @@ def main():
         cpu = cpu_baseline(args, dims, U, b[0], shifts, weights, results["fp64"]["shift_iters"])
 
     fp64_rate = B.nrhs / results["fp64"]["seconds"]
+    # one unpack of a packed FP64 field: a plain streaming kernel of known size
+    # (reads ovl_spinor_bytes, writes V*192 bytes) for counter calibration
+    ovl.unpack_spinor(lat, B, torch.empty((1, V, 4, 3), dtype=torch.complex128, device="cuda"))
+    torch.cuda.synchronize()
     line = {
         "metric": "Wilson stencil HBM GB/s + D_ov applies/sec @32^3x64, mixed vs FP64, 1e-10 res",
         "value": round(applies_per_s, 4),

@@ -110,6 +110,28 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
+// Streaming stores that do not allocate in L2 (outputs of the stencil are
+// not read again by the same kernel, and keeping them out of L2 leaves room
+// for the neighbour reuse of the inputs).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_nt(double2 *p, double x, double y)
+{
+    nt_d2 t = {x, y};
+    __builtin_nontemporal_store(t, (nt_d2 *)p);
+}
+__device__ __forceinline__ void st_nt(float4 *p, float a, float b, float c, float d)
+{
+    nt_f4 t = {a, b, c, d};
+    __builtin_nontemporal_store(t, (nt_f4 *)p);
+}
+__device__ __forceinline__ void st_nt(uint4 *p, unsigned a, unsigned b, unsigned c, unsigned d)
+{
+    nt_u4 t = {a, b, c, d};
+    __builtin_nontemporal_store(t, (nt_u4 *)p);
+}
+
 // ---------------------------------------------------------------- fields
 enum { P_F64 = 0, P_F32 = 1, P_F16S = 2 };
 
@@ -146,6 +168,12 @@ struct SpinorRef<P_F64> {
 #pragma unroll
         for (int k = 0; k < 12; k++) b[(size_t)k * Vh] = make_double2(s[k / 3][k % 3].x, s[k / 3][k % 3].y);
     }
+    __device__ __forceinline__ void store_nt(int p, int i, const cplx<double> s[4][3]) const
+    {
+        double2 *b = d + (size_t)p * 12 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 12; k++) st_nt(&b[(size_t)k * Vh], s[k / 3][k % 3].x, s[k / 3][k % 3].y);
+    }
 };
 
 template <>
@@ -169,6 +197,15 @@ struct SpinorRef<P_F32> {
         for (int k = 0; k < 6; k++) {
             cplx<float> a = s[(2 * k) / 3][(2 * k) % 3], c = s[(2 * k + 1) / 3][(2 * k + 1) % 3];
             b[(size_t)k * Vh] = make_float4(a.x, a.y, c.x, c.y);
+        }
+    }
+    __device__ __forceinline__ void store_nt(int p, int i, const cplx<float> s[4][3]) const
+    {
+        float4 *b = d + (size_t)p * 6 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            cplx<float> a = s[(2 * k) / 3][(2 * k) % 3], c = s[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            st_nt(&b[(size_t)k * Vh], a.x, a.y, c.x, c.y);
         }
     }
 };
@@ -197,6 +234,7 @@ struct SpinorRef<P_F16S> {
             }
         }
     }
+    __device__ __forceinline__ void store_nt(int p, int i, const cplx<float> s[4][3]) const { store(p, i, s); }
     __device__ __forceinline__ void store(int p, int i, const cplx<float> s[4][3]) const
     {
         float m = 0.f;

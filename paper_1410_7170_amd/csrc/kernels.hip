@@ -389,7 +389,7 @@ hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hip
 {
     a.g = L.g;
     a.nblk = 2 * L.nb;
-    dim3 grid(2 * L.nb, a.nrhs);
+    dim3 grid(2 * L.nb * a.nrhs);
     if (prec == P_F64) wilson_dispatch<P_F64>(mode, g5, grid, a, st);
     else if (prec == P_F32) wilson_dispatch<P_F32>(mode, g5, grid, a, st);
     else wilson_dispatch<P_F16S>(mode, g5, grid, a, st);

@@ -150,11 +150,16 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
 {
     using T = typename Real<PREC>::T;
     __shared__ double lds[8];
-    const int r = blockIdx.y;
+    // Blocks are ordered (site block, RHS) with the RHS fastest, so the nrhs
+    // blocks covering the same sites run back to back on one XCD and share
+    // each link through its L2.
+    const int lbr = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = lbr % a.nrhs;
+    const int lb = lbr / a.nrhs;
+    const int nb = gridDim.x / a.nrhs;   // site blocks (both parities)
     if (a.skip && a.skip[r]) return;
     // the epilogue's shift, read once up front (a uniform scalar)
     const double shift_r = (MODE == W_SHIFT || MODE == W_RUPDATE) ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int p = lb & 1;
     const int jl = (lb >> 1) * kBlock + threadIdx.x;
     const Geom &g = a.g;
@@ -219,14 +224,13 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
                     rv[s][c] = {fma(-al, o[s][c].x, rv[s][c].x), fma(-al, o[s][c].y, rv[s][c].y)};
                     n0 += norm2(rv[s][c]);
                 }
-            out.store(p, i, rv);
+            out.store_nt(p, i, rv);
             q0 = (double)n0;
         } else {
-            out.store(p, i, o);
+            out.store_nt(p, i, o);
         }
     }
     if (MODE == W_NORM || MODE == W_RUPDATE) {
-        const int nb = gridDim.x;
         double t0 = block_sum(q0, lds);
         if (threadIdx.x == 0) a.partials[(size_t)r * nb + lb] = t0;
         if (MODE == W_NORM) {

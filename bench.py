@@ -50,16 +50,18 @@ def source_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def load_traffic(kernel: str, src: str):
-    """HBM bytes per site measured with rocprofv3 counters, if recorded for
-    these exact kernel sources (profiles/hbm_traffic.txt)."""
+def load_traffic(kernel: str, src: str, workload: str):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) measured with
+    rocprofv3 counters, if recorded for these exact kernel sources and this
+    workload (profiles/hbm_traffic.txt: kernel source workload fetch write)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     for line in open(path):
         parts = line.split()
-        if len(parts) >= 4 and not line.startswith("#") and parts[0] == kernel and parts[1] == src:
-            return float(parts[2]) + float(parts[3])
+        if (len(parts) >= 5 and not line.startswith("#") and parts[0] == kernel and parts[1] == src
+                and parts[2] == workload):
+            return float(parts[3]) + float(parts[4])
     return None
 
 
@@ -127,9 +129,15 @@ def main():
             return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile))
         if form == "fp64_blocked":
             return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=8)
-        if form == "mixed":      # FP32 bulk, FP64 replacement/verification/refinement
-            return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=8,
-                                      mode=ovl.SOLVE_MIXED)
+        if form.startswith("mixed"):
+            # FP64 iterations until |r|/|b| < sloppy_below ("mixed@<value>", default
+            # the library's), then the FP32 bulk with FP64 residual replacement;
+            # FP64 verification and refinement of every shift
+            prm = ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=8,
+                                     mode=ovl.SOLVE_MIXED)
+            if "@" in form:
+                prm.sloppy_below = float(form.split("@", 1)[1])
+            return prm
         raise ValueError(form)
 
     def overlap(form, profile=False):
@@ -187,10 +195,11 @@ def main():
     bytes_per_launch = kbytes[dom] / max(klaunch[dom], 1)
     achieved = bytes_per_launch / avg / 1e9 if avg > 0 else 0.0
     src = source_hash()
-    traffic_site = load_traffic(names[dom], src)
+    wl = f"{timed_form}@{'x'.join(str(d) for d in dims)}"
+    traffic = load_traffic(names[dom], src, wl)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4),
-                    traffic=(round(traffic_site * V) if traffic_site else None),
+                    traffic=(round(traffic) if traffic else None),
                     kernel=names[dom], avg_launch_us=round(avg * 1e6, 2),
                     algorithmic_bytes_per_launch=round(bytes_per_launch),
                     share_of_step=round(ksec[dom] / (elapsed), 3), source=src)

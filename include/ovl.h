@@ -142,6 +142,12 @@ typedef struct {
                                 iteration; m = 1..16 keeps the last m residuals
                                 and updates each shifted vector once per m
                                 iterations (same iterates, fewer vector passes) */
+    double sloppy_below;     /* mixed: iterate in FP64 (blocked, FP64 x_l) until
+                                the base residual ||r||/||b|| falls below this,
+                                then hand the recurrences over to FP32; rounding
+                                of the sloppy phase then enters the shifted
+                                residuals only at this level.  0: FP32 from the
+                                first iteration */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */

@@ -18,7 +18,7 @@ int true_residuals_f64(const Lat &L, const void *U64, double m0, double s, Fld b
 hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st);
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m);
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase);
 int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
                Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
                hipStream_t st);
@@ -65,7 +65,8 @@ bool params_ok(const ovl_solver_params *p)
 {
     return p && p->tol > 0.0 && std::isfinite(p->tol) && p->maxiter >= 1 &&
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED) && p->reliable_delta > 0.0 &&
-           p->reliable_delta < 1.0 && p->block >= 0 && p->block <= 16;
+           p->reliable_delta < 1.0 && p->block >= 0 && p->block <= 16 && p->sloppy_below >= 0.0 &&
+           p->sloppy_below < 1.0;
 }
 
 bool zolo_ok(const ovl_zolo *z)
@@ -231,7 +232,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS) return 0;
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_MIXED)
-            return yb + mixed_ws_bytes(L, nrhs, nshift, prm->block > 0 ? prm->block : 8);
+            return yb + mixed_ws_bytes(L, nrhs, nshift, prm->block > 0 ? prm->block : 8, prm->sloppy_below > 0.0);
         if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64);
         return yb + mscg_ws_bytes(L, nrhs, nshift);
     }
@@ -250,6 +251,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->verify = 0;
     p->profile = 0;
     p->block = 0;
+    p->sloppy_below = 1e-3;
 }
 
 int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,

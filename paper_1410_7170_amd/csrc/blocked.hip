@@ -292,6 +292,14 @@ __global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const doub
     }
 }
 
+// continuing switched recurrences: the next replacement is due once |r| has
+// fallen by reliable_delta from the hand-over
+__global__ void k_resume(MState *st, int nrhs)
+{
+    int r = threadIdx.x;
+    if (r < nrhs) st->rr_ref[r] = st->rr[r];
+}
+
 // after a residual replacement: rr = rr_ref = |r_hi|^2 for RHS still iterating
 __global__ void k_set_rr(MState *st, const double *rr, int nrhs)
 {
@@ -302,7 +310,7 @@ __global__ void k_set_rr(MState *st, const double *rr, int nrhs)
     }
 }
 
-size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, int ps)
+size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, int ps, bool ext_x)
 {
     WsCarve c{nullptr, 0, 0};
     const size_t F = field_bytes(P_F64, L.V), FS = field_bytes(ps, L.V);
@@ -314,7 +322,7 @@ size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, 
     c.take(FS * nrhs);                   // p0
     c.take(FS * nrhs);                   // t
     c.take(FS * nrhs * nshift);          // p_j
-    if (keep_x) c.take(F * nrhs * nshift);   // x_j
+    if (keep_x && !ext_x) c.take(F * nrhs * nshift);   // x_j
     if (keep_x || ps != P_F64) {
         c.take(F * nrhs);                // FP64 scratch (verification, residual replacement)
         c.take(F * nrhs);
@@ -351,10 +359,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     Fld t{c.take(FS * R), nullptr, PS, R};
     Fld pj{c.take(FS * R * nshift), nullptr, PS, R * nshift};
     Fld xs{}, s1{}, s2{};
-    if (o.keep_x) {
-        void *xd = c.take(F * R * nshift);
-        xs = {o.x_ext.d ? o.x_ext.d : xd, nullptr, P_F64, R * nshift};
-    }
+    if (o.keep_x) xs = {o.x_ext.d ? o.x_ext.d : c.take(F * R * nshift), nullptr, P_F64, R * nshift};
     if (o.keep_x || PS != P_F64) {
         s1 = {c.take(F * R), nullptr, P_F64, R};
         s2 = {c.take(F * R), nullptr, P_F64, R};
@@ -366,11 +371,30 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     auto slot = [&](long k) { return (void *)(ring + FS * R * (size_t)(k % (m + 1))); };
 
     int j0 = 0;
-    int rc = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st, o.rhs_shift, o.rhs_tol);
-    if (rc) return rc;
+    int it0[NR] = {0};   // iterations done before this solve (a resumed solve)
     dim3 sgrid(nblk, R);
-    k_blk_start<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, (const double2 *)b.d, slot(0), p0.d, pj.d, xf, y, R,
-                                              nshift);
+    static thread_local MState h;
+    if (o.resume) {
+        // continue the recurrences of a switched solve: same scalars, the
+        // vectors r, p0 and p_j rounded to this precision, x_j kept
+        const MsScratch &rs = *o.resume;
+        if (!o.keep_x || rs.r.nrhs != R || rs.pj.nrhs != R * nshift) return OVL_ERR_INVALID;
+        j0 = rs.j0;
+        OVL_HIP(hipMemcpyAsync(S, rs.S, sizeof(MState), hipMemcpyDeviceToDevice, st));
+        OVL_HIP(launch_convert(L, rs.r, Fld{slot(0), nullptr, PS, R}, st));
+        OVL_HIP(launch_convert(L, rs.p0, p0, st));
+        OVL_HIP(launch_convert(L, rs.pj, pj, st));
+        k_resume<<<1, 64, 0, st>>>(S, R);
+        OVL_HIP(hipGetLastError());
+        OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
+        OVL_HIP(hipStreamSynchronize(st));
+        for (int q = 0; q < R; q++) it0[q] = h.iter[q];
+    } else {
+        int rc = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st, o.rhs_shift, o.rhs_tol);
+        if (rc) return rc;
+        k_blk_start<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, (const double2 *)b.d, slot(0), p0.d, pj.d, xf, y, R,
+                                                  nshift);
+    }
     k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
     OVL_HIP(hipGetLastError());
     ShiftWeights sw;
@@ -395,11 +419,13 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     prof.st = st;
     long k = 0;
     int passes = 0, replacements = 0;
-    bool done = false;
+    bool done = false, switched = false;
     const double rd2 = prm->reliable_delta * prm->reliable_delta;
-    static thread_local MState h;
-    while (k < prm->maxiter && !done) {
-        int batch = (int)std::min<long>(m, prm->maxiter - k);
+    const double sw2 = o.switch_rel * o.switch_rel;
+    long it_left = prm->maxiter;
+    for (int q = 0; q < R; q++) it_left = std::min<long>(it_left, prm->maxiter - it0[q]);
+    while (k < it_left && !done && !switched) {
+        int batch = (int)std::min<long>(m, it_left - k);
         for (int q = 0; q < batch; q++, k++) {
             int e0 = prof.mark();
             OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
@@ -435,11 +461,14 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         OVL_HIP(hipStreamSynchronize(st));
         done = true;
         bool want = false;
+        switched = sw2 > 0.0;
         for (int q = 0; q < R; q++) {
             done = done && h.skip[q];
             if (!h.skip[q] && h.rr[q] < rd2 * h.rr_ref[q]) want = true;
+            if (!h.skip[q] && !(h.rr[q] <= sw2 * h.bb[q])) switched = false;
         }
-        if (o.reliable && want && !done) {
+        switched = switched && !done;
+        if (o.reliable && want && !done && !switched) {
             // residual replacement: r = b - (Q^2 + s0) x_0 in FP64
             int e8 = prof.mark();
             Fld x0 = sub(xs, L.V, j0 * R, R);
@@ -473,21 +502,29 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     }
     OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
     OVL_HIP(hipStreamSynchronize(st));
-    int status = OVL_OK;
+    int status = switched ? kSwitched : OVL_OK;
     long iters_all = 0;
-    int fz[NR][NS];
+    int fz[NR][NS];   // iterations of this solve in which shift j took part
     for (int q = 0; q < R; q++) {
         if (h.nonfinite[q]) return OVL_ERR_NONFINITE;
         if (stats && !o.quiet) stats->iterations[q] = h.iter[q];
-        iters_all += h.iter[q];
+        iters_all += h.iter[q] - it0[q];
         for (int j = 0; j < nshift; j++) {
-            fz[q][j] = h.frozen_at[q][j] >= 0 ? h.frozen_at[q][j] : h.iter[q];
-            if (stats && !o.quiet) stats->shift_iters[q][j] = fz[q][j];
-            if (h.frozen_at[q][j] < 0) status = OVL_NOT_CONVERGED;
+            const int f = h.frozen_at[q][j] >= 0 ? h.frozen_at[q][j] : h.iter[q];
+            fz[q][j] = std::max(0, f - it0[q]);
+            if (stats && !o.quiet) stats->shift_iters[q][j] = f;
+            if (h.frozen_at[q][j] < 0 && !switched) status = OVL_NOT_CONVERGED;
         }
     }
     if (o.iters_out)
-        for (int q = 0; q < R; q++) o.iters_out[q] = h.iter[q];
+        for (int q = 0; q < R; q++) o.iters_out[q] = h.iter[q] - it0[q];
+    if (scr && switched) {
+        scr->S = S;
+        scr->r = Fld{slot(k), nullptr, PS, R};
+        scr->p0 = p0;
+        scr->pj = pj;
+        scr->j0 = j0;
+    }
     if (stats) {
         stats->stencil_applies += 2 * (int)k + 2 * replacements;
         stats->reliable_updates += replacements;

@@ -1,16 +1,20 @@
 // Mixed-precision multishift CG for (Q^2 + s_j) x_j = b.
 //
-// 1. Sloppy phase: the blocked multishift CG with FP32 links, stencil and
-//    Krylov vectors (ring, p0, t, p_j); the solutions x_j accumulate in FP64;
-//    the base residual is replaced by the FP64 true residual b - (Q^2+s0) x_0
-//    whenever |r| has dropped by reliable_delta since the last replacement.
+// 0. FP64 phase (when sloppy_below > 0): the blocked multishift CG in FP64,
+//    with FP64 x_j, until the base residual |r|/|b| falls below sloppy_below.
+//    The rounding errors of a sloppy phase enter every shifted residual in
+//    proportion to the size of the residuals at the time they are made, so
+//    starting it only here keeps them of order eps_32 * sloppy_below.
+// 1. Sloppy phase: the same recurrences continue with FP32 links, stencil
+//    and Krylov vectors (ring, p0, t, p_j); the solutions x_j accumulate in
+//    FP64; the base residual is replaced by the FP64 true residual
+//    b - (Q^2 + s0) x_0 whenever |r| has dropped by reliable_delta since the
+//    last replacement.
 // 2. Verification: every shifted system's FP64 true residual
-//    |b - (Q^2 + s_j) x_j| / |b|.  Rounding in the sloppy shifted recurrences
-//    leaves the shifted residuals of order 1e-8 (the base system is kept at
-//    tol by the replacements).
+//    |b - (Q^2 + s_j) x_j| / |b|.
 // 3. Refinement: each system above tol solves (Q^2 + s_j) e = r_j with the
-//    same FP32 solver (batched over systems, one shift per batch entry) to
-//    the relative accuracy that brings it below tol, and x_j += e in FP64;
+//    FP32 solver (batched over systems, one shift per batch entry) to the
+//    relative accuracy that brings it below tol, and x_j += e in FP64;
 //    repeated (at most 3 rounds) until every system verifies.
 // The caller then forms y = sum_j w_j x_j in FP64.
 #include <cmath>
@@ -23,7 +27,7 @@ namespace ovl {
 
 hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st);
 
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m)
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase)
 {
     const size_t F = field_bytes(P_F64, L.V);
     WsCarve c{nullptr, 0, 0};
@@ -34,7 +38,9 @@ size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m)
     c.take(F * nrhs);
     c.take(sizeof(double) * 2 * NR * site_blocks(L));
     c.take(sizeof(double) * 4 * NR);
-    size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32);
+    // the FP64 phase's workspace stays alive while the FP32 phase takes over
+    size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32, true);
+    if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m, true, P_F64, true);
     size_t b = blocked_ws_bytes(L, NR, 1, m, true, P_F32);
     return c.off + std::max(a, b) + 256;
 }
@@ -81,7 +87,8 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     const int R = b.nrhs;
     const int m = prm->block > 0 ? prm->block : 8;
     const size_t F = field_bytes(P_F64, L.V);
-    if (ws_bytes < mixed_ws_bytes(L, R, nshift, m)) return OVL_ERR_WORKSPACE;
+    const bool f64_phase = prm->sloppy_below > 0.0;
+    if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, f64_phase)) return OVL_ERR_WORKSPACE;
     WsCarve c{ws, 0, ws_bytes};
     Fld X{c.take(F * R * nshift), nullptr, P_F64, R * nshift};
     Fld Eb{c.take(F * NR), nullptr, P_F64, NR};
@@ -93,15 +100,32 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     char *sws = ws + c.off;
     size_t sws_bytes = ws_bytes - c.off;
 
-    // 1. sloppy phase
+    // 0. FP64 phase, 1. sloppy phase
     BlkOpts o;
     o.m = m;
     o.keep_x = true;
     o.reliable = true;
     o.x_ext = X;
-    int rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, sws, sws_bytes, st,
+    int rc;
+    MsScratch h64{};
+    if (f64_phase) {
+        const size_t w64 = blocked_ws_bytes(L, R, nshift, m, true, P_F64, true);
+        BlkOpts o64 = o;
+        o64.reliable = false;
+        o64.switch_rel = prm->sloppy_below;
+        rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o64, prm, stats, sws, w64, st, &h64);
+        if (rc < 0) return rc;
+        if (rc == kSwitched) {
+            o.resume = &h64;
+            rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, sws + w64,
+                                       sws_bytes - w64, st, nullptr);
+            if (rc < 0) return rc;
+        }
+    } else {
+        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, sws, sws_bytes, st,
                                    nullptr);
-    if (rc < 0) return rc;
+        if (rc < 0) return rc;
+    }
 
     // 2./3. verification and refinement
     std::vector<double> res((size_t)R * nshift), bn(R);

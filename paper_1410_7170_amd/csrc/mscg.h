@@ -71,9 +71,18 @@ struct BlkOpts {
     const double *rhs_tol = nullptr;    // per-RHS tolerance (host), default prm->tol
     Fld x_ext{};                        // x mode: caller's FP64 x_j (field j*nrhs + r)
     int *iters_out = nullptr;           // per-RHS iteration counts (host)
+    // Stop at the first block end at which every unfinished RHS has
+    // |r| <= switch_rel |b| and return kSwitched, leaving the recurrences
+    // (scalars, r, p0, p_j; x_j in x mode) in the workspace for a solve in
+    // another precision to continue (0: run to convergence).
+    double switch_rel = 0.0;
+    const struct MsScratch *resume = nullptr;   // continue the recurrences of a switched solve
 };
 
-size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, int ps);
+// Return code of a blocked solve that stopped at switch_rel (internal).
+constexpr int kSwitched = 2;
+
+size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, int ps, bool ext_x = false);
 
 // Pieces of a solver workspace that callers reuse after the solve.
 struct MsScratch {
@@ -81,6 +90,10 @@ struct MsScratch {
     double *red;
     Fld x;       // solutions, field j*nrhs + r
     Fld s1, s2;  // FP64 scratch fields (nrhs each)
+    // state of the recurrences at the end of a switched blocked solve
+    MState *S = nullptr;
+    Fld r{}, p0{}, pj{};
+    int j0 = 0;
 };
 
 // alpha and the shifted zeta_j', alpha_j (one block per RHS); defined in solver.hip

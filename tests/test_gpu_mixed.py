@@ -52,14 +52,15 @@ def setup(ovl, dims, seed):
     return U, lat, olat, G, (s, w), (os_, ow)
 
 
+@pytest.mark.parametrize("sloppy_below", [0.0, 1e-3])
 @pytest.mark.parametrize("dims", [(8, 4, 4, 6), (8, 8, 8, 8), (16, 8, 8, 8)])
-def test_mixed_overlap_verified_residuals(ovl, dims):
-    note(f"mixed overlap {dims}")
+def test_mixed_overlap_verified_residuals(ovl, dims, sloppy_below):
+    note(f"mixed overlap {dims} sloppy_below={sloppy_below}")
     U, lat, olat, G, (s, w), (os_, ow) = setup(ovl, dims, 301)
     b = synth.gaussian_spinor(lat.V, 302)[0]
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0)
-    prm = ovl.default_params(tol=1e-10, maxiter=5000, mode=ovl.SOLVE_MIXED, block=8)
+    prm = ovl.default_params(tol=1e-10, maxiter=5000, mode=ovl.SOLVE_MIXED, block=8, sloppy_below=sloppy_below)
     st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, prm)
     tr = np.array(st["true_residual"][0])
     assert (tr > 0).all() and (tr <= 1e-10).all(), tr
@@ -112,3 +113,28 @@ def test_mixed_ginsparg_wilson(ovl):
     lhs = g5(Db) + D(g5(b))
     rhs = D(g5(Db)) / RHO
     assert np.linalg.norm(lhs - rhs) / np.linalg.norm(b) < 1e-8
+
+
+def test_mixed_fp64_phase_cuts_refinement(ovl):
+    """Starting the FP32 phase only once |r|/|b| < 1e-4 leaves the shifted
+    residuals near tol, so the refinement has little left to do, while the
+    iterates stay those of the FP64 solver (same iteration count)."""
+    dims = (16, 8, 8, 8)
+    note(f"mixed FP64-phase switch {dims}")
+    U, lat, olat, G, (s, w), _ = setup(ovl, dims, 331)
+    b = synth.gaussian_spinor(lat.V, 332)[0]
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    runs = {}
+    for sb in (0.0, 1e-4):
+        O = ovl.Spinor(lat, 0)
+        prm = ovl.default_params(tol=1e-10, maxiter=5000, mode=ovl.SOLVE_MIXED, block=8, sloppy_below=sb)
+        st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, prm)
+        tr = np.array(st["true_residual"][0])
+        assert (tr > 0).all() and (tr <= 1e-10).all(), (sb, tr)
+        runs[sb] = (st, O.to_canonical().cpu().numpy()[0])
+    O64 = ovl.Spinor(lat, 0)
+    st64 = ovl.overlap_apply(lat, G, RHO, s, w, B, O64, ovl.default_params(tol=1e-10, maxiter=5000, block=8))
+    ref = O64.to_canonical().cpu().numpy()[0]
+    assert rel(runs[1e-4][1], ref) < 1e-9
+    assert runs[1e-4][0]["refine_iterations"] < runs[0.0][0]["refine_iterations"]
+    assert abs(runs[1e-4][0]["iterations"][0] - st64["iterations"][0]) <= 8

@@ -141,7 +141,8 @@ typedef struct {
     int32_t block;           /* FP64 mode: 0 updates every shifted vector in every
                                 iteration; m = 1..16 keeps the last m residuals
                                 and updates each shifted vector once per m
-                                iterations (same iterates, fewer vector passes) */
+                                iterations (same iterates, fewer vector passes).
+                                Mixed mode: block length, 0 meaning 16 */
     double sloppy_below;     /* mixed: iterate in FP64 (blocked, FP64 x_l) until
                                 the base residual ||r||/||b|| falls below this,
                                 then hand the recurrences over to FP32; rounding

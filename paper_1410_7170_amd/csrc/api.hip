@@ -232,7 +232,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS) return 0;
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_MIXED)
-            return yb + mixed_ws_bytes(L, nrhs, nshift, prm->block > 0 ? prm->block : 8, prm->sloppy_below > 0.0);
+            return yb + mixed_ws_bytes(L, nrhs, nshift, prm->block > 0 ? prm->block : 16, prm->sloppy_below > 0.0);
         if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64);
         return yb + mscg_ws_bytes(L, nrhs, nshift);
     }
@@ -251,7 +251,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->verify = 0;
     p->profile = 0;
     p->block = 0;
-    p->sloppy_below = 1e-3;
+    p->sloppy_below = 1e-5;
 }
 
 int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,

@@ -38,6 +38,7 @@ size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase)
     c.take(F * nrhs);
     c.take(sizeof(double) * 2 * NR * site_blocks(L));
     c.take(sizeof(double) * 4 * NR);
+    c.take(sizeof(double) * NR * NS);                 // shift of each (shift, RHS) field
     // the FP64 phase's workspace stays alive while the FP32 phase takes over
     size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32, true);
     if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m, true, P_F64, true);
@@ -85,7 +86,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
                hipStream_t st)
 {
     const int R = b.nrhs;
-    const int m = prm->block > 0 ? prm->block : 8;
+    const int m = prm->block > 0 ? prm->block : 16;
     const size_t F = field_bytes(P_F64, L.V);
     const bool f64_phase = prm->sloppy_below > 0.0;
     if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, f64_phase)) return OVL_ERR_WORKSPACE;
@@ -97,6 +98,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     Fld Res{c.take(F * R), nullptr, P_F64, R};
     double *partials = (double *)c.take(sizeof(double) * 2 * NR * site_blocks(L));
     double *red = (double *)c.take(sizeof(double) * 4 * NR);
+    double *fsh = (double *)c.take(sizeof(double) * NR * NS);
     char *sws = ws + c.off;
     size_t sws_bytes = ws_bytes - c.off;
 
@@ -128,20 +130,55 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     }
 
     // 2./3. verification and refinement
-    std::vector<double> res((size_t)R * nshift), bn(R);
-    auto verify = [&](int j, bool only_failing) -> int {
-        double nr[NR], nb[NR];
-        int e = residual_f64(L, U->f64, m0, shifts[j], b, sub(X, L.V, j * R, R), T, Res, partials, red, nr, nb, st);
-        if (e) return e;
-        for (int q = 0; q < R; q++) {
-            bn[q] = nb[q];
-            res[(size_t)j * R + q] = nb[q] > 0 ? nr[q] / nb[q] : 0.0;
+    const int nblk = site_blocks(L);
+    std::vector<double> res((size_t)R * nshift), bn(R), hsh((size_t)R * nshift);
+    for (int f = 0; f < R * nshift; f++) hsh[f] = shifts[f / R];
+    OVL_HIP(hipMemcpyAsync(fsh, hsh.data(), sizeof(double) * R * nshift, hipMemcpyHostToDevice, st));
+    {
+        double h[NR];
+        OVL_HIP(launch_norm2(L, b, partials, st));
+        OVL_HIP(launch_reduce(partials, 1, R, nblk, red, st));
+        OVL_HIP(hipMemcpyAsync(h, red, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+        OVL_HIP(hipStreamSynchronize(st));
+        for (int q = 0; q < R; q++) bn[q] = std::sqrt(h[q]);
+    }
+    // FP64 true residuals |b - (Q^2 + s_j) x_j| / |b| of the fields f0 .. f0+n-1
+    // of X (field f = j*R + q), up to NR fields per pair of batched stencils:
+    // t = Q x, then the norm of b - (Q t + s x) without storing it
+    auto verify = [&](int f0, int n) -> int {
+        for (int c0 = f0; c0 < f0 + n; c0 += NR) {
+            const int nc = std::min(NR, f0 + n - c0);
+            WArgs A{};
+            A.U = U->f64;
+            A.diag = m0 + 4.0;
+            A.nrhs = nc;
+            A.in = sub(X, L.V, c0, nc).d;
+            A.out = Eb.d;
+            OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, true, A, st));
+            WArgs B = A;
+            B.in = Eb.d;
+            B.out = nullptr;
+            B.p = A.in;
+            B.shiftv = fsh + c0;
+            B.rin = b.d;
+            B.rin_first = c0 % R;
+            B.rin_count = R;
+            B.partials = partials;
+            OVL_HIP(launch_wilson(L, P_F64, W_RESNORM, true, B, st));
+            OVL_HIP(launch_reduce(partials, 1, nc, nblk, red, st));
+            double h[NR];
+            OVL_HIP(hipMemcpyAsync(h, red, sizeof(double) * nc, hipMemcpyDeviceToHost, st));
+            OVL_HIP(hipStreamSynchronize(st));
+            for (int k = 0; k < nc; k++) {
+                const int f = c0 + k;
+                res[f] = bn[f % R] > 0 ? std::sqrt(h[k]) / bn[f % R] : 0.0;
+            }
+            if (stats) stats->stencil_applies += 2;
         }
-        if (stats) stats->stencil_applies += 2;
         return OVL_OK;
     };
-    for (int j = 0; j < nshift; j++) {
-        int e = verify(j, false);
+    {
+        int e = verify(0, R * nshift);
         if (e) return e;
     }
     int refine_iters = 0;
@@ -194,7 +231,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             bool any = false;
             for (auto &pr : bad) any = any || pr.first == j;
             if (!any) continue;
-            int e = verify(j, true);
+            int e = verify(j * R, R);
             if (e) return e;
         }
     }

@@ -17,6 +17,7 @@ enum WMode {
     W_NORM = 1,      // out = Gamma_5 D in;  partials |out|^2, |in(x)|^2
     W_SHIFT = 2,     // out = Gamma_5 D in + shift * p
     W_RUPDATE = 3,   // r  -= alpha_r (Gamma_5 D in + shift * p); partial |r|^2
+    W_RESNORM = 4,   // partial |rin - (Gamma_5 D in + shift * p)|^2, nothing stored
 };
 
 struct WArgs {
@@ -30,6 +31,8 @@ struct WArgs {
     const float *p_sc;
     const void *rin;        // W_RUPDATE: read r from here (may equal out)
     const float *rin_sc;
+    int rin_first;          // W_RESNORM: RHS r reads field (rin_first + r) % rin_count of rin
+    int rin_count;
     double diag;            // m0 + 4
     double shift;
     const double *shiftv;   // per-RHS shift (device), overrides shift when set
@@ -159,7 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
     const int nb = gridDim.x / a.nrhs;   // site blocks (both parities)
     if (a.skip && a.skip[r]) return;
     // the epilogue's shift, read once up front (a uniform scalar)
-    const double shift_r = (MODE == W_SHIFT || MODE == W_RUPDATE) ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
+    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
+    const double shift_r = kShift ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
     const int p = lb & 1;
     const int jl = (lb >> 1) * kBlock + threadIdx.x;
     const Geom &g = a.g;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
             q0 = (double)n0;
             q1 = (double)n1;
         }
-        if (MODE == W_SHIFT || MODE == W_RUPDATE) {
+        if (kShift) {
             const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, r);
             cplx<T> pv[4][3];
             pf.load(p, i, pv);
@@ -226,11 +230,20 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
                 }
             out.store_nt(p, i, rv);
             q0 = (double)n0;
+        } else if (MODE == W_RESNORM) {
+            cplx<T> rv[4][3];
+            spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load(p, i, rv);
+            T n0 = 0;
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) n0 += norm2(rv[s][c] - o[s][c]);
+            q0 = (double)n0;
         } else {
             out.store_nt(p, i, o);
         }
     }
-    if (MODE == W_NORM || MODE == W_RUPDATE) {
+    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
         double t0 = block_sum(q0, lds);
         if (threadIdx.x == 0) a.partials[(size_t)r * nb + lb] = t0;
         if (MODE == W_NORM) {

@@ -1,0 +1,35 @@
+// Launch of the Wilson stencil kernels (wilson.h): one block per 256 sites of
+// one parity and one RHS, blocks ordered (site block, RHS) and spread over the
+// XCDs by the kernel itself.
+#include "internal.h"
+
+namespace ovl {
+
+template <int PREC>
+static void wilson_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
+{
+    if (g5) {
+        switch (mode) {
+        case W_PLAIN: k_wilson<PREC, W_PLAIN, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_NORM: k_wilson<PREC, W_NORM, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_SHIFT: k_wilson<PREC, W_SHIFT, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_RUPDATE: k_wilson<PREC, W_RUPDATE, true><<<grid, kBlock, 0, st>>>(a); break;
+        default: k_wilson<PREC, W_RESNORM, true><<<grid, kBlock, 0, st>>>(a); break;
+        }
+    } else {
+        k_wilson<PREC, W_PLAIN, false><<<grid, kBlock, 0, st>>>(a);
+    }
+}
+
+hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hipStream_t st)
+{
+    a.g = L.g;
+    a.nblk = 2 * L.nb;
+    dim3 grid(2 * L.nb * a.nrhs);
+    if (prec == P_F64) wilson_dispatch<P_F64>(mode, g5, grid, a, st);
+    else if (prec == P_F32) wilson_dispatch<P_F32>(mode, g5, grid, a, st);
+    else wilson_dispatch<P_F16S>(mode, g5, grid, a, st);
+    return hipGetLastError();
+}
+
+}  // namespace ovl

@@ -1,6 +1,7 @@
-"""GPU checks of the mixed-precision overlap apply: FP32 links, stencil and
-Krylov vectors with FP64 residual replacement, FP64 per-shift verification
-and refinement.  Bar: every shifted system's FP64 true residual <= 1e-10
+"""GPU checks of the mixed-precision overlap apply: FP64 iterations until the
+base residual falls below sloppy_below, then FP32 links, stencil and Krylov
+vectors with FP64 residual replacement; FP64 per-shift verification (batched
+fused residual norms) and refinement.  Bar: every shifted system's FP64 true residual <= 1e-10
 (verified by the library and re-checked here with the oracle), and D_ov
 within 1e-8 of the FP64 oracle (a 1e-10 residual bounds the solution error
 by the condition number of Q^2 + s, ~1e2 here)."""

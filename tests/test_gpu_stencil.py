@@ -18,6 +18,13 @@ pytestmark = pytest.mark.gpu
 
 RHO = 1.6
 M0 = -RHO
+# Relative L2 tolerances per storage precision.  FP64: rounding of ~100 flops
+# per output (1e-12 leaves three orders of margin).  FP32: 1e-6.  FP16S: every
+# stored spinor value carries a relative error up to 2^-11 = 4.9e-4 of its
+# site's largest component and every link entry up to 4.9e-4 (entries <= 1);
+# an output sums the diagonal term and 8 hops of comparable size, whose
+# independent errors add to about sqrt(9) * 2 * 4.9e-4 ~ 3e-3 in the worst
+# sites, so 5e-3 bounds the field-wide relative error.
 TOL = {0: 1e-12, 1: 1e-6, 2: 5e-3}
 
 

@@ -98,6 +98,14 @@ typedef struct {
                           x1 column (divides dims[0]); set by ovl_lattice_init,
                           may be changed by an autotuner; results do not
                           depend on it beyond summation order */
+    int32_t stream_t;  /* 0: one stencil thread per site, in tile_t order.
+                          s > 0: FP64 and FP32 stencils stream in time, each
+                          thread walking s consecutive time slices of one
+                          spatial site (needs s | dims[0], s <= 256 and
+                          dims[1]*dims[2]*dims[3] a multiple of 256); FP16
+                          stencils always use one thread per site.  Set by
+                          ovl_lattice_init; results do not depend on it
+                          beyond summation order */
 } ovl_lattice;
 
 /* A gauge field packed in up to three precisions (device pointers).  An

@@ -20,6 +20,7 @@ Lat make_lat(const ovl_lattice *lat)
     L.g.Vh = L.Vh;
     L.g.S = padded_stride(L.Vh);
     L.g.T = lat->tile_t;
+    L.g.Ts = lat->stream_t;
     L.nb = (L.Vh + kBlock - 1) / kBlock;
     return L;
 }

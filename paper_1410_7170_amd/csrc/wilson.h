@@ -39,7 +39,7 @@ struct WArgs {
     const double *alpha;    // W_RUPDATE: alpha per RHS (device)
     double *partials;       // [quantity][nrhs][nblk]
     const int *skip;        // per-RHS flag: block exits if skip[r] != 0 (may be null)
-    int nblk;
+    int nblk;               // partial-sum slots per RHS and quantity (2 * blocks per parity)
     int nrhs;
 };
 
@@ -148,6 +148,86 @@ __device__ __forceinline__ void hops_mu(const Geom &g, const SpinorRef<PREC> &in
     hop<T, MU, false>(acc, s, u, ph);
 }
 
+// Output of one site from v = (m0+4) d - acc/2 (the Wilson operator on the
+// site before Gamma_5) and |d|^2 of its centre d: applies Gamma_5, then the
+// mode's shift term, residual update or residual norm; stores the result and
+// adds the site's norms to q0, q1.
+template <int PREC, int MODE, bool G5>
+__device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, double shift_r,
+                                         cplx<typename Real<PREC>::T> o[4][3], typename Real<PREC>::T dn2,
+                                         double &q0, double &q1)
+{
+    using T = typename Real<PREC>::T;
+    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
+    const Geom &g = a.g;
+    if (G5) {
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) o[s][c] = {-o[s][c].x, -o[s][c].y};
+    }
+    if (MODE == W_NORM) {
+        T n0 = 0;
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) n0 += norm2(o[s][c]);
+        q0 += (double)n0;
+        q1 += (double)dn2;
+    }
+    if (kShift) {
+        const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, r);
+        cplx<T> pv[4][3];
+        pf.load(p, i, pv);
+        const T sh = (T)shift_r;
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) o[s][c] = {fma(sh, pv[s][c].x, o[s][c].x), fma(sh, pv[s][c].y, o[s][c].y)};
+    }
+    if (MODE == W_RUPDATE) {
+        cplx<T> rv[4][3];
+        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load(p, i, rv);
+        const T al = (T)a.alpha[r];
+        T n0 = 0;
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                rv[s][c] = {fma(-al, o[s][c].x, rv[s][c].x), fma(-al, o[s][c].y, rv[s][c].y)};
+                n0 += norm2(rv[s][c]);
+            }
+        spinor_ref<PREC>(a.out, a.out_sc, g.S, r).store_nt(p, i, rv);
+        q0 += (double)n0;
+    } else if (MODE == W_RESNORM) {
+        cplx<T> rv[4][3];
+        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load(p, i, rv);
+        T n0 = 0;
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) n0 += norm2(rv[s][c] - o[s][c]);
+        q0 += (double)n0;
+    } else {
+        spinor_ref<PREC>(a.out, a.out_sc, g.S, r).store_nt(p, i, o);
+    }
+}
+
+// v = (m0+4) d - acc/2 in place of acc; returns |d|^2
+template <typename T>
+__device__ __forceinline__ T diag_minus_half(cplx<T> acc[4][3], const cplx<T> d[4][3], T diag)
+{
+    T dn2 = 0;
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[s][c] = {fma(diag, d[s][c].x, (T)-0.5 * acc[s][c].x), fma(diag, d[s][c].y, (T)-0.5 * acc[s][c].y)};
+            dn2 += norm2(d[s][c]);
+        }
+    return dn2;
+}
+
 template <int PREC, int MODE, bool G5>
 __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
 {
@@ -186,62 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         hops_mu<PREC, 3>(g, in, U, p, i, x, acc);
         cplx<T> d[4][3];
         in.load(p, i, d);
-        const T diag = (T)a.diag;
-        cplx<T> o[4][3];
-#pragma unroll
-        for (int s = 0; s < 4; s++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                cplx<T> v = {fma(diag, d[s][c].x, (T)-0.5 * acc[s][c].x), fma(diag, d[s][c].y, (T)-0.5 * acc[s][c].y)};
-                if (G5 && s < 2) v = {-v.x, -v.y};
-                o[s][c] = v;
-            }
-        if (MODE == W_NORM) {
-            T n0 = 0, n1 = 0;
-#pragma unroll
-            for (int s = 0; s < 4; s++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) { n0 += norm2(o[s][c]); n1 += norm2(d[s][c]); }
-            q0 = (double)n0;
-            q1 = (double)n1;
-        }
-        if (kShift) {
-            const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, r);
-            cplx<T> pv[4][3];
-            pf.load(p, i, pv);
-            const T sh = (T)shift_r;
-#pragma unroll
-            for (int s = 0; s < 4; s++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) o[s][c] = {fma(sh, pv[s][c].x, o[s][c].x), fma(sh, pv[s][c].y, o[s][c].y)};
-        }
-        const SpinorRef<PREC> out = spinor_ref<PREC>(a.out, a.out_sc, g.S, r);
-        if (MODE == W_RUPDATE) {
-            cplx<T> rv[4][3];
-            spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load(p, i, rv);
-            const T al = (T)a.alpha[r];
-            T n0 = 0;
-#pragma unroll
-            for (int s = 0; s < 4; s++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    rv[s][c] = {fma(-al, o[s][c].x, rv[s][c].x), fma(-al, o[s][c].y, rv[s][c].y)};
-                    n0 += norm2(rv[s][c]);
-                }
-            out.store_nt(p, i, rv);
-            q0 = (double)n0;
-        } else if (MODE == W_RESNORM) {
-            cplx<T> rv[4][3];
-            spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load(p, i, rv);
-            T n0 = 0;
-#pragma unroll
-            for (int s = 0; s < 4; s++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) n0 += norm2(rv[s][c] - o[s][c]);
-            q0 = (double)n0;
-        } else {
-            out.store_nt(p, i, o);
-        }
+        const T dn2 = diag_minus_half(acc, d, (T)a.diag);
+        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, acc, dn2, q0, q1);
     }
     if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
         double t0 = block_sum(q0, lds);
@@ -249,6 +275,132 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         if (MODE == W_NORM) {
             double t1 = block_sum(q1, lds + 4);
             if (threadIdx.x == 0) a.partials[(size_t)(a.nrhs + r) * nb + lb] = t1;
+        }
+    }
+}
+
+// Backward time hop split in two: w = U_0(x-0)^H (1 + gamma_0) psi(x-0) on the
+// two independent spins, and its reconstruction into the four spins of acc.
+template <typename T>
+__device__ __forceinline__ void tback_half(cplx<T> w[2][3], const cplx<T> s[4][3], const cplx<T> u[3][3])
+{
+    cplx<T> h[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        h[0][c] = s[0][c] + s[2][c];
+        h[1][c] = s[1][c] + s[3][c];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) w[a][c] = cmc(u[0][c], h[a][0]) + cmc(u[1][c], h[a][1]) + cmc(u[2][c], h[a][2]);
+}
+
+template <typename T>
+__device__ __forceinline__ void tback_add(cplx<T> acc[4][3], const cplx<T> w[2][3], T ph)
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc[0][c] = acc[0][c] + ph * w[0][c];
+        acc[1][c] = acc[1][c] + ph * w[1][c];
+        acc[2][c] = acc[2][c] + ph * w[0][c];
+        acc[3][c] = acc[3][c] + ph * w[1][c];
+    }
+}
+
+// Time-streaming form of the stencil.  A thread owns one spatial site
+// (x1, x2, x3) and walks g.Ts consecutive time slices; block lb covers the
+// 256 consecutive spatial sites of spatial block lb % nsb (x3 fastest, so a
+// wave reads whole x3 rows of both parities) in time chunk lb / nsb.  The
+// time hops need no neighbour loads after the first slice: psi(t+1), loaded
+// for the forward hop, is the centre of the next slice, and the backward
+// hop's U_0(t)^H (1 + gamma_0) psi(t) is formed while slice t holds U_0(t)
+// and psi(t) in registers.  Requires L1*L2*L3 % 256 == 0 and Ts | L0.
+// Partial sums: slot lb holds the block's sum, the slots lb + m*nblk_ts
+// (m = 1 .. Ts-1) are zeroed, so a.nblk = 2*nb slots per RHS stay valid.
+template <int PREC, int MODE, bool G5>
+__global__ __launch_bounds__(kBlock, 2) void k_wilson_ts(WArgs a)
+{
+    using T = typename Real<PREC>::T;
+    __shared__ double lds[8];
+    const Geom &g = a.g;
+    const int lbr = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = lbr % a.nrhs;
+    const int lb = lbr / a.nrhs;
+    const int nbt = gridDim.x / a.nrhs;   // blocks per RHS
+    if (a.skip && a.skip[r]) return;
+    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
+    const double shift_r = kShift ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
+    const int nsb = L1 * L2 * L3 / kBlock;
+    const int sb = lb % nsb, tc = lb / nsb;
+    const int sidx = sb * kBlock + threadIdx.x;
+    int x[4];
+    x[3] = sidx % L3;
+    x[2] = (sidx / L3) % L2;
+    x[1] = sidx / (L3 * L2);
+    const int t0 = tc * g.Ts;
+    const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.S, r);
+    const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.S};
+    const int sp = x[1] + x[2] + x[3];   // parity of the spatial part
+    cplx<T> cen[4][3], w[2][3];   // centre of the current slice, backward-hop carry
+    {
+        // centre of the first slice and the backward-hop carry from t0 - 1
+        x[0] = t0;
+        in.load((t0 + sp) & 1, cb_index(g, x), cen);
+        int y[4] = {t0 == 0 ? L0 - 1 : t0 - 1, x[1], x[2], x[3]};
+        const int py = (y[0] + sp) & 1, iy = cb_index(g, y);
+        cplx<T> sv[4][3], u[3][3];
+        in.load(py, iy, sv);
+        U.load(py, 0, iy, u);
+        tback_half(w, sv, u);
+    }
+    double q0 = 0.0, q1 = 0.0;
+    for (int k = 0; k < g.Ts; k++) {
+        const int t = t0 + k;
+        x[0] = t;
+        const int p = (t + sp) & 1;
+        const int i = cb_index(g, x);
+        cplx<T> acc[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[s][c] = {(T)0, (T)0};
+        tback_add(acc, w, t == 0 ? (T)g.bc[0] : (T)1);
+        hops_mu<PREC, 1>(g, in, U, p, i, x, acc);
+        hops_mu<PREC, 2>(g, in, U, p, i, x, acc);
+        hops_mu<PREC, 3>(g, in, U, p, i, x, acc);
+        // U_0(t): the next slice's carry from this centre, then the centre's
+        // diagonal term; the centre is then dead before psi(t+1) arrives
+        cplx<T> u[3][3];
+        U.load(p, 0, i, u);
+        tback_half(w, cen, u);
+        const T dn2 = diag_minus_half(acc, cen, (T)a.diag);
+        {
+            // forward time hop, subtracted with its factor -1/2 straight into v
+            int y[4] = {t + 1 == L0 ? 0 : t + 1, x[1], x[2], x[3]};
+            in.load(1 - p, cb_index(g, y), cen);
+            cplx<T> f[4][3];
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) f[s][c] = {(T)0, (T)0};
+            hop<T, 0, true>(f, cen, u, t + 1 == L0 ? (T)(-0.5 * g.bc[0]) : (T)-0.5);
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) acc[s][c] = acc[s][c] + f[s][c];
+        }
+        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, acc, dn2, q0, q1);
+    }
+    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
+        const int nq = MODE == W_NORM ? 2 : 1;
+        double t0s = block_sum(q0, lds);
+        double t1s = MODE == W_NORM ? block_sum(q1, lds + 4) : 0.0;
+        if (threadIdx.x < g.Ts) {
+            const size_t slot = (size_t)lb + (size_t)threadIdx.x * nbt;
+            a.partials[(size_t)r * a.nblk + slot] = threadIdx.x == 0 ? t0s : 0.0;
+            if (nq == 2) a.partials[(size_t)(a.nrhs + r) * a.nblk + slot] = threadIdx.x == 0 ? t1s : 0.0;
         }
     }
 }

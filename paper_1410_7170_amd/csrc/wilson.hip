@@ -6,6 +6,22 @@
 namespace ovl {
 
 template <int PREC>
+static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
+{
+    if (g5) {
+        switch (mode) {
+        case W_PLAIN: k_wilson_ts<PREC, W_PLAIN, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_NORM: k_wilson_ts<PREC, W_NORM, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true><<<grid, kBlock, 0, st>>>(a); break;
+        default: k_wilson_ts<PREC, W_RESNORM, true><<<grid, kBlock, 0, st>>>(a); break;
+        }
+    } else {
+        k_wilson_ts<PREC, W_PLAIN, false><<<grid, kBlock, 0, st>>>(a);
+    }
+}
+
+template <int PREC>
 static void wilson_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
 {
     if (g5) {
@@ -25,6 +41,15 @@ hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hip
 {
     a.g = L.g;
     a.nblk = 2 * L.nb;
+    if (L.g.Ts > 0 && prec != P_F16S) {
+        // time-streaming form (FP64, FP32): V / (256 Ts) blocks per RHS; the
+        // FP16 stencil keeps one site per thread, which measured faster
+        dim3 grid((unsigned)(L.V / ((int64_t)kBlock * L.g.Ts)) * a.nrhs);
+        if (prec == P_F64) wilson_ts_dispatch<P_F64>(mode, g5, grid, a, st);
+        else if (prec == P_F32) wilson_ts_dispatch<P_F32>(mode, g5, grid, a, st);
+        else wilson_ts_dispatch<P_F16S>(mode, g5, grid, a, st);
+        return hipGetLastError();
+    }
     dim3 grid(2 * L.nb * a.nrhs);
     if (prec == P_F64) wilson_dispatch<P_F64>(mode, g5, grid, a, st);
     else if (prec == P_F32) wilson_dispatch<P_F32>(mode, g5, grid, a, st);

@@ -206,3 +206,62 @@ def test_wilson_apply_32x64_full(ovl):
     olat = oracle.Lattice(dims)
     ref = oracle.dw(olat, U, M0, psi)
     assert rel(got, ref) < 1e-12
+
+
+# time-streaming form: lattices whose spatial volume is a multiple of 256
+STREAM_CASES = [((4, 4, 8, 8), 1), ((4, 4, 8, 8), 2), ((4, 4, 8, 8), 4), ((6, 4, 8, 8), 3),
+                ((8, 8, 8, 4), 8), ((16, 8, 8, 8), 4), ((2, 8, 4, 8), 2)]
+
+
+@pytest.mark.parametrize("dims,ts", STREAM_CASES)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_wilson_stream_matches_oracle(ovl, dims, ts, prec):
+    note(f"wilson_apply streaming prec={prec} dims={dims} stream_t={ts}")
+    lat, olat, U, G = setup(ovl, dims, seed=17)
+    lat.stream_t = ts
+    psi = synth.gaussian_spinor(lat.V, 18, 2)
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+    out = ovl.Spinor(lat, prec, 2)
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    got = out.to_canonical().cpu().numpy()
+    for r in range(2):
+        ref = oracle.dw(olat, U, M0, psi[r])
+        assert rel(got[r], ref) < TOL[prec], (dims, ts, prec, r, rel(got[r], ref))
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1), (-1, -1, 1, -1)])
+@pytest.mark.parametrize("ts", [1, 2, 4])
+def test_stream_boundary_phases_and_q2(ovl, bc, ts):
+    dims = (4, 4, 8, 8)
+    note(f"streaming boundary phases bc={bc} stream_t={ts}")
+    lat, olat, U, G = setup(ovl, dims, seed=19, bc=bc, n_stout=1)
+    lat.stream_t = ts
+    psi = synth.gaussian_spinor(lat.V, 20)[0]
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), 0)
+    out = ovl.Spinor(lat, 0)
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    assert rel(out.to_canonical().cpu().numpy()[0], oracle.dw(olat, U, M0, psi)) < 1e-13
+    ovl.q_apply(lat, G, M0, inp, out)
+    assert rel(out.to_canonical().cpu().numpy()[0], oracle.q(olat, U, M0, psi)) < 1e-13
+    ovl.q2_apply(lat, G, M0, 0.37, inp, out)
+    assert rel(out.to_canonical().cpu().numpy()[0], oracle.q2(olat, U, M0, psi, 0.37)) < 1e-13
+
+
+@pytest.mark.parametrize("cfg,ts", [(1, 4), (2, 8), (2, 16)])
+def test_wilson_stream_full_workloads(ovl, cfg, ts):
+    """Every site of the 16^3x32 and 32^3x64 fields in the streaming form, all
+    three precisions against the oracle."""
+    dims = synth.CONFIGS[cfg]["dims"]
+    note(f"wilson_apply streaming full {dims} stream_t={ts}")
+    lat = ovl.Lattice(dims)
+    lat.stream_t = ts
+    olat = oracle.Lattice(dims)
+    U = synth.config_gauge(cfg)
+    G = ovl.Gauge(lat, dev(U))
+    psi = synth.config_sources(cfg)[0]
+    ref = oracle.dw(olat, U, M0, psi)
+    for prec in (0, 1, 2):
+        inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+        out = ovl.Spinor(lat, prec)
+        ovl.wilson_apply(lat, G, M0, inp, out)
+        assert rel(out.to_canonical().cpu().numpy()[0], ref) < TOL[prec], prec

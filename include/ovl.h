@@ -106,6 +106,9 @@ typedef struct {
                           stencils always use one thread per site.  Set by
                           ovl_lattice_init; results do not depend on it
                           beyond summation order */
+    int32_t stream_t64;/* time slices per thread of the FP64 stencil in the
+                          streaming form (same conditions as stream_t);
+                          0: FP64 follows stream_t.  Set by ovl_lattice_init */
 } ovl_lattice;
 
 /* A gauge field packed in up to three precisions (device pointers).  An

@@ -40,7 +40,8 @@ c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, cty
 
 
 class ovl_lattice(ctypes.Structure):
-    _fields_ = [("dims", c_i32 * 4), ("bc", c_i32 * 4), ("vol", c_i64), ("tile_t", c_i32), ("stream_t", c_i32)]
+    _fields_ = [("dims", c_i32 * 4), ("bc", c_i32 * 4), ("vol", c_i64), ("tile_t", c_i32), ("stream_t", c_i32),
+                ("stream_t64", c_i32)]
 
 
 class ovl_gauge(ctypes.Structure):
@@ -176,6 +177,16 @@ class Lattice:
         if s and (s < 0 or s > 256 or self.dims[0] % s or (self.dims[1] * self.dims[2] * self.dims[3]) % 256):
             raise ValueError(f"stream_t={s} needs s | L0 and L1*L2*L3 % 256 == 0")
         self.c.stream_t = int(s)
+
+    @property
+    def stream_t64(self) -> int:
+        return int(self.c.stream_t64)
+
+    @stream_t64.setter
+    def stream_t64(self, s: int):
+        if s and (s < 0 or s > 256 or self.dims[0] % s or (self.dims[1] * self.dims[2] * self.dims[3]) % 256):
+            raise ValueError(f"stream_t64={s} needs s | L0 and L1*L2*L3 % 256 == 0")
+        self.c.stream_t64 = int(s)
 
     @property
     def ref(self):

@@ -42,6 +42,10 @@ bool lat_ok(const ovl_lattice *lat)
     if (lat->stream_t > 0 && (lat->dims[0] % lat->stream_t ||
                               ((int64_t)lat->dims[1] * lat->dims[2] * lat->dims[3]) % 256))
         return false;
+    if (lat->stream_t64 < 0 || lat->stream_t64 > 256) return false;
+    if (lat->stream_t64 > 0 && (lat->dims[0] % lat->stream_t64 ||
+                                ((int64_t)lat->dims[1] * lat->dims[2] * lat->dims[3]) % 256))
+        return false;
     return V < ((int64_t)1 << 31) && lat->vol == V;
 }
 
@@ -113,18 +117,27 @@ int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4
     // default time tile: 4 slices when L0 allows it (measured best for the
     // FP64 and FP32 stencils at 32^3x64 on MI355X; 2 or 1 otherwise)
     lat->tile_t = (dims[0] % 4 == 0) ? 4 : (dims[0] % 2 == 0) ? 2 : 1;
-    // time-streaming stencil: the longest of 16, 8, 4, 2 slices per thread
-    // that divides L0 and still launches >= 512 blocks (measured on MI355X at
-    // 32^3x64: 16 slices cut the FP64 stencil's L2-miss traffic from 2.7x to
-    // 1.9x of its compulsory reads and the FP32 one's from 2.4x to 1.1x)
+    // time-streaming stencil: FP32 takes the longest of 16, 8, 4, 2 slices per
+    // thread that divides L0 and still launches >= 512 blocks, FP64 also 32
+    // slices when that leaves >= 256 blocks (measured on MI355X at
+    // 32^3x64: L2-miss traffic of the FP64 stencil falls from 2.7x to 1.2x of
+    // its compulsory reads at 32 slices, of the FP32 one from 2.4x to 1.1x at
+    // 16; beyond that too few blocks are left to hide memory latency)
     lat->stream_t = 0;
+    lat->stream_t64 = 0;
     const int64_t V3 = (int64_t)dims[1] * dims[2] * dims[3];
-    if (V3 % 256 == 0)
+    if (V3 % 256 == 0) {
         for (int s : {16, 8, 4, 2})
             if (dims[0] % s == 0 && V / (256 * (int64_t)s) >= 512) {
                 lat->stream_t = s;
                 break;
             }
+        for (int s : {32, 16, 8, 4, 2})
+            if (dims[0] % s == 0 && V / (256 * (int64_t)s) >= (s >= 32 ? 256 : 512)) {
+                lat->stream_t64 = s;
+                break;
+            }
+    }
     return OVL_OK;
 }
 

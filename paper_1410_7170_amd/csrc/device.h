@@ -59,6 +59,7 @@ struct Geom {
                    // components to the same L2 set and HBM channel)
     int T;         // time-tile length of the stencil's site order (divides L0)
     int Ts;        // time slices per thread of the time-streaming stencil (0: not used)
+    int Ts64;      // time slices per thread of the FP64 streaming stencil (0: Ts)
 };
 
 __host__ __device__ inline int padded_stride(int Vh) { return ((Vh + 15) / 16) * 16 + 24; }

@@ -21,6 +21,7 @@ Lat make_lat(const ovl_lattice *lat)
     L.g.S = padded_stride(L.Vh);
     L.g.T = lat->tile_t;
     L.g.Ts = lat->stream_t;
+    L.g.Ts64 = lat->stream_t64;
     L.nb = (L.Vh + kBlock - 1) / kBlock;
     return L;
 }

@@ -309,15 +309,16 @@ __device__ __forceinline__ void tback_add(cplx<T> acc[4][3], const cplx<T> w[2][
 }
 
 // Time-streaming form of the stencil.  A thread owns one spatial site
-// (x1, x2, x3) and walks g.Ts consecutive time slices; block lb covers the
+// (x1, x2, x3) and walks Ts consecutive time slices (g.Ts64 for FP64 when
+// set, else g.Ts); block lb covers the
 // 256 consecutive spatial sites of spatial block lb % nsb (x3 fastest, so a
 // wave reads whole x3 rows of both parities) in time chunk lb / nsb.  The
 // time hops need no neighbour loads after the first slice: psi(t+1), loaded
 // for the forward hop, is the centre of the next slice, and the backward
 // hop's U_0(t)^H (1 + gamma_0) psi(t) is formed while slice t holds U_0(t)
 // and psi(t) in registers.  Requires L1*L2*L3 % 256 == 0 and Ts | L0.
-// Partial sums: slot lb holds the block's sum, the slots lb + m*nblk_ts
-// (m = 1 .. Ts-1) are zeroed, so a.nblk = 2*nb slots per RHS stay valid.
+// Partial sums: slot lb holds the block's sum and the block zeroes the slots
+// lb + m*nblk_ts (m >= 1) below a.nblk, so all 2*nb slots per RHS are valid.
 template <int PREC, int MODE, bool G5>
 __global__ __launch_bounds__(kBlock, 2) void k_wilson_ts(WArgs a)
 {
@@ -339,7 +340,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_wilson_ts(WArgs a)
     x[3] = sidx % L3;
     x[2] = (sidx / L3) % L2;
     x[1] = sidx / (L3 * L2);
-    const int t0 = tc * g.Ts;
+    const int Ts = PREC == P_F64 && g.Ts64 > 0 ? g.Ts64 : g.Ts;
+    const int t0 = tc * Ts;
     const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.S, r);
     const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.S};
     const int sp = x[1] + x[2] + x[3];   // parity of the spatial part
@@ -356,7 +358,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_wilson_ts(WArgs a)
         tback_half(w, sv, u);
     }
     double q0 = 0.0, q1 = 0.0;
-    for (int k = 0; k < g.Ts; k++) {
+    for (int k = 0; k < Ts; k++) {
         const int t = t0 + k;
         x[0] = t;
         const int p = (t + sp) & 1;
@@ -397,10 +399,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_wilson_ts(WArgs a)
         const int nq = MODE == W_NORM ? 2 : 1;
         double t0s = block_sum(q0, lds);
         double t1s = MODE == W_NORM ? block_sum(q1, lds + 4) : 0.0;
-        if (threadIdx.x < g.Ts) {
-            const size_t slot = (size_t)lb + (size_t)threadIdx.x * nbt;
-            a.partials[(size_t)r * a.nblk + slot] = threadIdx.x == 0 ? t0s : 0.0;
-            if (nq == 2) a.partials[(size_t)(a.nrhs + r) * a.nblk + slot] = threadIdx.x == 0 ? t1s : 0.0;
+        for (int m = threadIdx.x; lb + (size_t)m * nbt < (size_t)a.nblk; m += kBlock) {
+            const size_t slot = (size_t)lb + (size_t)m * nbt;
+            a.partials[(size_t)r * a.nblk + slot] = m == 0 ? t0s : 0.0;
+            if (nq == 2) a.partials[(size_t)(a.nrhs + r) * a.nblk + slot] = m == 0 ? t1s : 0.0;
         }
     }
 }

@@ -41,10 +41,11 @@ hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hip
 {
     a.g = L.g;
     a.nblk = 2 * L.nb;
-    if (L.g.Ts > 0 && prec != P_F16S) {
+    const int ts = prec == P_F64 && L.g.Ts64 > 0 ? L.g.Ts64 : L.g.Ts;
+    if (ts > 0 && prec != P_F16S) {
         // time-streaming form (FP64, FP32): V / (256 Ts) blocks per RHS; the
         // FP16 stencil keeps one site per thread, which measured faster
-        dim3 grid((unsigned)(L.V / ((int64_t)kBlock * L.g.Ts)) * a.nrhs);
+        dim3 grid((unsigned)(L.V / ((int64_t)kBlock * ts)) * a.nrhs);
         if (prec == P_F64) wilson_ts_dispatch<P_F64>(mode, g5, grid, a, st);
         else if (prec == P_F32) wilson_ts_dispatch<P_F32>(mode, g5, grid, a, st);
         else wilson_ts_dispatch<P_F16S>(mode, g5, grid, a, st);

@@ -225,15 +225,16 @@ def test_nonfinite_input_reported(ovl):
     assert e.value.status == ovl.ERR_NONFINITE
 
 
-@pytest.mark.parametrize("block,ts", [(0, 2), (8, 4), (16, 8)])
-def test_solvers_with_streaming_stencil(ovl, block, ts):
+@pytest.mark.parametrize("block,ts,ts64", [(0, 2, 0), (8, 4, 0), (16, 8, 0), (0, 2, 4), (16, 4, 8)])
+def test_solvers_with_streaming_stencil(ovl, block, ts, ts64):
     """Multishift CG and the overlap apply with the time-streaming stencil: its
     partial sums (fewer blocks than slots) feed the same reductions."""
     dims = (8, 8, 8, 8)
-    note(f"solvers with streaming stencil block={block} stream_t={ts}")
+    note(f"solvers with streaming stencil block={block} stream_t={ts} stream_t64={ts64}")
     U = synth.gauge(dims, 0.3, 61, n_stout=2)
     lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
     lat.stream_t = ts
+    lat.stream_t64 = ts64
     b = synth.gaussian_spinor(lat.V, 62, 2)
     x_ref, it_ref, _ = oracle.mscg(olat, U, M0, s, b[0], 1e-12, 3000)
     B = ovl.Spinor.from_canonical(lat, dev(b[:1]), 0)

@@ -265,3 +265,19 @@ def test_wilson_stream_full_workloads(ovl, cfg, ts):
         out = ovl.Spinor(lat, prec)
         ovl.wilson_apply(lat, G, M0, inp, out)
         assert rel(out.to_canonical().cpu().numpy()[0], ref) < TOL[prec], prec
+
+
+@pytest.mark.parametrize("dims,ts,ts64", [((4, 4, 8, 8), 2, 4), ((8, 8, 8, 4), 4, 8), ((16, 8, 8, 8), 8, 16)])
+def test_stream_t64_selects_fp64_length(ovl, dims, ts, ts64):
+    """FP64 follows stream_t64 and FP32 stream_t when both are set."""
+    note(f"stream_t64 dims={dims} stream_t={ts} stream_t64={ts64}")
+    lat, olat, U, G = setup(ovl, dims, seed=27, n_stout=1)
+    lat.stream_t = ts
+    lat.stream_t64 = ts64
+    psi = synth.gaussian_spinor(lat.V, 28)[0]
+    ref = oracle.dw(olat, U, M0, psi)
+    for prec in (0, 1):
+        inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+        out = ovl.Spinor(lat, prec)
+        ovl.wilson_apply(lat, G, M0, inp, out)
+        assert rel(out.to_canonical().cpu().numpy()[0], ref) < TOL[prec], prec

@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--forms", default="fp64,fp64_blocked",
                     help="comma-separated forms timed once each besides the timed form")
+    ap.add_argument("--multi-rhs", type=int, default=3,
+                    help="workload recipe of the batched multi-RHS line (3 = 24^3x48, 12 point "
+                         "sources); -1 skips it")
+    ap.add_argument("--multi-rhs-steps", type=int, default=2)
     return ap.parse_args()
 
 
@@ -193,7 +197,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
-    applies_per_s = B.nrhs * args.steps / elapsed
+    applies_per_s = len(b) * args.steps / elapsed
 
     got = out.to_canonical().cpu().numpy()
     timed_diff = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
@@ -214,15 +218,24 @@ def main():
                     algorithmic_bytes_per_launch=round(bytes_per_launch),
                     share_of_step=round(ksec[dom] / (elapsed), 3), source=src)
 
+    # ---- batched multi-RHS workload (its own lattice, after the timed region)
+    mrhs = None
+    if args.multi_rhs >= 0:
+        del G, B, out
+        torch.cuda.empty_cache()
+        mrhs = multi_rhs_line(args, ovl, synth, np, torch)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, dims, U, b[0], shifts, weights, results["fp64"]["shift_iters"])
 
-    fp64_rate = B.nrhs / results["fp64"]["seconds"]
-    # one unpack of a packed FP64 field: a plain streaming kernel of known size
-    # (reads ovl_spinor_bytes, writes V*192 bytes) for counter calibration
-    ovl.unpack_spinor(lat, B, torch.empty((1, V, 4, 3), dtype=torch.complex128, device="cuda"))
+    nrhs = len(b)
+    fp64_rate = nrhs / results["fp64"]["seconds"]
+    # one unpack and one pack of a packed FP64 field: plain streaming kernels
+    # of known size for counter calibration
+    Bc = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), ovl.F64)
+    ovl.unpack_spinor(lat, Bc, torch.empty((1, V, 4, 3), dtype=torch.complex128, device="cuda"))
     torch.cuda.synchronize()
     line = {
         "metric": "Wilson stencil HBM GB/s + D_ov applies/sec @32^3x64, mixed vs FP64, 1e-10 res",
@@ -239,25 +252,81 @@ def main():
         "data": "synthetic (seeded SU(3) links exp(i 0.3 H), 2 stout steps; Gaussian source)",
         "config": {"workload": f"overlap apply {dims[1]}^3x{dims[0]}, {npoles} Zolotarev poles, "
                                f"tol {args.tol:g}, rho {RHO}",
-                   "lattice": list(dims), "nrhs": B.nrhs, "poles": npoles, "form": timed_form,
+                   "lattice": list(dims), "nrhs": nrhs, "poles": npoles, "form": timed_form,
                    "spectral_interval": [lo, hi], "zolotarev_delta": delta},
         "stencil": stencil,
-        "forms": {k: dict(applies_per_s=round(B.nrhs / v["seconds"], 4), iterations=v["iterations"],
+        "forms": {k: dict(applies_per_s=round(nrhs / v["seconds"], 4), iterations=v["iterations"],
                           rel_diff_vs_fp64=v["rel_diff_vs_fp64"], reliable_updates=v["reliable_updates"],
                           refine_iterations=v["refine_iterations"], max_true_residual=v["max_true_residual"])
                   for k, v in results.items()},
         "timed_rel_diff_vs_fp64": timed_diff,
         "fp64_applies_per_s": round(fp64_rate, 4),
         "speedup_vs_fp64": round(applies_per_s / fp64_rate, 3),
-        "speedup_vs_fp64_blocked": (round(applies_per_s * results["fp64_blocked"]["seconds"] / B.nrhs, 3)
+        "speedup_vs_fp64_blocked": (round(applies_per_s * results["fp64_blocked"]["seconds"] / nrhs, 3)
                                     if "fp64_blocked" in results else None),
         "iterations": last["iterations"],
-        "timed_max_true_residual": max(max(r) for r in last["true_residual"][:B.nrhs]),
+        "timed_max_true_residual": max(max(r) for r in last["true_residual"][:nrhs]),
         "timed_refine_iterations": last["refine_iterations"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "multi_rhs": mrhs,
     }
     print(json.dumps(line))
+
+
+def multi_rhs_line(args, ovl, synth, np, torch):
+    """The batched multi-RHS workload: the 12 spin-colour point sources of one
+    seeded site on 24^3x48 (20 poles), solved together in one mixed overlap
+    apply (one link load serves all 12 RHS in every stencil), against the
+    plain FP64 single-RHS form on the first of them."""
+    cfg = args.multi_rhs
+    c = synth.CONFIGS[cfg]
+    dims = c["dims"]
+    lat = ovl.Lattice(dims)
+    U = synth.config_gauge(cfg)
+    G = ovl.Gauge(lat, torch.from_numpy(U).cuda())
+    del U
+    v0 = synth.gaussian_spinor(lat.V, synth.SEED_BASE + 10 * cfg + 3)[0]
+    lo, hi = ovl.spectral_bounds(lat, G, -RHO, 300, ovl.Spinor.from_canonical(lat, torch.from_numpy(v0).cuda(),
+                                                                                ovl.F64))
+    shifts, weights, delta = ovl.zolotarev(lo, hi, c["poles"])
+    b = synth.config_sources(cfg)
+    B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
+    out = ovl.Spinor(lat, ovl.F64, B.nrhs)
+    prm = ovl.default_params(tol=args.tol, maxiter=5000, block=16, mode=ovl.SOLVE_MIXED)
+    ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.multi_rhs_steps):
+        st = ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rate = B.nrhs * args.multi_rhs_steps / el
+    # plain FP64, one RHS at a time
+    B1 = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), ovl.F64)
+    out1 = ovl.Spinor(lat, ovl.F64)
+    p64 = ovl.default_params(tol=args.tol, maxiter=5000)
+    ovl.overlap_apply(lat, G, RHO, shifts, weights, B1, out1, p64)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st64 = ovl.overlap_apply(lat, G, RHO, shifts, weights, B1, out1, p64)
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t1
+    got = out.to_canonical().cpu().numpy()[0]
+    ref = out1.to_canonical().cpu().numpy()[0]
+    line = dict(workload=f"overlap apply {dims[1]}^3x{dims[0]}, 12 spin-colour point sources at one site, "
+                         f"{c['poles']} Zolotarev poles, tol {args.tol:g}",
+                nrhs=B.nrhs, form="mixed (FP64 until 1e-5, FP32 bulk, FP64 verification)",
+                applies_per_s=round(rate, 4), seconds_per_batch=round(el / args.multi_rhs_steps, 4),
+                fp64_single_rhs_applies_per_s=round(1.0 / el64, 4),
+                speedup_vs_fp64_single_rhs=round(rate * el64, 3),
+                iterations=st["iterations"], max_true_residual=max(max(r) for r in st["true_residual"]),
+                refine_iterations=st["refine_iterations"],
+                rel_diff_rhs0_vs_fp64=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                stream_t=lat.stream_t, stream_t64=lat.stream_t64)
+    print(f"[bench] multi-rhs {dims}: {rate:.3f} RHS-applies/s, FP64 single {1.0/el64:.3f}/s, "
+          f"max residual {line['max_true_residual']:.2e}", file=sys.stderr, flush=True)
+    return line
 
 
 def cpu_baseline(args, dims, U, b, shifts, weights, shift_iters):

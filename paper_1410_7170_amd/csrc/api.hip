@@ -15,7 +15,8 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
              MsScratch *scr);
 int true_residuals_f64(const Lat &L, const void *U64, double m0, double s, Fld b, Fld x, Fld q, Fld t,
                        double *partials, double *red, double *out, hipStream_t st);
-hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st);
+hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st,
+                          bool accumulate = false);
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
 size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase);

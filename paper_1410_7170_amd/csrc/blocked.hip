@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const 
             if (zn * zn * rr_new <= thr) {
                 st->act[r][j] = 0;
                 st->frozen_at[r][j] = it;
+                st->frozen_rr[r][j] = zn * zn * rr_new;
             } else {
                 left++;
             }

@@ -1,22 +1,28 @@
-// Mixed-precision multishift CG for (Q^2 + s_j) x_j = b.
+// Mixed-precision multishift CG for (Q^2 + s_j) x_j = b, combined into
+// y = sum_j w_j x_j.
 //
 // 0. FP64 phase (when sloppy_below > 0): the blocked multishift CG in FP64,
-//    with FP64 x_j, until the base residual |r|/|b| falls below sloppy_below.
-//    The rounding errors of a sloppy phase enter every shifted residual in
-//    proportion to the size of the residuals at the time they are made, so
-//    starting it only here keeps them of order eps_32 * sloppy_below.
-// 1. Sloppy phase: the same recurrences continue with FP32 links, stencil
-//    and Krylov vectors (ring, p0, t, p_j); the solutions x_j accumulate in
-//    FP64; the base residual is replaced by the FP64 true residual
-//    b - (Q^2 + s0) x_0 whenever |r| has dropped by reliable_delta since the
-//    last replacement.
-// 2. Verification: every shifted system's FP64 true residual
-//    |b - (Q^2 + s_j) x_j| / |b|.
+//    accumulating y directly, until the base residual |r|/|b| falls below
+//    sloppy_below.  The rounding errors of a sloppy phase enter every shifted
+//    residual in proportion to the size of the residuals at the time they are
+//    made, so starting it only here keeps them of order eps_32 * sloppy_below.
+// 1. Sloppy phase: the same recurrences continue with FP32 links, stencil and
+//    Krylov vectors (ring, p0, t, p_j); the increments dx_j of the solutions
+//    accumulate in FP64.  At the hand-over the residual of shift j is
+//    zeta_j r0 (r0 the FP64 base residual then, exact up to FP64 rounding),
+//    so the true residual of x_j is zeta_j r0 - (Q^2 + s_j) dx_j; for the base
+//    shift (zeta = 1) it replaces the recursive residual whenever |r| has
+//    dropped by reliable_delta since the last replacement.
+// 2. Verification: every shifted system's FP64 true relative residual.  A
+//    shift frozen in the FP64 phase has no sloppy part; its residual is the
+//    FP64 recursive one at the iteration it froze.
 // 3. Refinement: each system above tol solves (Q^2 + s_j) e = r_j with the
 //    FP32 solver (batched over systems, one shift per batch entry) to the
-//    relative accuracy that brings it below tol, and x_j += e in FP64;
+//    relative accuracy that brings it below tol, and dx_j += e in FP64;
 //    repeated (at most 3 rounds) until every system verifies.
-// The caller then forms y = sum_j w_j x_j in FP64.
+// Finally y += sum_j w_j dx_j in FP64.
+// Without an FP64 phase (sloppy_below = 0) the sloppy phase starts from
+// x_j = 0 with r0 = b and zeta_j = 1.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -25,33 +31,36 @@
 
 namespace ovl {
 
-hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st);
+hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st,
+                          bool accumulate = false);
 
 size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase)
 {
     const size_t F = field_bytes(P_F64, L.V);
     WsCarve c{nullptr, 0, 0};
-    c.take(F * nrhs * nshift);                        // x_j
+    c.take(F * nrhs * nshift);                        // x_j (or their increments dx_j)
     c.take(F * NR);                                   // batch right-hand sides
     c.take(F * NR);                                   // batch corrections
     c.take(F * nrhs);                                 // residual scratch
     c.take(F * nrhs);
+    c.take(F * nrhs);                                 // base residual at the hand-over
     c.take(sizeof(double) * 2 * NR * site_blocks(L));
     c.take(sizeof(double) * 4 * NR);
     c.take(sizeof(double) * NR * NS);                 // shift of each (shift, RHS) field
-    // the FP64 phase's workspace stays alive while the FP32 phase takes over
+    c.take(sizeof(double) * NR * NS);                 // zeta at the hand-over of each field
+    // the FP64 phase's workspace (y mode) stays alive while the FP32 phase takes over
     size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32, true);
-    if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m, true, P_F64, true);
+    if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m, false, P_F64);
     size_t b = blocked_ws_bytes(L, NR, 1, m, true, P_F32);
     return c.off + std::max(a, b) + 256;
 }
 
-// FP64 residuals res = b - (Q^2 + s) x for the nrhs fields of x; norms of
-// res and b per RHS to host (nres, nb)
-static int residual_f64(const Lat &L, const void *U64, double m0, double s, Fld b, Fld x, Fld t, Fld res,
-                        double *partials, double *red, double *nres, double *nb, hipStream_t st)
+// FP64 residuals res = bscale*b - (Q^2 + s) x for the nrhs fields of x (b has
+// one field per RHS); their norms per RHS to host
+static int residual_f64(const Lat &L, const void *U64, double m0, double s, Fld b, double bscale, Fld x, Fld t,
+                        Fld res, double *partials, double *red, double *nres, hipStream_t st)
 {
-    const int R = b.nrhs;
+    const int R = x.nrhs;
     const int nblk = site_blocks(L);
     WArgs A{};
     A.U = U64;
@@ -66,18 +75,13 @@ static int residual_f64(const Lat &L, const void *U64, double m0, double s, Fld 
     B.shift = s;
     B.out = res.d;
     OVL_HIP(launch_wilson(L, P_F64, W_SHIFT, true, B, st));
-    OVL_HIP(launch_axpby(L, 1.0, b, -1.0, res, st));
+    OVL_HIP(launch_axpby(L, bscale, b, -1.0, res, st));
     OVL_HIP(launch_norm2(L, res, partials, st));
     OVL_HIP(launch_reduce(partials, 1, R, nblk, red, st));
-    OVL_HIP(launch_norm2(L, b, partials, st));
-    OVL_HIP(launch_reduce(partials, 1, R, nblk, red + R, st));
-    double h[2 * NR];
-    OVL_HIP(hipMemcpyAsync(h, red, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, st));
+    double h[NR];
+    OVL_HIP(hipMemcpyAsync(h, red, sizeof(double) * R, hipMemcpyDeviceToHost, st));
     OVL_HIP(hipStreamSynchronize(st));
-    for (int q = 0; q < R; q++) {
-        nres[q] = std::sqrt(h[q]);
-        nb[q] = std::sqrt(h[R + q]);
-    }
+    for (int q = 0; q < R; q++) nres[q] = std::sqrt(h[q]);
     return OVL_OK;
 }
 
@@ -89,6 +93,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     const int m = prm->block > 0 ? prm->block : 16;
     const size_t F = field_bytes(P_F64, L.V);
     const bool f64_phase = prm->sloppy_below > 0.0;
+    if (!weights) return OVL_ERR_INVALID;
     if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, f64_phase)) return OVL_ERR_WORKSPACE;
     WsCarve c{ws, 0, ws_bytes};
     Fld X{c.take(F * R * nshift), nullptr, P_F64, R * nshift};
@@ -96,44 +101,17 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     Fld Ex{c.take(F * NR), nullptr, P_F64, NR};
     Fld T{c.take(F * R), nullptr, P_F64, R};
     Fld Res{c.take(F * R), nullptr, P_F64, R};
+    Fld R0{c.take(F * R), nullptr, P_F64, R};
     double *partials = (double *)c.take(sizeof(double) * 2 * NR * site_blocks(L));
     double *red = (double *)c.take(sizeof(double) * 4 * NR);
     double *fsh = (double *)c.take(sizeof(double) * NR * NS);
+    double *fze = (double *)c.take(sizeof(double) * NR * NS);
     char *sws = ws + c.off;
     size_t sws_bytes = ws_bytes - c.off;
-
-    // 0. FP64 phase, 1. sloppy phase
-    BlkOpts o;
-    o.m = m;
-    o.keep_x = true;
-    o.reliable = true;
-    o.x_ext = X;
-    int rc;
-    MsScratch h64{};
-    if (f64_phase) {
-        const size_t w64 = blocked_ws_bytes(L, R, nshift, m, true, P_F64, true);
-        BlkOpts o64 = o;
-        o64.reliable = false;
-        o64.switch_rel = prm->sloppy_below;
-        rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o64, prm, stats, sws, w64, st, &h64);
-        if (rc < 0) return rc;
-        if (rc == kSwitched) {
-            o.resume = &h64;
-            rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, sws + w64,
-                                       sws_bytes - w64, st, nullptr);
-            if (rc < 0) return rc;
-        }
-    } else {
-        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, sws, sws_bytes, st,
-                                   nullptr);
-        if (rc < 0) return rc;
-    }
-
-    // 2./3. verification and refinement
     const int nblk = site_blocks(L);
-    std::vector<double> res((size_t)R * nshift), bn(R), hsh((size_t)R * nshift);
-    for (int f = 0; f < R * nshift; f++) hsh[f] = shifts[f / R];
-    OVL_HIP(hipMemcpyAsync(fsh, hsh.data(), sizeof(double) * R * nshift, hipMemcpyHostToDevice, st));
+
+    // |b| per RHS
+    std::vector<double> bn(R);
     {
         double h[NR];
         OVL_HIP(launch_norm2(L, b, partials, st));
@@ -142,9 +120,60 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
         OVL_HIP(hipStreamSynchronize(st));
         for (int q = 0; q < R; q++) bn[q] = std::sqrt(h[q]);
     }
-    // FP64 true residuals |b - (Q^2 + s_j) x_j| / |b| of the fields f0 .. f0+n-1
-    // of X (field f = j*R + q), up to NR fields per pair of batched stencils:
-    // t = Q x, then the norm of b - (Q t + s x) without storing it
+
+    // 0. FP64 phase (y mode), 1. sloppy phase (x mode: x_j, or dx_j after a hand-over)
+    BlkOpts o;
+    o.m = m;
+    o.keep_x = true;
+    o.reliable = true;
+    o.x_ext = X;
+    int rc;
+    bool switched = false;
+    Fld r0 = b;                                                    // residual at the hand-over
+    std::vector<double> zeta((size_t)R * nshift, 1.0);             // zeta_j at the hand-over
+    std::vector<double> frozen_res((size_t)R * nshift, -1.0);      // shifts frozen in the FP64 phase
+    if (f64_phase) {
+        const size_t w64 = blocked_ws_bytes(L, R, nshift, m, false, P_F64);
+        BlkOpts o64;
+        o64.m = m;
+        o64.switch_rel = prm->sloppy_below;
+        MsScratch h64{};
+        rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, weights, b, y, o64, prm, stats, sws, w64, st, &h64);
+        if (rc < 0) return rc;
+        if (rc != kSwitched) return rc;   // converged (or stopped) within the FP64 phase: y is complete
+        switched = true;
+        static thread_local MState hs;
+        OVL_HIP(hipMemcpyAsync(&hs, h64.S, sizeof(MState), hipMemcpyDeviceToHost, st));
+        OVL_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < nshift; j++)
+            for (int q = 0; q < R; q++) {
+                zeta[(size_t)j * R + q] = hs.zeta[q][j];
+                if (!hs.act[q][j] && bn[q] > 0)
+                    frozen_res[(size_t)j * R + q] = std::sqrt(hs.frozen_rr[q][j]) / bn[q];
+            }
+        // keep r0 outside the solver workspace, which the refinement reuses
+        OVL_HIP(hipMemcpyAsync(R0.d, h64.r.d, F * R, hipMemcpyDeviceToDevice, st));
+        r0 = R0;
+        OVL_HIP(launch_zero(L, X, st));
+        o.resume = &h64;
+        // the base system's true residual during the sloppy phase is r0 - (Q^2 + s0) dx_0
+        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, r0, Fld{}, o, prm, stats, sws + w64,
+                                   sws_bytes - w64, st, nullptr);
+        if (rc < 0) return rc;
+    } else {
+        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, sws, sws_bytes, st,
+                                   nullptr);
+        if (rc < 0) return rc;
+    }
+
+    // 2./3. verification and refinement
+    std::vector<double> res((size_t)R * nshift), hsh((size_t)R * nshift);
+    for (int f = 0; f < R * nshift; f++) hsh[f] = shifts[f / R];
+    OVL_HIP(hipMemcpyAsync(fsh, hsh.data(), sizeof(double) * R * nshift, hipMemcpyHostToDevice, st));
+    OVL_HIP(hipMemcpyAsync(fze, zeta.data(), sizeof(double) * R * nshift, hipMemcpyHostToDevice, st));
+    // FP64 true residuals |zeta_j r0 - (Q^2 + s_j) x_j| / |b| of the fields
+    // f0 .. f0+n-1 of X (field f = j*R + q), up to NR fields per pair of
+    // batched stencils: t = Q x, then the norm without storing the residual
     auto verify = [&](int f0, int n) -> int {
         for (int c0 = f0; c0 < f0 + n; c0 += NR) {
             const int nc = std::min(NR, f0 + n - c0);
@@ -160,9 +189,10 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             B.out = nullptr;
             B.p = A.in;
             B.shiftv = fsh + c0;
-            B.rin = b.d;
+            B.rin = r0.d;
             B.rin_first = c0 % R;
             B.rin_count = R;
+            B.rin_scale = fze + c0;
             B.partials = partials;
             OVL_HIP(launch_wilson(L, P_F64, W_RESNORM, true, B, st));
             OVL_HIP(launch_reduce(partials, 1, nc, nblk, red, st));
@@ -171,15 +201,24 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             OVL_HIP(hipStreamSynchronize(st));
             for (int k = 0; k < nc; k++) {
                 const int f = c0 + k;
-                res[f] = bn[f % R] > 0 ? std::sqrt(h[k]) / bn[f % R] : 0.0;
+                res[f] = frozen_res[f] >= 0.0 ? frozen_res[f] : bn[f % R] > 0 ? std::sqrt(h[k]) / bn[f % R] : 0.0;
             }
             if (stats) stats->stencil_applies += 2;
         }
         return OVL_OK;
     };
     {
-        int e = verify(0, R * nshift);
-        if (e) return e;
+        // shifts frozen for every RHS in the FP64 phase need no stencils
+        // (shifts ascend, and the largest converge first)
+        int jmax = -1;
+        for (int j = 0; j < nshift; j++)
+            for (int q = 0; q < R; q++)
+                if (frozen_res[(size_t)j * R + q] < 0.0) jmax = j;
+        for (int f = (jmax + 1) * R; f < R * nshift; f++) res[f] = frozen_res[f];
+        if (jmax >= 0) {
+            int e = verify(0, (jmax + 1) * R);
+            if (e) return e;
+        }
     }
     int refine_iters = 0;
     for (int round = 0; round < 3 && prm->refine; round++) {
@@ -193,14 +232,14 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             double bshift[NR], btol[NR];
             for (int k = 0; k < nbat; k++) {
                 const int j = bad[b0 + k].first, q = bad[b0 + k].second;
-                // right-hand side r_j = b - (Q^2 + s_j) x_j for this RHS
-                double nr[NR], nb[NR];
-                int e = residual_f64(L, U->f64, m0, shifts[j], b, sub(X, L.V, j * R, R), T, Res, partials, red, nr,
-                                     nb, st);
+                // right-hand side r_j = zeta_j r0 - (Q^2 + s_j) x_j of this RHS
+                double nr[NR];
+                int e = residual_f64(L, U->f64, m0, shifts[j], sub(r0, L.V, q, 1), zeta[(size_t)j * R + q],
+                                     sub(X, L.V, j * R + q, 1), T, Res, partials, red, nr, st);
                 if (e) return e;
-                OVL_HIP(hipMemcpyAsync((char *)Eb.d + F * k, (char *)Res.d + F * q, F, hipMemcpyDeviceToDevice, st));
+                OVL_HIP(hipMemcpyAsync((char *)Eb.d + F * k, Res.d, F, hipMemcpyDeviceToDevice, st));
                 bshift[k] = shifts[j];
-                const double rel = nb[q] > 0 ? nr[q] / nb[q] : 0.0;
+                const double rel = bn[q] > 0 ? nr[0] / bn[q] : 0.0;
                 btol[k] = std::min(0.5, std::max(1e-7, 0.25 * prm->tol / std::max(rel, 1e-300)));
                 if (stats) stats->stencil_applies += 2;
             }
@@ -225,6 +264,8 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             for (int k = 0; k < nbat; k++) {
                 const int j = bad[b0 + k].first, q = bad[b0 + k].second;
                 OVL_HIP(launch_axpby(L, 1.0, sub(ex, L.V, k, 1), 1.0, sub(X, L.V, j * R + q, 1), st));
+                // a refined shift now has a sloppy part: verify it like the others
+                frozen_res[(size_t)j * R + q] = -1.0;
             }
         }
         for (int j = 0; j < nshift; j++) {
@@ -235,14 +276,14 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             if (e) return e;
         }
     }
-    int status = rc;
+    int status = rc == kSwitched ? OVL_OK : rc;
     for (int j = 0; j < nshift; j++)
         for (int q = 0; q < R; q++) {
             if (stats) stats->true_residual[q][j] = res[(size_t)j * R + q];
             if (!(res[(size_t)j * R + q] <= prm->tol)) status = OVL_NOT_CONVERGED;
         }
     if (stats) stats->refine_iterations += refine_iters;
-    OVL_HIP(launch_combine(L, weights, nshift, X, y, st));
+    OVL_HIP(launch_combine(L, weights, nshift, X, y, st, switched));
     return status;
 }
 

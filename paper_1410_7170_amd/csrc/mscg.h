@@ -48,6 +48,7 @@ struct MState {
     int act[NR][NS];       // shift still iterating
     int act_cur[NR][NS];   // shifts updated in the current iteration
     int frozen_at[NR][NS];
+    double frozen_rr[NR][NS];   // zeta^2 |r|^2 of a shift at the iteration it froze
     int iter[NR];
     int skip[NR];          // RHS finished (every shift frozen) or failed
     int nonfinite[NR];

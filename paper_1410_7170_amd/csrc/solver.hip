@@ -113,6 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_beta(MState *st, const double *pa
             if (zn * zn * rr_new <= thr) {
                 st->act[r][j] = 0;
                 st->frozen_at[r][j] = it;
+                st->frozen_rr[r][j] = zn * zn * rr_new;
             } else {
                 left++;
             }
@@ -179,16 +180,21 @@ __global__ __launch_bounds__(kBlock) void k_ms_start(Geom g, int nb, const doubl
 }
 
 // y_r = sum_j w_j x_{j,r} (FP64)
+// y = sum_j w_j x_j, or y += sum_j w_j x_j with accumulate
 __global__ __launch_bounds__(kBlock) void k_combine(Geom g, int nb, ShiftWeights w, const double2 *xf, double2 *y,
-                                                    int nrhs, int nshift)
+                                                    int nrhs, int nshift, int accumulate)
 {
     const int rr = blockIdx.y;
     const int bl = blockIdx.x;
     const int p = bl / nb, i = (bl % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
     cplx<double> acc[4][3], v[4][3];
+    if (accumulate) {
+        spinor_ref<P_F64>(y, nullptr, g.S, rr).load(p, i, acc);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 12; k++) acc[k / 3][k % 3] = {0.0, 0.0};
+        for (int k = 0; k < 12; k++) acc[k / 3][k % 3] = {0.0, 0.0};
+    }
     for (int j = 0; j < nshift; j++) {
         spinor_ref<P_F64>(xf, nullptr, g.S, j * nrhs + rr).load(p, i, v);
         const double wj = w.w[j];
@@ -409,12 +415,13 @@ int true_residuals_f64(const Lat &L, const void *U64, double m0, double s, Fld b
     return OVL_OK;
 }
 
-hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st)
+hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st, bool accumulate)
 {
     ShiftWeights sw;
     for (int j = 0; j < NS; j++) sw.w[j] = j < nshift ? w[j] : 0.0;
     dim3 grid(site_blocks(L), y.nrhs);
-    k_combine<<<grid, kBlock, 0, st>>>(L.g, L.nb, sw, (const double2 *)x.d, (double2 *)y.d, y.nrhs, nshift);
+    k_combine<<<grid, kBlock, 0, st>>>(L.g, L.nb, sw, (const double2 *)x.d, (double2 *)y.d, y.nrhs, nshift,
+                                       accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

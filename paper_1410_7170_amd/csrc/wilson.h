@@ -33,6 +33,7 @@ struct WArgs {
     const float *rin_sc;
     int rin_first;          // W_RESNORM: RHS r reads field (rin_first + r) % rin_count of rin
     int rin_count;
+    const double *rin_scale;  // W_RESNORM: rin of RHS r taken times rin_scale[r] (null: 1)
     double diag;            // m0 + 4
     double shift;
     const double *shiftv;   // per-RHS shift (device), overrides shift when set
@@ -202,11 +203,12 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
     } else if (MODE == W_RESNORM) {
         cplx<T> rv[4][3];
         spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load(p, i, rv);
+        const T rs = a.rin_scale ? (T)a.rin_scale[r] : (T)1;
         T n0 = 0;
 #pragma unroll
         for (int s = 0; s < 4; s++)
 #pragma unroll
-            for (int c = 0; c < 3; c++) n0 += norm2(rv[s][c] - o[s][c]);
+            for (int c = 0; c < 3; c++) n0 += norm2(rs * rv[s][c] - o[s][c]);
         q0 += (double)n0;
     } else {
         spinor_ref<PREC>(a.out, a.out_sc, g.S, r).store_nt(p, i, o);
@@ -317,10 +319,12 @@ __device__ __forceinline__ void tback_add(cplx<T> acc[4][3], const cplx<T> w[2][
 // for the forward hop, is the centre of the next slice, and the backward
 // hop's U_0(t)^H (1 + gamma_0) psi(t) is formed while slice t holds U_0(t)
 // and psi(t) in registers.  Requires L1*L2*L3 % 256 == 0 and Ts | L0.
+// WPE is the minimum number of waves per SIMD the build allows for (1 or 2);
+// the one-wave build overlaps pairs of time slices.
 // Partial sums: slot lb holds the block's sum and the block zeroes the slots
 // lb + m*nblk_ts (m >= 1) below a.nblk, so all 2*nb slots per RHS are valid.
-template <int PREC, int MODE, bool G5>
-__global__ __launch_bounds__(kBlock, 2) void k_wilson_ts(WArgs a)
+template <int PREC, int MODE, bool G5, int WPE>
+__global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
 {
     using T = typename Real<PREC>::T;
     __shared__ double lds[8];
@@ -358,6 +362,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_wilson_ts(WArgs a)
         tback_half(w, sv, u);
     }
     double q0 = 0.0, q1 = 0.0;
+#pragma unroll(WPE == 1 ? 2 : 1)
     for (int k = 0; k < Ts; k++) {
         const int t = t0 + k;
         x[0] = t;

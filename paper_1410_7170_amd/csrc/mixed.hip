@@ -34,13 +34,18 @@ namespace ovl {
 hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld y, hipStream_t st,
                           bool accumulate = false);
 
+// Systems per refinement batch: as many as RHS (at most NR), so that the
+// workspace grows with nrhs only; refinement is rare and small.
+static int refine_batch(int nrhs) { return std::max(1, std::min(NR, nrhs)); }
+
 size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase)
 {
     const size_t F = field_bytes(P_F64, L.V);
     WsCarve c{nullptr, 0, 0};
+    const int nbat = refine_batch(nrhs);
     c.take(F * nrhs * nshift);                        // x_j (or their increments dx_j)
-    c.take(F * NR);                                   // batch right-hand sides
-    c.take(F * NR);                                   // batch corrections
+    c.take(F * nbat);                                 // refinement batch right-hand sides
+    c.take(F * nbat);                                 // refinement batch corrections
     c.take(F * nrhs);                                 // residual scratch
     c.take(F * nrhs);
     c.take(F * nrhs);                                 // base residual at the hand-over
@@ -51,7 +56,7 @@ size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase)
     // the FP64 phase's workspace (y mode) stays alive while the FP32 phase takes over
     size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32, true);
     if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m, false, P_F64);
-    size_t b = blocked_ws_bytes(L, NR, 1, m, true, P_F32);
+    size_t b = blocked_ws_bytes(L, nbat, 1, m, true, P_F32);
     return c.off + std::max(a, b) + 256;
 }
 
@@ -96,9 +101,10 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     if (!weights) return OVL_ERR_INVALID;
     if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, f64_phase)) return OVL_ERR_WORKSPACE;
     WsCarve c{ws, 0, ws_bytes};
+    const int NB = refine_batch(R);
     Fld X{c.take(F * R * nshift), nullptr, P_F64, R * nshift};
-    Fld Eb{c.take(F * NR), nullptr, P_F64, NR};
-    Fld Ex{c.take(F * NR), nullptr, P_F64, NR};
+    Fld Eb{c.take(F * NB), nullptr, P_F64, NB};
+    Fld Ex{c.take(F * NB), nullptr, P_F64, NB};
     Fld T{c.take(F * R), nullptr, P_F64, R};
     Fld Res{c.take(F * R), nullptr, P_F64, R};
     Fld R0{c.take(F * R), nullptr, P_F64, R};
@@ -172,20 +178,23 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     OVL_HIP(hipMemcpyAsync(fsh, hsh.data(), sizeof(double) * R * nshift, hipMemcpyHostToDevice, st));
     OVL_HIP(hipMemcpyAsync(fze, zeta.data(), sizeof(double) * R * nshift, hipMemcpyHostToDevice, st));
     // FP64 true residuals |zeta_j r0 - (Q^2 + s_j) x_j| / |b| of the fields
-    // f0 .. f0+n-1 of X (field f = j*R + q), up to NR fields per pair of
-    // batched stencils: t = Q x, then the norm without storing the residual
+    // f0 .. f0+n-1 of X (field f = j*R + q), up to NV fields per pair of
+    // batched stencils: t = Q x (into the solver workspace, free between
+    // solves), then the norm without storing the residual
+    const int NV = (int)std::min<size_t>(NR, std::max<size_t>(1, sws_bytes / F));
+    Fld Tv{sws, nullptr, P_F64, NV};
     auto verify = [&](int f0, int n) -> int {
-        for (int c0 = f0; c0 < f0 + n; c0 += NR) {
-            const int nc = std::min(NR, f0 + n - c0);
+        for (int c0 = f0; c0 < f0 + n; c0 += NV) {
+            const int nc = std::min(NV, f0 + n - c0);
             WArgs A{};
             A.U = U->f64;
             A.diag = m0 + 4.0;
             A.nrhs = nc;
             A.in = sub(X, L.V, c0, nc).d;
-            A.out = Eb.d;
+            A.out = Tv.d;
             OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, true, A, st));
             WArgs B = A;
-            B.in = Eb.d;
+            B.in = Tv.d;
             B.out = nullptr;
             B.p = A.in;
             B.shiftv = fsh + c0;
@@ -227,8 +236,8 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             for (int q = 0; q < R; q++)
                 if (res[(size_t)j * R + q] > prm->tol) bad.push_back({j, q});
         if (bad.empty()) break;
-        for (size_t b0 = 0; b0 < bad.size(); b0 += NR) {
-            const int nbat = (int)std::min<size_t>(NR, bad.size() - b0);
+        for (size_t b0 = 0; b0 < bad.size(); b0 += NB) {
+            const int nbat = (int)std::min<size_t>(NB, bad.size() - b0);
             double bshift[NR], btol[NR];
             for (int k = 0; k < nbat; k++) {
                 const int j = bad[b0 + k].first, q = bad[b0 + k].second;

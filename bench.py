@@ -102,6 +102,7 @@ def main():
     shifts, weights, delta = ovl.zolotarev(lo, hi, npoles)
     B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
     out = ovl.Spinor(lat, ovl.F64, B.nrhs)
+    tune = ovl.autotune_stencil(lat, G, B.nrhs)
     setup_s = time.time() - t_setup
     print(f"[bench] setup {setup_s:.1f}s dims={dims} |Q| in [{lo:.4f}, {hi:.4f}] delta={delta:.2e}",
           file=sys.stderr, flush=True)
@@ -209,7 +210,7 @@ def main():
     bytes_per_launch = kbytes[dom] / max(klaunch[dom], 1)
     achieved = bytes_per_launch / avg / 1e9 if avg > 0 else 0.0
     src = source_hash(names[dom])
-    wl = f"{timed_form}@{'x'.join(str(d) for d in dims)}"
+    wl = f"{timed_form}@{'x'.join(str(d) for d in dims)}@s{lat.stream_t}-{lat.stream_t64}"
     traffic = load_traffic(names[dom], src, wl)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4),
@@ -253,6 +254,7 @@ def main():
         "config": {"workload": f"overlap apply {dims[1]}^3x{dims[0]}, {npoles} Zolotarev poles, "
                                f"tol {args.tol:g}, rho {RHO}",
                    "lattice": list(dims), "nrhs": nrhs, "poles": npoles, "form": timed_form,
+                   "stencil_order": {k: tune[k] for k in ("tile_t", "stream_t", "stream_t64")},
                    "spectral_interval": [lo, hi], "zolotarev_delta": delta},
         "stencil": stencil,
         "forms": {k: dict(applies_per_s=round(nrhs / v["seconds"], 4), iterations=v["iterations"],
@@ -270,6 +272,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "multi_rhs": mrhs,
+        "autotune": tune["timings"],
     }
     print(json.dumps(line))
 
@@ -293,6 +296,7 @@ def multi_rhs_line(args, ovl, synth, np, torch):
     b = synth.config_sources(cfg)
     B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
     out = ovl.Spinor(lat, ovl.F64, B.nrhs)
+    tune = ovl.autotune_stencil(lat, G, B.nrhs)
     prm = ovl.default_params(tol=args.tol, maxiter=5000, block=16, mode=ovl.SOLVE_MIXED)
     ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
     torch.cuda.synchronize()
@@ -323,7 +327,8 @@ def multi_rhs_line(args, ovl, synth, np, torch):
                 iterations=st["iterations"], max_true_residual=max(max(r) for r in st["true_residual"]),
                 refine_iterations=st["refine_iterations"],
                 rel_diff_rhs0_vs_fp64=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-                stream_t=lat.stream_t, stream_t64=lat.stream_t64)
+                stencil_order={k: tune[k] for k in ("tile_t", "stream_t", "stream_t64")},
+                autotune=tune["timings"])
     print(f"[bench] multi-rhs {dims}: {rate:.3f} RHS-applies/s, FP64 single {1.0/el64:.3f}/s, "
           f"max residual {line['max_true_residual']:.2e}", file=sys.stderr, flush=True)
     return line

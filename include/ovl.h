@@ -277,6 +277,7 @@ enum ovl_op {
     OVL_OP_Q2 = 0,
     OVL_OP_LANCZOS = 1,
     OVL_OP_MSCG = 2,      /* ovl_multishift_cg, sign_q_apply, overlap_apply */
+    OVL_OP_TUNE = 3,      /* ovl_autotune_stencil (prec ignored) */
 };
 
 /* Workspace bytes for an operation; prm may be NULL for OVL_OP_Q2/LANCZOS. */
@@ -286,6 +287,23 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
  * check_every 10, refine 1, verify 0, profile 0, block 0. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
+
+/* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on
+ * nrhs fields of a fixed pattern in every precision whose links U provides,
+ * over the candidate site orders -- lat->tile_t in {1,2,4,8,16} for the one-site form
+ * (timed on FP16 links when given, else FP32), lat->stream_t in
+ * {0,2,4,8,16,32} on FP32 and lat->stream_t64 likewise on FP64 (lengths that
+ * divide dims[0]; streaming only when dims[1]*dims[2]*dims[3] % 256 == 0) --
+ * and writes the fastest of each into *lat (a candidate replaces the current
+ * value only when more than 2% faster).  Outputs of every operator
+ * depend on these fields only through summation order.  ws: device workspace
+ * of ovl_workspace_bytes(lat, OVL_OP_TUNE, 0, nrhs, 0, NULL) bytes.
+ * tried/times_us (host, optional, max_tried entries): candidate k as
+ * 1000*what + value (what 0 tile_t, 1 stream_t, 2 stream_t64) and its average
+ * launch time in microseconds.  Returns the number of candidates timed (>= 0)
+ * or a negative error.  Synchronises the stream. */
+OVL_API int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
+                                 int32_t *tried, float *times_us, int32_t max_tried, void *stream);
 
 OVL_API const char *ovl_status_string(int status);
 OVL_API int ovl_last_hip_error(void);

@@ -31,7 +31,7 @@ OK, NOT_CONVERGED = 0, 1
 ERR_INVALID, ERR_WORKSPACE, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
 F64, F32, F16S = 0, 1, 2
 SOLVE_F64, SOLVE_MIXED = 0, 1
-OP_Q2, OP_LANCZOS, OP_MSCG = 0, 1, 2
+OP_Q2, OP_LANCZOS, OP_MSCG, OP_TUNE = 0, 1, 2, 3
 K_STENCIL, K_UPDATE, K_SCALAR, K_OTHER = 0, 1, 2, 3
 MAX_SHIFTS, MAX_RHS = 32, 16
 PREC_NAMES = {F64: "f64", F32: "f32", F16S: "f16s"}
@@ -108,6 +108,8 @@ _sig = {
                                   P(ovl_solver_params), P(ovl_solver_stats), c_vp, ctypes.c_size_t, c_vp]),
     "ovl_workspace_bytes": (ctypes.c_size_t, [P(ovl_lattice), c_i32, c_i32, c_i32, c_i32, P(ovl_solver_params)]),
     "ovl_default_params": (None, [P(ovl_solver_params)]),
+    "ovl_autotune_stencil": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_i32, c_vp, ctypes.c_size_t, P(c_i32),
+                                     P(ctypes.c_float), c_i32, c_vp]),
     "ovl_status_string": (ctypes.c_char_p, [c_i32]),
     "ovl_last_hip_error": (c_i32, []),
     "ovl_version": (ctypes.c_char_p, []),
@@ -309,6 +311,22 @@ def zolotarev(lambda_min: float, lambda_max: float, npoles: int):
     _check(_lib.ovl_zolotarev(float(lambda_min), float(lambda_max), int(npoles), s, w, ctypes.byref(d)),
            "ovl_zolotarev")
     return np.array(s[:]), np.array(w[:]), d.value
+
+
+def autotune_stencil(lat: Lattice, U: Gauge, nrhs: int = 1, ws=None, stream=None) -> dict:
+    """Time the stencil's candidate site orders (ovl_autotune_stencil) and keep
+    the fastest in `lat`; returns the choices and every timing (microseconds)."""
+    if ws is None:
+        ws = workspace(lat, OP_TUNE, F64, nrhs)
+    n = 64
+    tried = (c_i32 * n)()
+    times = (ctypes.c_float * n)()
+    rc = _lib.ovl_autotune_stencil(lat.ref, U.ref, int(nrhs), c_vp(ws.data_ptr()), ws.numel(), tried, times, n,
+                                   _stream(stream))
+    _check(rc, "ovl_autotune_stencil")
+    names = ("tile_t", "stream_t", "stream_t64")
+    table = [(names[tried[k] // 1000], tried[k] % 1000, round(float(times[k]), 2)) for k in range(min(rc, n))]
+    return dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, timings=table)
 
 
 def spectral_bounds(lat: Lattice, U: Gauge, m0: float, iters: int, start: Spinor,

@@ -20,6 +20,9 @@ hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld 
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
 size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase);
+size_t tune_ws_bytes(const Lat &L, int nrhs);
+int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes, hipStream_t st,
+                     int32_t *tried, float *times_us, int32_t max_tried);
 int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
                Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
                hipStream_t st);
@@ -258,6 +261,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         return ((F + 255) & ~(size_t)255) + scale_bytes(L.V) * nrhs + 256;
     }
     if (op == OVL_OP_LANCZOS) return lanczos_ws_bytes(L);
+    if (op == OVL_OP_TUNE) return tune_ws_bytes(L, nrhs);
     if (op == OVL_OP_MSCG) {
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS) return 0;
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
@@ -282,6 +286,14 @@ void ovl_default_params(ovl_solver_params *p)
     p->profile = 0;
     p->block = 0;
     p->sloppy_below = 1e-5;
+}
+
+int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
+                         int32_t *tried, float *times_us, int32_t max_tried, void *stream)
+{
+    if (!lat_ok(lat) || !U || !ws || nrhs < 1 || nrhs > OVL_MAX_RHS || max_tried < 0) return OVL_ERR_INVALID;
+    if (!U->f64 && !U->f32 && !U->f16) return OVL_ERR_INVALID;
+    return autotune_stencil(lat, U, nrhs, (char *)ws, ws_bytes, (hipStream_t)stream, tried, times_us, max_tried);
 }
 
 int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,

@@ -1,0 +1,174 @@
+// Stencil autotuner: times the candidate site orders of the Wilson stencil
+// on the caller's lattice, links and RHS count and keeps the fastest.
+//
+// Candidates per precision (results differ only in summation order):
+//   FP16 (and the one-site form of FP64/FP32): tile_t in {1, 2, 4, 8, 16}
+//     dividing L0;
+//   FP32: stream_t = 0 (one site per thread) or a divisor of L0 in
+//     {2, 4, 8, 16, 32} when L1*L2*L3 % 256 == 0;
+//   FP64: stream_t64 = 0 (follow stream_t) or such a divisor.
+// tile_t is tuned first (on the FP16 stencil when those links are given,
+// else on FP32), then stream_t on FP32, then stream_t64 on FP64.  A candidate
+// replaces the lattice's current value only when it is more than 2% faster,
+// so near-ties keep the defaults and repeated tuning gives the same choices.
+// Input fields hold a fixed hashed pattern in [-1/2, 1/2), like the data of
+// a solve (all-zero fields measured faster than real data).
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace ovl {
+
+size_t tune_ws_bytes(const Lat &L, int nrhs)
+{
+    size_t b = 0;
+    for (int prec = 0; prec < 3; prec++)
+        b += 2 * (((field_bytes(prec, L.V) * nrhs + 255) & ~(size_t)255) + ((scale_bytes(L.V) * nrhs + 255) & ~(size_t)255));
+    return b + 256;
+}
+
+namespace {
+
+__device__ __forceinline__ float pattern(size_t i)
+{
+    uint32_t h = (uint32_t)(i * 0x9E3779B1u) ^ (uint32_t)(i >> 32);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return (float)(h & 0xffffu) * (1.0f / 65536.0f) - 0.5f;
+}
+
+// n reals of a field in its storage type (double, float or half); F16
+// scales are set to 1
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_tune_fill(void *d, size_t n, float *sc, size_t nsc)
+{
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        if (PREC == P_F64) ((double *)d)[i] = (double)pattern(i);
+        else if (PREC == P_F32) ((float *)d)[i] = pattern(i);
+        else ((unsigned short *)d)[i] = f2h(pattern(i));
+    }
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; sc && i < nsc; i += stride) sc[i] = 1.0f;
+}
+
+struct Field {
+    Fld in, out;
+};
+
+// average time of one stencil launch (two warm-up launches, then `reps`)
+int time_stencil(const Lat &L, const void *Ul, int prec, const Field &f, int reps, hipEvent_t e0, hipEvent_t e1,
+                 hipStream_t st, float *us)
+{
+    WArgs a{};
+    a.U = Ul;
+    a.diag = 4.0;
+    a.nrhs = f.in.nrhs;
+    a.in = f.in.d;
+    a.in_sc = f.in.sc;
+    a.out = f.out.d;
+    a.out_sc = f.out.sc;
+    for (int k = 0; k < 2; k++) OVL_HIP(launch_wilson(L, prec, W_PLAIN, false, a, st));
+    OVL_HIP(hipEventRecord(e0, st));
+    for (int k = 0; k < reps; k++) OVL_HIP(launch_wilson(L, prec, W_PLAIN, false, a, st));
+    OVL_HIP(hipEventRecord(e1, st));
+    OVL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    OVL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *us = 1e3f * ms / reps;
+    return OVL_OK;
+}
+
+}  // namespace
+
+int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes, hipStream_t st,
+                     int32_t *tried, float *times_us, int32_t max_tried)
+{
+    Lat L = make_lat(lat);
+    if (ws_bytes < tune_ws_bytes(L, nrhs)) return OVL_ERR_WORKSPACE;
+    Field fl[3];
+    size_t off = 0;
+    for (int prec = 0; prec < 3; prec++) {
+        const size_t F = (field_bytes(prec, L.V) * nrhs + 255) & ~(size_t)255;
+        const size_t Sc = (scale_bytes(L.V) * nrhs + 255) & ~(size_t)255;
+        fl[prec].in = {ws + off, prec == P_F16S ? (float *)(ws + off + F) : nullptr, prec, nrhs};
+        off += F + Sc;
+        fl[prec].out = {ws + off, prec == P_F16S ? (float *)(ws + off + F) : nullptr, prec, nrhs};
+        off += F + Sc;
+        // reals of the nrhs input fields: 2 per complex, 12 complex per site, 2*S sites
+        const size_t nreal = (size_t)nrhs * 2 * 12 * 2 * L.g.S;
+        const size_t nsc = prec == P_F16S ? (size_t)nrhs * scale_floats(L.V) : 0;
+        if (prec == P_F64) k_tune_fill<P_F64><<<1024, kBlock, 0, st>>>(fl[prec].in.d, nreal, nullptr, 0);
+        else if (prec == P_F32) k_tune_fill<P_F32><<<1024, kBlock, 0, st>>>(fl[prec].in.d, nreal, nullptr, 0);
+        else k_tune_fill<P_F16S><<<1024, kBlock, 0, st>>>(fl[prec].in.d, nreal, fl[prec].in.sc, nsc);
+        OVL_HIP(hipGetLastError());
+    }
+    const void *Up[3] = {U->f64, U->f32, U->f16};
+    hipEvent_t e0, e1;
+    OVL_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return OVL_ERR_HIP;
+    }
+    const int reps = 5;
+    int n = 0, rc = OVL_OK;
+    auto record = [&](int what, int value, float us) {
+        if (tried && times_us && n < max_tried) {
+            tried[n] = what * 1000 + value;
+            times_us[n] = us;
+        }
+        n++;
+    };
+    const int L0 = lat->dims[0];
+    const bool can_stream = ((int64_t)lat->dims[1] * lat->dims[2] * lat->dims[3]) % 256 == 0;
+    // 1. tile_t of the one-site form
+    {
+        const int prec = Up[P_F16S] ? P_F16S : P_F32;
+        if (Up[prec]) {
+            const int s0 = lat->stream_t, s64 = lat->stream_t64;
+            lat->stream_t = 0;
+            lat->stream_t64 = 0;
+            const int cur = lat->tile_t;
+            int best = cur;
+            float tb = INFINITY, tcur = INFINITY;
+            for (int t : {1, 2, 4, 8, 16}) {
+                if (L0 % t) continue;
+                lat->tile_t = t;
+                float us;
+                rc = time_stencil(make_lat(lat), Up[prec], prec, fl[prec], reps, e0, e1, st, &us);
+                if (rc) break;
+                record(0, t, us);
+                if (t == cur) tcur = us;
+                if (us < tb) { tb = us; best = t; }
+            }
+            lat->tile_t = tb < 0.98f * tcur ? best : cur;
+            lat->stream_t = s0;
+            lat->stream_t64 = s64;
+        }
+    }
+    // 2. stream_t on FP32, 3. stream_t64 on FP64
+    for (int prec : {P_F32, P_F64}) {
+        if (rc || !Up[prec]) continue;
+        int *field = prec == P_F32 ? &lat->stream_t : &lat->stream_t64;
+        const int cur = *field;
+        int best = cur;
+        float tb = INFINITY, tcur = INFINITY;
+        for (int s : {0, 2, 4, 8, 16, 32}) {
+            if (s && (!can_stream || L0 % s)) continue;
+            *field = s;
+            float us;
+            rc = time_stencil(make_lat(lat), Up[prec], prec, fl[prec], reps, e0, e1, st, &us);
+            if (rc) break;
+            record(prec == P_F32 ? 1 : 2, s, us);
+            if (s == cur) tcur = us;
+            if (us < tb) { tb = us; best = s; }
+        }
+        *field = tb < 0.98f * tcur ? best : cur;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc ? rc : n;
+}
+
+}  // namespace ovl

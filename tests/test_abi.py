@@ -96,6 +96,22 @@ def test_null_and_alias_rejected_before_launch(ovl):
                             ctypes.c_void_p(1 << 24), 16, None) == ovl.ERR_WORKSPACE
 
 
+def test_autotune_rejected_before_launch(ovl):
+    lat = ovl.Lattice((4, 4, 4, 4))
+    lib = ovl._lib
+    g0 = ovl.ovl_gauge(None, None, None)
+    gf = ovl.ovl_gauge(ctypes.c_void_p(8192), None, None)
+    ws = ctypes.c_void_p(1 << 24)
+    need = lib.ovl_workspace_bytes(lat.ref, ovl.OP_TUNE, 0, 1, 0, None)
+    assert need > 6 * lat.spinor_bytes(ovl.F16S)
+    # no links, no workspace, bad RHS count, too small a workspace
+    assert lib.ovl_autotune_stencil(lat.ref, ctypes.byref(g0), 1, ws, need, None, None, 0, None) == ovl.ERR_INVALID
+    assert lib.ovl_autotune_stencil(lat.ref, ctypes.byref(gf), 1, None, need, None, None, 0, None) == ovl.ERR_INVALID
+    assert lib.ovl_autotune_stencil(lat.ref, ctypes.byref(gf), 0, ws, need, None, None, 0, None) == ovl.ERR_INVALID
+    assert lib.ovl_autotune_stencil(lat.ref, ctypes.byref(gf), 17, ws, need, None, None, 0, None) == ovl.ERR_INVALID
+    assert lib.ovl_autotune_stencil(lat.ref, ctypes.byref(gf), 1, ws, 64, None, None, 0, None) == ovl.ERR_WORKSPACE
+
+
 def test_solver_params_rejected(ovl):
     lat = ovl.Lattice((4, 4, 4, 4))
     lib = ovl._lib

@@ -281,3 +281,24 @@ def test_stream_t64_selects_fp64_length(ovl, dims, ts, ts64):
         out = ovl.Spinor(lat, prec)
         ovl.wilson_apply(lat, G, M0, inp, out)
         assert rel(out.to_canonical().cpu().numpy()[0], ref) < TOL[prec], prec
+
+
+@pytest.mark.parametrize("dims,nrhs", [((8, 8, 8, 4), 1), ((16, 8, 8, 8), 3)])
+def test_autotune_keeps_results(ovl, dims, nrhs):
+    """The autotuner only reorders summation: after it, the stencil still
+    matches the oracle in every precision, and its choices are valid."""
+    note(f"autotune dims={dims} nrhs={nrhs}")
+    lat, olat, U, G = setup(ovl, dims, seed=29, n_stout=1)
+    res = ovl.autotune_stencil(lat, G, nrhs)
+    assert len(res["timings"]) > 3 and all(t > 0 for _, _, t in res["timings"])
+    assert dims[0] % lat.tile_t == 0
+    assert lat.stream_t == 0 or dims[0] % lat.stream_t == 0
+    assert lat.stream_t64 == 0 or dims[0] % lat.stream_t64 == 0
+    psi = synth.gaussian_spinor(lat.V, 30, nrhs)
+    for prec in (0, 1, 2):
+        inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+        out = ovl.Spinor(lat, prec, nrhs)
+        ovl.wilson_apply(lat, G, M0, inp, out)
+        got = out.to_canonical().cpu().numpy()
+        for r in range(nrhs):
+            assert rel(got[r], oracle.dw(olat, U, M0, psi[r])) < TOL[prec], (prec, r, res)

@@ -149,6 +149,116 @@ __device__ __forceinline__ void hops_mu(const Geom &g, const SpinorRef<PREC> &in
     hop<T, MU, false>(acc, s, u, ph);
 }
 
+// LDS copy of one time slice of a streaming block: the centres of its 256
+// sites as component arrays indexed by the thread's local site index
+// (double2 per complex in FP64, float4 per complex pair otherwise).
+template <int PREC>
+struct LdsPsi {
+    using E = float4;
+    static constexpr int NC = 6;
+    E (*d)[kBlock];
+    __device__ __forceinline__ void store(int l, const cplx<float> s[4][3]) const
+    {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            cplx<float> a = s[(2 * k) / 3][(2 * k) % 3], c = s[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            d[k][l] = make_float4(a.x, a.y, c.x, c.y);
+        }
+    }
+    __device__ __forceinline__ void load(int l, cplx<float> s[4][3]) const
+    {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            float4 v = d[k][l];
+            s[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+            s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+        }
+    }
+};
+template <>
+struct LdsPsi<P_F64> {
+    using E = double2;
+    static constexpr int NC = 12;
+    E (*d)[kBlock];
+    __device__ __forceinline__ void store(int l, const cplx<double> s[4][3]) const
+    {
+#pragma unroll
+        for (int k = 0; k < 12; k++) d[k][l] = make_double2(s[k / 3][k % 3].x, s[k / 3][k % 3].y);
+    }
+    __device__ __forceinline__ void load(int l, cplx<double> s[4][3]) const
+    {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 v = d[k][l];
+            s[k / 3][k % 3] = {v.x, v.y};
+        }
+    }
+};
+
+// Neighbour spinor from the slice's LDS copy (local index ln) when inside,
+// else from memory (parity pn, index jn): one generic-pointer load path for
+// both, so the compiler need not carry both versions.  The LDS and memory
+// layouts share their element type; FP16 (never staged) keeps a branch.
+template <int PREC>
+__device__ __forceinline__ void load_either(const LdsPsi<PREC> &lp, const SpinorRef<PREC> &in, bool inside, int ln,
+                                            int pn, int jn, int S, cplx<typename Real<PREC>::T> s[4][3])
+{
+    if constexpr (PREC == P_F16S) {
+        if (inside) lp.load(ln, s);
+        else in.load(pn, jn, s);
+    } else {
+        using E = typename LdsPsi<PREC>::E;
+        constexpr int NC = LdsPsi<PREC>::NC;
+        const E *b = inside ? (const E *)&lp.d[0][ln] : (const E *)in.d + (size_t)pn * NC * S + jn;
+        const size_t stride = inside ? (size_t)kBlock : (size_t)S;
+        E v[NC];
+#pragma unroll
+        for (int k = 0; k < NC; k++) v[k] = b[k * stride];
+        if constexpr (PREC == P_F64) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) s[k / 3][k % 3] = {v[k].x, v[k].y};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                s[(2 * k) / 3][(2 * k) % 3] = {v[k].x, v[k].y};
+                s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v[k].z, v[k].w};
+            }
+        }
+    }
+}
+
+// Hops in direction MU = 2 or 3 of the LDS-staged streaming form: a
+// neighbour inside the block (every x3 neighbour; x2 neighbours except from
+// the block's first and last rows) comes from the slice's LDS copy, others
+// from memory.  l: the thread's local site index; rows of L3 sites.
+template <int PREC, int MU>
+__device__ __forceinline__ void hops_mu_lds(const Geom &g, const SpinorRef<PREC> &in, const GaugeRef<PREC> &U,
+                                            const LdsPsi<PREC> &lp, int p, int i, const int x[4], int l,
+                                            cplx<typename Real<PREC>::T> acc[4][3])
+{
+    using T = typename Real<PREC>::T;
+    const int L3 = g.L[3];
+    const int row = l / L3, rows = kBlock / L3;
+    cplx<T> s[4][3], u[3][3];
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    T ph = (T)1;
+    y[MU] = x[MU] + 1;
+    if (y[MU] == g.L[MU]) { y[MU] = 0; ph = (T)g.bc[MU]; }
+    int j = cb_index(g, y);
+    if (MU == 3) lp.load(l - x[3] + y[3], s);
+    else load_either(lp, in, row + 1 < rows, l + L3, 1 - p, j, g.S, s);
+    U.load(p, MU, i, u);
+    hop<T, MU, true>(acc, s, u, ph);
+    ph = (T)1;
+    y[MU] = x[MU] - 1;
+    if (y[MU] < 0) { y[MU] = g.L[MU] - 1; ph = (T)g.bc[MU]; }
+    j = cb_index(g, y);
+    if (MU == 3) lp.load(l - x[3] + y[3], s);
+    else load_either(lp, in, row > 0, l - L3, 1 - p, j, g.S, s);
+    U.load(1 - p, MU, j, u);
+    hop<T, MU, false>(acc, s, u, ph);
+}
+
 // Output of one site from v = (m0+4) d - acc/2 (the Wilson operator on the
 // site before Gamma_5) and |d|^2 of its centre d: applies Gamma_5, then the
 // mode's shift term, residual update or residual norm; stores the result and
@@ -320,14 +430,19 @@ __device__ __forceinline__ void tback_add(cplx<T> acc[4][3], const cplx<T> w[2][
 // hop's U_0(t)^H (1 + gamma_0) psi(t) is formed while slice t holds U_0(t)
 // and psi(t) in registers.  Requires L1*L2*L3 % 256 == 0 and Ts | L0.
 // WPE is the minimum number of waves per SIMD the build allows for (1 or 2);
-// the one-wave build overlaps pairs of time slices.
+// the one-wave build overlaps pairs of time slices.  STAGE (blocks of whole
+// x3 rows of consecutive x2 at one x1: kBlock % L3 == 0 and
+// L2*L3 % kBlock == 0) keeps each slice's centres in LDS, where the next
+// slice reads its x3 and in-block x2 neighbours.
 // Partial sums: slot lb holds the block's sum and the block zeroes the slots
 // lb + m*nblk_ts (m >= 1) below a.nblk, so all 2*nb slots per RHS are valid.
-template <int PREC, int MODE, bool G5, int WPE>
+template <int PREC, int MODE, bool G5, int WPE, bool STAGE>
 __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
 {
     using T = typename Real<PREC>::T;
     __shared__ double lds[8];
+    __shared__ typename LdsPsi<PREC>::E lds_psi[STAGE ? LdsPsi<PREC>::NC : 1][kBlock];
+    const LdsPsi<PREC> lp{lds_psi};
     const Geom &g = a.g;
     const int lbr = xcd_remap(blockIdx.x, gridDim.x);
     const int r = lbr % a.nrhs;
@@ -361,6 +476,10 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
         U.load(py, 0, iy, u);
         tback_half(w, sv, u);
     }
+    if (STAGE) {
+        lp.store(threadIdx.x, cen);
+        __syncthreads();
+    }
     double q0 = 0.0, q1 = 0.0;
 #pragma unroll(WPE == 1 ? 2 : 1)
     for (int k = 0; k < Ts; k++) {
@@ -375,8 +494,13 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
             for (int c = 0; c < 3; c++) acc[s][c] = {(T)0, (T)0};
         tback_add(acc, w, t == 0 ? (T)g.bc[0] : (T)1);
         hops_mu<PREC, 1>(g, in, U, p, i, x, acc);
-        hops_mu<PREC, 2>(g, in, U, p, i, x, acc);
-        hops_mu<PREC, 3>(g, in, U, p, i, x, acc);
+        if (STAGE) {
+            hops_mu_lds<PREC, 2>(g, in, U, lp, p, i, x, threadIdx.x, acc);
+            hops_mu_lds<PREC, 3>(g, in, U, lp, p, i, x, threadIdx.x, acc);
+        } else {
+            hops_mu<PREC, 2>(g, in, U, p, i, x, acc);
+            hops_mu<PREC, 3>(g, in, U, p, i, x, acc);
+        }
         // U_0(t): the next slice's carry from this centre, then the centre's
         // diagonal term; the centre is then dead before psi(t+1) arrives
         cplx<T> u[3][3];
@@ -399,6 +523,12 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
                 for (int c = 0; c < 3; c++) acc[s][c] = acc[s][c] + f[s][c];
         }
         site_out<PREC, MODE, G5>(a, r, p, i, shift_r, acc, dn2, q0, q1);
+        if (STAGE) {
+            // every thread has read this slice's copy: replace it by the next slice
+            __syncthreads();
+            lp.store(threadIdx.x, cen);
+            __syncthreads();
+        }
     }
     if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
         const int nq = MODE == W_NORM ? 2 : 1;

@@ -5,19 +5,19 @@
 
 namespace ovl {
 
-template <int PREC, int WPE>
-static void wilson_ts_dispatch_w(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
+template <int PREC, int WPE, bool STAGE>
+static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
 {
     if (g5) {
         switch (mode) {
-        case W_PLAIN: k_wilson_ts<PREC, W_PLAIN, true, WPE><<<grid, kBlock, 0, st>>>(a); break;
-        case W_NORM: k_wilson_ts<PREC, W_NORM, true, WPE><<<grid, kBlock, 0, st>>>(a); break;
-        case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true, WPE><<<grid, kBlock, 0, st>>>(a); break;
-        case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true, WPE><<<grid, kBlock, 0, st>>>(a); break;
-        default: k_wilson_ts<PREC, W_RESNORM, true, WPE><<<grid, kBlock, 0, st>>>(a); break;
+        case W_PLAIN: k_wilson_ts<PREC, W_PLAIN, true, WPE, STAGE><<<grid, kBlock, 0, st>>>(a); break;
+        case W_NORM: k_wilson_ts<PREC, W_NORM, true, WPE, STAGE><<<grid, kBlock, 0, st>>>(a); break;
+        case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true, WPE, STAGE><<<grid, kBlock, 0, st>>>(a); break;
+        case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true, WPE, STAGE><<<grid, kBlock, 0, st>>>(a); break;
+        default: k_wilson_ts<PREC, W_RESNORM, true, WPE, STAGE><<<grid, kBlock, 0, st>>>(a); break;
         }
     } else {
-        k_wilson_ts<PREC, W_PLAIN, false, WPE><<<grid, kBlock, 0, st>>>(a);
+        k_wilson_ts<PREC, W_PLAIN, false, WPE, STAGE><<<grid, kBlock, 0, st>>>(a);
     }
 }
 
@@ -25,11 +25,20 @@ static void wilson_ts_dispatch_w(int mode, bool g5, dim3 grid, const WArgs &a, h
 // SIMD, which may use the whole register file and overlaps two time slices;
 // larger grids take the two-wave build (measured at 32^3x64: 447 against
 // 456 us for FP64 with 256 blocks, 223 against 227 us for FP32 with 512).
+// The one-wave build also stages each slice in LDS when blocks hold whole
+// x3 rows of consecutive x2 at one x1, except in the residual-norm mode of
+// the verification (whose staged build spills registers).
 template <int PREC>
 static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
 {
-    if (grid.x <= 512) wilson_ts_dispatch_w<PREC, 1>(mode, g5, grid, a, st);
-    else wilson_ts_dispatch_w<PREC, 2>(mode, g5, grid, a, st);
+    const int L2 = a.g.L[2], L3 = a.g.L[3];
+    const bool rows = kBlock % L3 == 0 && (L2 * L3) % kBlock == 0;
+    if (grid.x <= 512) {
+        if (rows && mode != W_RESNORM) wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st);
+        else wilson_ts_dispatch_s<PREC, 1, false>(mode, g5, grid, a, st);
+    } else {
+        wilson_ts_dispatch_s<PREC, 2, false>(mode, g5, grid, a, st);
+    }
 }
 
 template <int PREC>

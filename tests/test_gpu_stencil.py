@@ -302,3 +302,29 @@ def test_autotune_keeps_results(ovl, dims, nrhs):
         got = out.to_canonical().cpu().numpy()
         for r in range(nrhs):
             assert rel(got[r], oracle.dw(olat, U, M0, psi[r])) < TOL[prec], (prec, r, res)
+
+
+# LDS-staged streaming form: blocks of whole x3 rows of consecutive x2 at one
+# x1 (256 % L3 == 0, L2*L3 % 256 == 0) and launches of at most 512 blocks
+STAGED_CASES = [((4, 2, 16, 16), 2), ((4, 4, 8, 32), 4), ((6, 2, 32, 8), 3), ((8, 2, 16, 16), 8), ((4, 4, 16, 16), 1)]
+
+
+@pytest.mark.parametrize("dims,ts", STAGED_CASES)
+@pytest.mark.parametrize("bc", [(-1, 1, 1, 1), (1, -1, -1, -1)])
+def test_staged_stream_matches_oracle(ovl, dims, ts, bc):
+    note(f"staged streaming dims={dims} stream={ts} bc={bc}")
+    lat, olat, U, G = setup(ovl, dims, seed=31, n_stout=1, bc=bc)
+    lat.stream_t = ts
+    lat.stream_t64 = ts
+    psi = synth.gaussian_spinor(lat.V, 32, 2)
+    for prec in (0, 1):
+        inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+        out = ovl.Spinor(lat, prec, 2)
+        ovl.wilson_apply(lat, G, M0, inp, out)
+        got = out.to_canonical().cpu().numpy()
+        for r in range(2):
+            assert rel(got[r], oracle.dw(olat, U, M0, psi[r])) < TOL[prec], (prec, r)
+        ovl.q2_apply(lat, G, M0, 0.29, inp, out)
+        got = out.to_canonical().cpu().numpy()
+        for r in range(2):
+            assert rel(got[r], oracle.q2(olat, U, M0, psi[r], 0.29)) < 2 * TOL[prec], (prec, r)

@@ -32,54 +32,62 @@ __global__ void k_blk_reset(Blk *bk, const MState *st, int nrhs, int nshift)
     }
 }
 
-// beta, beta_j, freezing, and the block coefficients; RHS blockIdx.x
+// beta, beta_j, freezing, and the block coefficients; RHS blockIdx.x, shift
+// j in thread j
 __global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const double *partials, int nblk)
 {
     __shared__ double lds[4];
     const int r = blockIdx.x;
+    const int j = threadIdx.x;
     if (st->skip[r]) return;
     double a = 0.0;
     for (int k = threadIdx.x; k < nblk; k += kBlock) a += partials[(size_t)r * nblk + k];
-    double rr_new = block_sum(a, lds);
-    if (threadIdx.x == 0) {
-        int it = ++st->iter[r];
-        if (!isfinite(rr_new)) {
+    const double rr_new = block_sum_all(a, lds);
+    const int it = st->iter[r] + 1;
+    if (!isfinite(rr_new)) {
+        if (j == 0) {
+            st->iter[r] = it;
             st->nonfinite[r] = 1;
             st->skip[r] = 1;
-            return;
         }
-        double beta = rr_new / st->rr[r];
+        return;
+    }
+    const double beta = rr_new / st->rr[r];
+    const double thr = st->tol2r[r] * st->bb[r];
+    const int t = bk->t[r];
+    int live = 0;
+    if (j < st->nshift && st->act_cur[r][j]) {
+        const double z = st->zeta[r][j], zn = st->zeta_new[r][j];
+        const double q = zn / z;
+        const double bj = beta * q * q;
+        const double aj = st->aj[r][j];
+        // x += a p^{(t)};  p^{(t+1)} = zn r^{(t+1)} + bj p^{(t)}
+        const double P = bk->P[r][j];
+        bk->XP[r][j] += aj * P;
+        bk->P[r][j] = bj * P;
+        for (int i = 1; i <= t; i++) {
+            const double c = bk->C[r][j][i];
+            bk->X[r][j][i] += aj * c;
+            bk->C[r][j][i] = bj * c;
+        }
+        bk->C[r][j][t + 1] = zn;
+        st->bj[r][j] = bj;
+        st->zeta_old[r][j] = z;
+        st->zeta[r][j] = zn;
+        if (zn * zn * rr_new <= thr) {
+            st->act[r][j] = 0;
+            st->frozen_at[r][j] = it;
+            st->frozen_rr[r][j] = zn * zn * rr_new;
+        } else {
+            live = 1;
+        }
+    }
+    // also the barrier between every thread's reads of rr, iter and t and
+    // thread 0's writes below
+    const int left = __syncthreads_count(live);
+    if (j == 0) {
+        st->iter[r] = it;
         st->beta[r] = beta;
-        const double thr = st->tol2r[r] * st->bb[r];
-        const int t = bk->t[r];
-        int left = 0;
-        for (int j = 0; j < st->nshift; j++) {
-            if (!st->act_cur[r][j]) continue;
-            double z = st->zeta[r][j], zn = st->zeta_new[r][j];
-            double q = zn / z;
-            double bj = beta * q * q;
-            double aj = st->aj[r][j];
-            // x += a p^{(t)};  p^{(t+1)} = zn r^{(t+1)} + bj p^{(t)}
-            double P = bk->P[r][j];
-            bk->XP[r][j] += aj * P;
-            bk->P[r][j] = bj * P;
-            for (int i = 1; i <= t; i++) {
-                double c = bk->C[r][j][i];
-                bk->X[r][j][i] += aj * c;
-                bk->C[r][j][i] = bj * c;
-            }
-            bk->C[r][j][t + 1] = zn;
-            st->bj[r][j] = bj;
-            st->zeta_old[r][j] = z;
-            st->zeta[r][j] = zn;
-            if (zn * zn * rr_new <= thr) {
-                st->act[r][j] = 0;
-                st->frozen_at[r][j] = it;
-                st->frozen_rr[r][j] = zn * zn * rr_new;
-            } else {
-                left++;
-            }
-        }
         bk->t[r] = t + 1;
         st->rr[r] = rr_new;
         st->alpha_old[r] = st->alpha[r];

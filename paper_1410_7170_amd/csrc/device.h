@@ -351,4 +351,18 @@ __device__ __forceinline__ double block_sum(double v, double *lds /* >= 4 */)
     return t;
 }
 
+// The same sum, valid in every thread (each adds the four wave sums in the
+// same order, so all threads hold the same bits as block_sum's thread 0).
+__device__ __forceinline__ double block_sum_all(double v, double *lds /* >= 4 */)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double t = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    __syncthreads();
+    return t;
+}
+
 }  // namespace ovl

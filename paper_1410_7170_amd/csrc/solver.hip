@@ -49,8 +49,9 @@ __global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *p
     __shared__ double lds[8];
     const int r = blockIdx.x;
     const int nr = st->nrhs;
+    const int j = threadIdx.x;   // shift j is thread j (NS <= 64: all in wave 0)
     if (st->skip[r]) {
-        if (threadIdx.x < NS) st->act_cur[r][threadIdx.x] = 0;
+        if (j < NS) st->act_cur[r][j] = 0;
         return;
     }
     double a = 0.0, b = 0.0;
@@ -58,66 +59,74 @@ __global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *p
         a += partials[(size_t)r * nblk + k];
         b += partials[(size_t)(nr + r) * nblk + k];
     }
-    double tt = block_sum(a, lds);
-    double pp = block_sum(b, lds + 4);
-    if (threadIdx.x == 0) {
-        double pq = tt + st->s0r[r] * pp;
-        double alpha = st->rr[r] / pq;
-        if (!isfinite(alpha) || !(pq > 0.0)) {
+    const double tt = block_sum_all(a, lds);
+    const double pp = block_sum_all(b, lds + 4);
+    const double pq = tt + st->s0r[r] * pp;
+    const double alpha = st->rr[r] / pq;
+    if (!isfinite(alpha) || !(pq > 0.0)) {
+        if (j < st->nshift) st->act_cur[r][j] = 0;
+        if (j == 0) {
             st->nonfinite[r] = 1;
             st->skip[r] = 1;
-            for (int j = 0; j < st->nshift; j++) st->act_cur[r][j] = 0;
-            return;
         }
-        st->alpha[r] = alpha;
-        const double ao = st->alpha_old[r], be = st->beta[r];
-        for (int j = 0; j < st->nshift; j++) {
-            int on = st->act[r][j];
-            st->act_cur[r][j] = on;
-            if (!on) continue;
-            double z = st->zeta[r][j], zo = st->zeta_old[r][j];
-            double zn = z * zo * ao / (alpha * be * (zo - z) + zo * ao * (1.0 + alpha * st->delta[j]));
+        return;
+    }
+    if (j == 0) st->alpha[r] = alpha;
+    if (j < st->nshift) {
+        const int on = st->act[r][j];
+        st->act_cur[r][j] = on;
+        if (on) {
+            const double ao = st->alpha_old[r], be = st->beta[r];
+            const double z = st->zeta[r][j], zo = st->zeta_old[r][j];
+            const double zn = z * zo * ao / (alpha * be * (zo - z) + zo * ao * (1.0 + alpha * st->delta[j]));
             st->zeta_new[r][j] = zn;
             st->aj[r][j] = alpha * zn / z;
         }
     }
 }
 
-// beta, beta_j, freezing; RHS blockIdx.x
+// beta, beta_j, freezing; RHS blockIdx.x, shift j in thread j
 __global__ __launch_bounds__(kBlock) void k_ms_beta(MState *st, const double *partials, int nblk)
 {
     __shared__ double lds[4];
     const int r = blockIdx.x;
+    const int j = threadIdx.x;
     if (st->skip[r]) return;
     double a = 0.0;
     for (int k = threadIdx.x; k < nblk; k += kBlock) a += partials[(size_t)r * nblk + k];
-    double rr_new = block_sum(a, lds);
-    if (threadIdx.x == 0) {
-        int it = ++st->iter[r];
-        if (!isfinite(rr_new)) {
+    const double rr_new = block_sum_all(a, lds);
+    const int it = st->iter[r] + 1;
+    if (!isfinite(rr_new)) {
+        if (j == 0) {
+            st->iter[r] = it;
             st->nonfinite[r] = 1;
             st->skip[r] = 1;
-            return;
         }
-        double beta = rr_new / st->rr[r];
+        return;
+    }
+    const double beta = rr_new / st->rr[r];
+    const double thr = st->tol2r[r] * st->bb[r];
+    int live = 0;
+    if (j < st->nshift && st->act_cur[r][j]) {
+        const double z = st->zeta[r][j], zn = st->zeta_new[r][j];
+        const double q = zn / z;
+        st->bj[r][j] = beta * q * q;
+        st->zeta_old[r][j] = z;
+        st->zeta[r][j] = zn;
+        if (zn * zn * rr_new <= thr) {
+            st->act[r][j] = 0;
+            st->frozen_at[r][j] = it;
+            st->frozen_rr[r][j] = zn * zn * rr_new;
+        } else {
+            live = 1;
+        }
+    }
+    // also the barrier between every thread's reads of rr and iter and
+    // thread 0's writes below
+    const int left = __syncthreads_count(live);
+    if (j == 0) {
+        st->iter[r] = it;
         st->beta[r] = beta;
-        const double thr = st->tol2r[r] * st->bb[r];
-        int left = 0;
-        for (int j = 0; j < st->nshift; j++) {
-            if (!st->act_cur[r][j]) continue;
-            double z = st->zeta[r][j], zn = st->zeta_new[r][j];
-            double q = zn / z;
-            st->bj[r][j] = beta * q * q;
-            st->zeta_old[r][j] = z;
-            st->zeta[r][j] = zn;
-            if (zn * zn * rr_new <= thr) {
-                st->act[r][j] = 0;
-                st->frozen_at[r][j] = it;
-                st->frozen_rr[r][j] = zn * zn * rr_new;
-            } else {
-                left++;
-            }
-        }
         st->rr[r] = rr_new;
         st->alpha_old[r] = st->alpha[r];
         if (!left) st->skip[r] = 1;

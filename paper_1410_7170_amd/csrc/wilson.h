@@ -264,7 +264,7 @@ __device__ __forceinline__ void hops_mu_lds(const Geom &g, const SpinorRef<PREC>
 // mode's shift term, residual update or residual norm; stores the result and
 // adds the site's norms to q0, q1.
 template <int PREC, int MODE, bool G5>
-__device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, double shift_r,
+__device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, double shift_r, double rin_s,
                                          cplx<typename Real<PREC>::T> o[4][3], typename Real<PREC>::T dn2,
                                          double &q0, double &q1)
 {
@@ -313,7 +313,7 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
     } else if (MODE == W_RESNORM) {
         cplx<T> rv[4][3];
         spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load(p, i, rv);
-        const T rs = a.rin_scale ? (T)a.rin_scale[r] : (T)1;
+        const T rs = (T)rin_s;
         T n0 = 0;
 #pragma unroll
         for (int s = 0; s < 4; s++)
@@ -356,6 +356,10 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
     // the epilogue's shift, read once up front (a uniform scalar)
     constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
     const double shift_r = kShift ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
+    // the residual norm's scale of rin, likewise read once up front (a load
+    // left inside the epilogue behind the null test made the compiler keep far
+    // more values live across the hops and spill)
+    const double rin_s = MODE == W_RESNORM && a.rin_scale ? a.rin_scale[r] : 1.0;
     const int p = lb & 1;
     const int jl = (lb >> 1) * kBlock + threadIdx.x;
     const Geom &g = a.g;
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         cplx<T> d[4][3];
         in.load(p, i, d);
         const T dn2 = diag_minus_half(acc, d, (T)a.diag);
-        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, acc, dn2, q0, q1);
+        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, rin_s, acc, dn2, q0, q1);
     }
     if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
         double t0 = block_sum(q0, lds);
@@ -451,6 +455,10 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
     if (a.skip && a.skip[r]) return;
     constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
     const double shift_r = kShift ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
+    // the residual norm's scale of rin, likewise read once up front (a load
+    // left inside the epilogue behind the null test made the compiler keep far
+    // more values live across the hops and spill)
+    const double rin_s = MODE == W_RESNORM && a.rin_scale ? a.rin_scale[r] : 1.0;
     const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
     const int nsb = L1 * L2 * L3 / kBlock;
     const int sb = lb % nsb, tc = lb / nsb;
@@ -522,7 +530,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; c++) acc[s][c] = acc[s][c] + f[s][c];
         }
-        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, acc, dn2, q0, q1);
+        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, rin_s, acc, dn2, q0, q1);
         if (STAGE) {
             // every thread has read this slice's copy: replace it by the next slice
             __syncthreads();

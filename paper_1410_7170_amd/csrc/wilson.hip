@@ -26,15 +26,14 @@ static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, h
 // larger grids take the two-wave build (measured at 32^3x64: 447 against
 // 456 us for FP64 with 256 blocks, 223 against 227 us for FP32 with 512).
 // The one-wave build also stages each slice in LDS when blocks hold whole
-// x3 rows of consecutive x2 at one x1, except in the residual-norm mode of
-// the verification (whose staged build spills registers).
+// x3 rows of consecutive x2 at one x1.
 template <int PREC>
 static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
 {
     const int L2 = a.g.L[2], L3 = a.g.L[3];
     const bool rows = kBlock % L3 == 0 && (L2 * L3) % kBlock == 0;
     if (grid.x <= 512) {
-        if (rows && mode != W_RESNORM) wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st);
+        if (rows) wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st);
         else wilson_ts_dispatch_s<PREC, 1, false>(mode, g5, grid, a, st);
     } else {
         wilson_ts_dispatch_s<PREC, 2, false>(mode, g5, grid, a, st);

@@ -69,6 +69,7 @@ extern "C" {
 
 #define OVL_MAX_SHIFTS 32
 #define OVL_MAX_RHS 16
+#define OVL_MAX_BLOCK 32   /* longest block length of ovl_solver_params.block */
 
 enum ovl_status {
     OVL_OK = 0,
@@ -150,7 +151,7 @@ typedef struct {
     int32_t profile;         /* bracket the solver's kernels with HIP events on
                                 the call's stream and fill the kernel_* stats */
     int32_t block;           /* FP64 mode: 0 updates every shifted vector in every
-                                iteration; m = 1..16 keeps the last m residuals
+                                iteration; m = 1..OVL_MAX_BLOCK keeps the last m residuals
                                 and updates each shifted vector once per m
                                 iterations (same iterates, fewer vector passes).
                                 Mixed mode: block length, 0 meaning 16 */

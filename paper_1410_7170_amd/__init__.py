@@ -33,7 +33,7 @@ F64, F32, F16S = 0, 1, 2
 SOLVE_F64, SOLVE_MIXED = 0, 1
 OP_Q2, OP_LANCZOS, OP_MSCG, OP_TUNE = 0, 1, 2, 3
 K_STENCIL, K_UPDATE, K_SCALAR, K_OTHER = 0, 1, 2, 3
-MAX_SHIFTS, MAX_RHS = 32, 16
+MAX_SHIFTS, MAX_RHS, MAX_BLOCK = 32, 16, 32
 PREC_NAMES = {F64: "f64", F32: "f32", F16S: "f16s"}
 
 c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p

@@ -77,7 +77,7 @@ bool params_ok(const ovl_solver_params *p)
 {
     return p && p->tol > 0.0 && std::isfinite(p->tol) && p->maxiter >= 1 &&
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED) && p->reliable_delta > 0.0 &&
-           p->reliable_delta < 1.0 && p->block >= 0 && p->block <= 16 && p->sloppy_below >= 0.0 &&
+           p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
            p->sloppy_below < 1.0;
 }
 
@@ -263,7 +263,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
     if (op == OVL_OP_LANCZOS) return lanczos_ws_bytes(L);
     if (op == OVL_OP_TUNE) return tune_ws_bytes(L, nrhs);
     if (op == OVL_OP_MSCG) {
-        if (nshift < 1 || nshift > OVL_MAX_SHIFTS) return 0;
+        if (nshift < 1 || nshift > OVL_MAX_SHIFTS || (prm && !params_ok(prm))) return 0;
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_MIXED)
             return yb + mixed_ws_bytes(L, nrhs, nshift, prm->block > 0 ? prm->block : 16, prm->sloppy_below > 0.0);

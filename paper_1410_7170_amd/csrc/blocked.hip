@@ -33,8 +33,9 @@ __global__ void k_blk_reset(Blk *bk, const MState *st, int nrhs, int nshift)
 }
 
 // beta, beta_j, freezing, and the block coefficients; RHS blockIdx.x, shift
-// j in thread j
-__global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const double *partials, int nblk)
+// j in thread j.  sw2 > 0: an RHS with |r|^2 <= sw2 |b|^2 pauses (hand-over).
+__global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const double *partials, int nblk,
+                                                     double sw2)
 {
     __shared__ double lds[4];
     const int r = blockIdx.x;
@@ -91,7 +92,13 @@ __global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const 
         bk->t[r] = t + 1;
         st->rr[r] = rr_new;
         st->alpha_old[r] = st->alpha[r];
-        if (!left) st->skip[r] = 1;
+        st->run_c[r] = left ? 1 : 0;
+        if (!left) {
+            st->skip[r] = 1;
+        } else if (sw2 > 0.0 && rr_new <= sw2 * st->bb[r]) {
+            st->paused[r] = 1;
+            st->skip[r] = 1;
+        }
     }
 }
 
@@ -107,6 +114,7 @@ struct El<P_F64> {
     static constexpr int C = 1;    // complex numbers per element
     __device__ static void get(const V &v, double *re, double *im) { re[0] = v.x; im[0] = v.y; }
     __device__ static V put(const double *re, const double *im) { return make_double2(re[0], im[0]); }
+    __device__ static V fresh(const V &v) { return v; }
 };
 template <>
 struct El<P_F32> {
@@ -121,16 +129,26 @@ struct El<P_F32> {
     {
         return make_float4((float)re[0], (float)im[0], (float)re[1], (float)im[1]);
     }
+    // A copy the compiler cannot see through (an empty asm statement), so
+    // the widening of a value held across a loop stays inside the loop instead
+    // of being hoisted, which would hold the value twice as wide in registers.
+    __device__ static V fresh(const V &v)
+    {
+        V c = v;
+        asm volatile("" : "+v"(c.x), "+v"(c.y), "+v"(c.z), "+v"(c.w));
+        return c;
+    }
 };
 
-// p0 = r_new + beta p0 on RHS that are still iterating
+// p0 = r_new + beta p0 on RHS that are still iterating or paused in this
+// iteration (run_c)
 template <int PS>
 __global__ __launch_bounds__(kBlock) void k_base_p(Geom g, int nb, const MState *st, const void *rnv, void *p0v)
 {
     using E = El<PS>;
     using V = typename E::V;
     const int r = blockIdx.y;
-    if (st->skip[r]) return;
+    if (!st->run_c[r]) return;
     const int b = blockIdx.x;
     const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
@@ -158,14 +176,14 @@ struct RingPtrs {
 
 // The block pass.  Sloppy fields (ring, p_j) in precision PS; x_j and y are
 // FP64.  y mode (xf == null): y_r += sum_j w_j dx_j; x mode: x_j += dx_j.
-template <int PS>
+template <int PS, int MBT>
 __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
                                                      ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs)
 {
     using E = El<PS>;
     using V = typename E::V;
     __shared__ double sP[NS], sXP[NS], sW[NS];
-    __shared__ double sC[NS][MB + 1], sX[NS][MB + 1];
+    __shared__ double sC[NS][MBT + 1], sX[NS][MBT + 1];
     __shared__ int sj[NS], sact[NS];
     __shared__ int sn;
     const int r = blockIdx.y;
@@ -186,8 +204,8 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     }
     __syncthreads();
     const int n = sn;
-    for (int k = threadIdx.x; k < n * (MB + 1); k += kBlock) {
-        int q = k / (MB + 1), i = k % (MB + 1);
+    for (int k = threadIdx.x; k < n * (MBT + 1); k += kBlock) {
+        int q = k / (MBT + 1), i = k % (MBT + 1);
         sC[q][i] = bk->C[r][sj[q]][i];
         sX[q][i] = bk->X[r][sj[q]][i];
     }
@@ -203,10 +221,12 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     const size_t site64 = (size_t)p * 12 * g.S + i;
     for (int e = 0; e < E::N; e++) {
         const size_t off = site + (size_t)e * g.S;
-        double rre[MB][E::C], rim[MB][E::C];
+        // the block's residuals stay in their storage precision in registers
+        // (4 VGPRs per slot) and are widened where they are used
+        V rv[MBT];
 #pragma unroll
-        for (int q = 0; q < MB; q++)
-            if (q < T) E::get(((const V *)ring.slot[q + 1])[(size_t)r * FS + off], rre[q], rim[q]);
+        for (int q = 0; q < MBT; q++)
+            if (q < T) rv[q] = ((const V *)ring.slot[q + 1])[(size_t)r * FS + off];
         double yre[E::C], yim[E::C];
 #pragma unroll
         for (int c = 0; c < E::C; c++) yre[c] = yim[c] = 0.0;
@@ -224,15 +244,17 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
                 pni[c] = sP[q] * pim[c];
             }
 #pragma unroll
-            for (int t = 0; t < MB; t++)
+            for (int t = 0; t < MBT; t++)
                 if (t < T) {
                     const double xc = sX[q][t + 1], cc = sC[q][t + 1];
+                    double rre[E::C], rim[E::C];
+                    E::get(E::fresh(rv[t]), rre, rim);
 #pragma unroll
                     for (int c = 0; c < E::C; c++) {
-                        dxr[c] = fma(xc, rre[t][c], dxr[c]);
-                        dxi[c] = fma(xc, rim[t][c], dxi[c]);
-                        pnr[c] = fma(cc, rre[t][c], pnr[c]);
-                        pni[c] = fma(cc, rim[t][c], pni[c]);
+                        dxr[c] = fma(xc, rre[c], dxr[c]);
+                        dxi[c] = fma(xc, rim[c], dxi[c]);
+                        pnr[c] = fma(cc, rre[c], pnr[c]);
+                        pni[c] = fma(cc, rim[c], pni[c]);
                     }
                 }
             if (sact[q]) *pp = E::put(pnr, pni);
@@ -306,7 +328,13 @@ __global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const doub
 __global__ void k_resume(MState *st, int nrhs)
 {
     int r = threadIdx.x;
-    if (r < nrhs) st->rr_ref[r] = st->rr[r];
+    if (r < nrhs) {
+        st->rr_ref[r] = st->rr[r];
+        if (st->paused[r]) {
+            st->paused[r] = 0;
+            st->skip[r] = 0;
+        }
+    }
 }
 
 // after a residual replacement: rr = rr_ref = |r_hi|^2 for RHS still iterating
@@ -445,7 +473,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             B.out = slot(k + 1);
             OVL_HIP(launch_wilson(L, PS, W_RUPDATE, true, B, st));
             int e3 = prof.mark();
-            k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk);
+            k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk, sw2);
             int e4 = prof.mark();
             k_base_p<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), p0.d);
             int e5 = prof.mark();
@@ -460,7 +488,10 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         RingPtrs rp;
         for (int i = 0; i <= MB; i++) rp.slot[i] = slot((k - batch + i + (m + 1)) % (m + 1));
         int e6 = prof.mark();
-        k_blk_pass<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R);
+        // blocks of up to 16 take the build that holds 16 residuals in
+        // registers (more waves per SIMD)
+        if (m <= 16) k_blk_pass<PS, 16><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R);
+        else k_blk_pass<PS, MB><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R);
         int e7 = prof.mark();
         k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
         OVL_HIP(hipGetLastError());
@@ -468,13 +499,17 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         passes++;
         OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
         OVL_HIP(hipStreamSynchronize(st));
+        // an RHS is finished (skip without pause), paused at the hand-over
+        // level (k_blk_beta stops it at the iteration it gets there) or open;
+        // the hand-over comes once no RHS is open
         done = true;
         bool want = false;
         switched = sw2 > 0.0;
         for (int q = 0; q < R; q++) {
-            done = done && h.skip[q];
+            const bool fin = h.skip[q] && !h.paused[q];
+            done = done && fin;
             if (!h.skip[q] && h.rr[q] < rd2 * h.rr_ref[q]) want = true;
-            if (!h.skip[q] && !(h.rr[q] <= sw2 * h.bb[q])) switched = false;
+            if (!fin && !h.paused[q]) switched = false;
         }
         switched = switched && !done;
         if (o.reliable && want && !done && !switched) {
@@ -528,6 +563,14 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     if (o.iters_out)
         for (int q = 0; q < R; q++) o.iters_out[q] = h.iter[q] - it0[q];
     if (scr && switched) {
+        // RHS q stopped after it_q iterations of this solve, so its residual
+        // is in ring slot it_q; gather every RHS's residual into slot k
+        for (int q = 0; q < R; q++) {
+            const long kq = h.iter[q] - it0[q];
+            if (kq >= 0 && kq % (m + 1) != k % (m + 1))
+                OVL_HIP(hipMemcpyAsync((char *)slot(k) + FS * q, (const char *)slot(kq) + FS * q, FS,
+                                       hipMemcpyDeviceToDevice, st));
+        }
         scr->S = S;
         scr->r = Fld{slot(k), nullptr, PS, R};
         scr->p0 = p0;

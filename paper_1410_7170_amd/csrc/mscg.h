@@ -9,7 +9,7 @@ namespace ovl {
 
 constexpr int NR = OVL_MAX_RHS;
 constexpr int NS = OVL_MAX_SHIFTS;
-constexpr int MB = 16;   // longest block of the blocked shift update
+constexpr int MB = OVL_MAX_BLOCK;   // longest block of the blocked shift update
 
 inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
@@ -56,6 +56,11 @@ struct MState {
     // reliable-update bookkeeping (mixed solver)
     double rr_ref[NR];     // |r|^2 at the last residual replacement
     int want_update[NR];
+    // hand-over to another precision: an RHS whose base residual reached the
+    // hand-over level stops (skip set, paused set) until the solve that
+    // continues its recurrences clears both
+    int paused[NR];
+    int run_c[NR];         // the iteration's p0 update is due (set by K_b, cleared by K_a)
 };
 
 struct ShiftWeights {
@@ -72,10 +77,11 @@ struct BlkOpts {
     const double *rhs_tol = nullptr;    // per-RHS tolerance (host), default prm->tol
     Fld x_ext{};                        // x mode: caller's FP64 x_j (field j*nrhs + r)
     int *iters_out = nullptr;           // per-RHS iteration counts (host)
-    // Stop at the first block end at which every unfinished RHS has
-    // |r| <= switch_rel |b| and return kSwitched, leaving the recurrences
-    // (scalars, r, p0, p_j; x_j in x mode) in the workspace for a solve in
-    // another precision to continue (0: run to convergence).
+    // Each RHS stops at the iteration at which |r| <= switch_rel |b| (the
+    // block pass then covers the iterations it did); once no unfinished RHS
+    // is still iterating, return kSwitched, leaving the recurrences (scalars,
+    // r, p0, p_j; x_j in x mode) in the workspace for a solve in another
+    // precision to continue (0: run to convergence).
     double switch_rel = 0.0;
     const struct MsScratch *resume = nullptr;   // continue the recurrences of a switched solve
 };

@@ -50,6 +50,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *p
     const int r = blockIdx.x;
     const int nr = st->nrhs;
     const int j = threadIdx.x;   // shift j is thread j (NS <= 64: all in wave 0)
+    // the previous iteration's p0 update has run (stream order)
+    if (j == 0) st->run_c[r] = 0;
     if (st->skip[r]) {
         if (j < NS) st->act_cur[r][j] = 0;
         return;

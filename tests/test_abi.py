@@ -68,6 +68,13 @@ def test_sizes(ovl):
     assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, p) > 40 * 256 * 192
     assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 0, p) == 0
     assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 17, 4, p) == 0
+    # the block length runs up to OVL_MAX_BLOCK; a longer one is rejected
+    pm = ovl.default_params(mode=ovl.SOLVE_MIXED, block=16)
+    w16 = ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm)
+    pm.block = ovl.MAX_BLOCK
+    assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm) > w16 > 0
+    pm.block = ovl.MAX_BLOCK + 1
+    assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm) == 0
 
 
 def test_null_and_alias_rejected_before_launch(ovl):

@@ -139,3 +139,30 @@ def test_mixed_fp64_phase_cuts_refinement(ovl):
     assert rel(runs[1e-4][1], ref) < 1e-9
     assert runs[1e-4][0]["refine_iterations"] < runs[0.0][0]["refine_iterations"]
     assert abs(runs[1e-4][0]["iterations"][0] - st64["iterations"][0]) <= 8
+
+
+def test_mixed_handover_per_rhs_long_blocks(ovl):
+    """Three RHS that reach the hand-over level at different iterations (two
+    Gaussian sources and a point source), blocks of the longest length: each
+    RHS stops its FP64 phase at its own iteration and waits for the others, so
+    every shifted residual still meets tol, D_ov agrees with the FP64 blocked
+    solver, and each RHS takes about the FP64 solver's iterations."""
+    dims = (16, 8, 8, 8)
+    note(f"mixed per-RHS hand-over {dims} block={ovl.MAX_BLOCK}")
+    U, lat, olat, G, (s, w), _ = setup(ovl, dims, 341)
+    b = np.concatenate([synth.gaussian_spinor(lat.V, 342, 2),
+                        synth.point_sources(lat.V, synth.random_site(lat.V, 343))[:1]])
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0, 3)
+    prm = ovl.default_params(tol=1e-10, maxiter=5000, mode=ovl.SOLVE_MIXED, block=ovl.MAX_BLOCK,
+                             sloppy_below=1e-4)
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, prm)
+    O64 = ovl.Spinor(lat, 0, 3)
+    st64 = ovl.overlap_apply(lat, G, RHO, s, w, B, O64,
+                             ovl.default_params(tol=1e-10, maxiter=5000, block=ovl.MAX_BLOCK))
+    got, ref = O.to_canonical().cpu().numpy(), O64.to_canonical().cpu().numpy()
+    for r in range(3):
+        tr = np.array(st["true_residual"][r])
+        assert (tr > 0).all() and (tr <= 1e-10).all(), (r, tr)
+        assert rel(got[r], ref[r]) < 1e-9, r
+        assert abs(st["iterations"][r] - st64["iterations"][r]) <= 8, (r, st["iterations"], st64["iterations"])

@@ -71,7 +71,7 @@ def test_spectral_bounds_bracket_exact_spectrum(ovl):
     assert lo2 < aw.min() and hi2 > aw.max()
 
 
-@pytest.mark.parametrize("block", [0, 1, 5, 8, 16])
+@pytest.mark.parametrize("block", [0, 1, 5, 8, 16, 32])
 def test_multishift_cg_matches_oracle(ovl, block):
     """Per-shift solutions of the plain (block 0) and blocked shift updates
     against the oracle's multishift CG and its true residuals."""

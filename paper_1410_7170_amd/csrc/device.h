@@ -43,6 +43,30 @@ __device__ __forceinline__ cplx<T> cmc(cplx<T> a, cplx<T> b)
 {
     return {fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -a.y * b.x)};
 }
+// acc + a*b, acc + conj(a)*b and acc - a*b as four fused multiply-adds
+// (sums of products chain through the accumulator instead of adding
+// separately rounded products)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmac(cplx<T> acc, cplx<T> a, cplx<T> b)
+{
+    return {fma(-a.y, b.y, fma(a.x, b.x, acc.x)), fma(a.y, b.x, fma(a.x, b.y, acc.y))};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmacc(cplx<T> acc, cplx<T> a, cplx<T> b)
+{
+    return {fma(a.y, b.y, fma(a.x, b.x, acc.x)), fma(-a.y, b.x, fma(a.x, b.y, acc.y))};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmsub(cplx<T> acc, cplx<T> a, cplx<T> b)
+{
+    return {fma(a.y, b.y, fma(-a.x, b.x, acc.x)), fma(-a.y, b.x, fma(-a.x, b.y, acc.y))};
+}
+// acc + s*a for a real s
+template <typename T>
+__device__ __forceinline__ cplx<T> fmac(cplx<T> acc, T s, cplx<T> a)
+{
+    return {fma(s, a.x, acc.x), fma(s, a.y, acc.y)};
+}
 template <typename T>
 __device__ __forceinline__ T norm2(cplx<T> a) { return fma(a.x, a.x, a.y * a.y); }
 
@@ -275,9 +299,9 @@ struct GaugeRef;
 template <typename T>
 __device__ __forceinline__ void rebuild_row2(cplx<T> u[3][3])
 {
-    cplx<T> a = cm(u[0][1], u[1][2]) - cm(u[0][2], u[1][1]);
-    cplx<T> b = cm(u[0][2], u[1][0]) - cm(u[0][0], u[1][2]);
-    cplx<T> c = cm(u[0][0], u[1][1]) - cm(u[0][1], u[1][0]);
+    cplx<T> a = cmsub(cm(u[0][1], u[1][2]), u[0][2], u[1][1]);
+    cplx<T> b = cmsub(cm(u[0][2], u[1][0]), u[0][0], u[1][2]);
+    cplx<T> c = cmsub(cm(u[0][0], u[1][1]), u[0][1], u[1][0]);
     u[2][0] = {a.x, -a.y};
     u[2][1] = {b.x, -b.y};
     u[2][2] = {c.x, -c.y};

@@ -95,31 +95,34 @@ __device__ __forceinline__ void hop(cplx<T> acc[4][3], const cplx<T> s[4][3], co
             cplx<T> t;
             if (FWD) {
                 t = cm(u[c][0], h[a][0]);
-                t = t + cm(u[c][1], h[a][1]);
-                t = t + cm(u[c][2], h[a][2]);
+                t = cmac(t, u[c][1], h[a][1]);
+                t = cmac(t, u[c][2], h[a][2]);
             } else {
                 t = cmc(u[0][c], h[a][0]);
-                t = t + cmc(u[1][c], h[a][1]);
-                t = t + cmc(u[2][c], h[a][2]);
+                t = cmacc(t, u[1][c], h[a][1]);
+                t = cmacc(t, u[2][c], h[a][2]);
             }
-            w[a][c] = ph * t;
+            w[a][c] = t;
         }
+    // the phase enters as the factor of each accumulation (a fused
+    // multiply-add in place of an add, no separate scaling of w)
+    const T mh = -ph;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        acc[0][c] = acc[0][c] + w[0][c];
-        acc[1][c] = acc[1][c] + w[1][c];
+        acc[0][c] = fmac(acc[0][c], ph, w[0][c]);
+        acc[1][c] = fmac(acc[1][c], ph, w[1][c]);
         if (MU == 0) {
-            acc[2][c] = FWD ? acc[2][c] - w[0][c] : acc[2][c] + w[0][c];
-            acc[3][c] = FWD ? acc[3][c] - w[1][c] : acc[3][c] + w[1][c];
+            acc[2][c] = fmac(acc[2][c], FWD ? mh : ph, w[0][c]);
+            acc[3][c] = fmac(acc[3][c], FWD ? mh : ph, w[1][c]);
         } else if (MU == 1) {
-            acc[2][c] = acc[2][c] + (FWD ? tmi(w[1][c]) : ti(w[1][c]));
-            acc[3][c] = acc[3][c] + (FWD ? tmi(w[0][c]) : ti(w[0][c]));
+            acc[2][c] = fmac(acc[2][c], ph, FWD ? tmi(w[1][c]) : ti(w[1][c]));
+            acc[3][c] = fmac(acc[3][c], ph, FWD ? tmi(w[0][c]) : ti(w[0][c]));
         } else if (MU == 2) {
-            acc[2][c] = FWD ? acc[2][c] - w[1][c] : acc[2][c] + w[1][c];
-            acc[3][c] = FWD ? acc[3][c] + w[0][c] : acc[3][c] - w[0][c];
+            acc[2][c] = fmac(acc[2][c], FWD ? mh : ph, w[1][c]);
+            acc[3][c] = fmac(acc[3][c], FWD ? ph : mh, w[0][c]);
         } else {
-            acc[2][c] = acc[2][c] + (FWD ? tmi(w[0][c]) : ti(w[0][c]));
-            acc[3][c] = acc[3][c] + (FWD ? ti(w[1][c]) : tmi(w[1][c]));
+            acc[2][c] = fmac(acc[2][c], ph, FWD ? tmi(w[0][c]) : ti(w[0][c]));
+            acc[3][c] = fmac(acc[3][c], ph, FWD ? ti(w[1][c]) : tmi(w[1][c]));
         }
     }
 }
@@ -409,7 +412,7 @@ __device__ __forceinline__ void tback_half(cplx<T> w[2][3], const cplx<T> s[4][3
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) w[a][c] = cmc(u[0][c], h[a][0]) + cmc(u[1][c], h[a][1]) + cmc(u[2][c], h[a][2]);
+        for (int c = 0; c < 3; c++) w[a][c] = cmacc(cmacc(cmc(u[0][c], h[a][0]), u[1][c], h[a][1]), u[2][c], h[a][2]);
 }
 
 template <typename T>
@@ -417,10 +420,10 @@ __device__ __forceinline__ void tback_add(cplx<T> acc[4][3], const cplx<T> w[2][
 {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        acc[0][c] = acc[0][c] + ph * w[0][c];
-        acc[1][c] = acc[1][c] + ph * w[1][c];
-        acc[2][c] = acc[2][c] + ph * w[0][c];
-        acc[3][c] = acc[3][c] + ph * w[1][c];
+        acc[0][c] = fmac(acc[0][c], ph, w[0][c]);
+        acc[1][c] = fmac(acc[1][c], ph, w[1][c]);
+        acc[2][c] = fmac(acc[2][c], ph, w[0][c]);
+        acc[3][c] = fmac(acc[3][c], ph, w[1][c]);
     }
 }
 

@@ -176,9 +176,13 @@ struct RingPtrs {
 
 // The block pass.  Sloppy fields (ring, p_j) in precision PS; x_j and y are
 // FP64.  y mode (xf == null): y_r += sum_j w_j dx_j; x mode: x_j += dx_j.
+// first: the first pass of a fresh solve, where every p_j still equals b
+// (ring slot 0): it is read from there, and written for every shift of the
+// block.
 template <int PS, int MBT>
 __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
-                                                     ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs)
+                                                     ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs,
+                                                     int first)
 {
     using E = El<PS>;
     using V = typename E::V;
@@ -227,6 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
 #pragma unroll
         for (int q = 0; q < MBT; q++)
             if (q < T) rv[q] = ((const V *)ring.slot[q + 1])[(size_t)r * FS + off];
+        V pb{};
+        if (first) pb = ((const V *)ring.slot[0])[(size_t)r * FS + off];
         double yre[E::C], yim[E::C];
 #pragma unroll
         for (int c = 0; c < E::C; c++) yre[c] = yim[c] = 0.0;
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
             const int j = sj[q];
             V *pp = pf + ((size_t)j * nrhs + r) * FS + off;
             double pre[E::C], pim[E::C];
-            E::get(*pp, pre, pim);
+            E::get(first ? pb : *pp, pre, pim);
             double dxr[E::C], dxi[E::C], pnr[E::C], pni[E::C];
 #pragma unroll
             for (int c = 0; c < E::C; c++) {
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
                         pni[c] = fma(cc, rim[c], pni[c]);
                     }
                 }
-            if (sact[q]) *pp = E::put(pnr, pni);
+            if (sact[q] || first) *pp = E::put(pnr, pni);
             if (xf) {
                 double2 *xp = xf + ((size_t)j * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
 #pragma unroll
@@ -284,10 +290,13 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     }
 }
 
-// ring slot 0 = b, p0 = b, p_j = b (precision PS), and y = 0 or x_j = 0 (FP64)
+// ring slot 0 = b, p0 = b (precision PS), and y = 0 or x_j = 0 (FP64).  The
+// p_j (= b) are left to the first block pass, which reads b from slot 0;
+// only an RHS that is finished from the start (b = 0) gets them here.
 template <int PS>
-__global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const double2 *b, void *r0v, void *p0v, void *pfv,
-                                                      double2 *xf, double2 *y, int nrhs, int nshift)
+__global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const MState *st, const double2 *b, void *r0v,
+                                                      void *p0v, void *pfv, double2 *xf, double2 *y, int nrhs,
+                                                      int nshift)
 {
     using E = El<PS>;
     using V = typename E::V;
@@ -313,7 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const doub
         const size_t o = off + (size_t)e * g.S;
         r0[o] = v;
         p0[o] = v;
-        for (int j = 0; j < nshift; j++) pf[(size_t)j * nrhs * FS + o] = v;
+        if (st->skip[rr])
+            for (int j = 0; j < nshift; j++) pf[(size_t)j * nrhs * FS + o] = v;
     }
     for (int c = 0; c < 12; c++) {
         const size_t o64 = off64 + (size_t)c * g.S;
@@ -429,7 +439,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     } else {
         int rc = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st, o.rhs_shift, o.rhs_tol);
         if (rc) return rc;
-        k_blk_start<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, (const double2 *)b.d, slot(0), p0.d, pj.d, xf, y, R,
+        k_blk_start<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, (const double2 *)b.d, slot(0), p0.d, pj.d, xf, y, R,
                                                   nshift);
     }
     k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
@@ -490,8 +500,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         int e6 = prof.mark();
         // blocks of up to 16 take the build that holds 16 residuals in
         // registers (more waves per SIMD)
-        if (m <= 16) k_blk_pass<PS, 16><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R);
-        else k_blk_pass<PS, MB><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R);
+        const int first = !o.resume && passes == 0;
+        if (m <= 16) k_blk_pass<PS, 16><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first);
+        else k_blk_pass<PS, MB><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first);
         int e7 = prof.mark();
         k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
         OVL_HIP(hipGetLastError());
@@ -585,15 +596,19 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         // active up to iteration f takes part in ceil(f/m) passes, reading p_j
         // in each and writing it in all but the last (x mode also reads and
         // writes the FP64 x_j each time); y mode reads and writes y once per pass.
+        // A fresh solve's first pass reads b once per RHS in place of the p_j
+        // and writes every p_j.
         const double Fs = (double)FS, F8 = (double)F;
         const double G = (double)L.V * 4 * (PS == P_F64 ? 96.0 : 48.0);
+        const bool fresh = !o.resume;
         double sten = iters_all * (6 * Fs + 2 * G);
         double upd = iters_all * 3 * Fs;
-        double pass = iters_all * Fs + (o.keep_x ? 0.0 : 2.0 * passes * R * F8);
+        double pass = iters_all * Fs + (o.keep_x ? 0.0 : 2.0 * passes * R * F8) + (fresh && passes ? R * Fs : 0.0);
         for (int q = 0; q < R; q++)
             for (int j = 0; j < nshift; j++) {
                 int np = (fz[q][j] + m - 1) / m;
-                if (np > 0) pass += (2.0 * np - 1.0) * Fs + (o.keep_x ? 2.0 * np * F8 : 0.0);
+                double pj_io = fresh ? (np >= 2 ? 2.0 * np - 2.0 : 1.0) : 2.0 * np - 1.0;
+                if (np > 0) pass += pj_io * Fs + (o.keep_x ? 2.0 * np * F8 : 0.0);
             }
         double other = replacements * (R * (2 * 768.0 * L.V + 6 * F8) + R * Fs);
         stats->kernel_bytes[OVL_K_STENCIL] += sten;

@@ -236,11 +236,31 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
         double yre[E::C], yim[E::C];
 #pragma unroll
         for (int c = 0; c < E::C; c++) yre[c] = yim[c] = 0.0;
+        // software pipeline over the shifts: the next shift's p_j (and x_j)
+        // are loaded before this shift's results are stored, so a load is
+        // always in flight while the previous shift computes
+        auto pptr = [&](int q) { return pf + ((size_t)sj[q] * nrhs + r) * FS + off; };
+        auto xptr = [&](int q) {
+            return xf + ((size_t)sj[q] * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
+        };
+        V pcur = first ? pb : *pptr(0);
+        double2 xcur[E::C];
+        if (xf) {
+#pragma unroll
+            for (int c = 0; c < E::C; c++) xcur[c] = xptr(0)[(size_t)c * g.S];
+        }
         for (int q = 0; q < n; q++) {
-            const int j = sj[q];
-            V *pp = pf + ((size_t)j * nrhs + r) * FS + off;
+            V pnext = pcur;
+            double2 xnext[E::C];
+            if (q + 1 < n) {
+                if (!first) pnext = *pptr(q + 1);
+                if (xf) {
+#pragma unroll
+                    for (int c = 0; c < E::C; c++) xnext[c] = xptr(q + 1)[(size_t)c * g.S];
+                }
+            }
             double pre[E::C], pim[E::C];
-            E::get(first ? pb : *pp, pre, pim);
+            E::get(pcur, pre, pim);
             double dxr[E::C], dxi[E::C], pnr[E::C], pni[E::C];
 #pragma unroll
             for (int c = 0; c < E::C; c++) {
@@ -263,14 +283,14 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
                         pni[c] = fma(cc, rim[c], pni[c]);
                     }
                 }
-            if (sact[q] || first) *pp = E::put(pnr, pni);
+            if (sact[q] || first) *pptr(q) = E::put(pnr, pni);
             if (xf) {
-                double2 *xp = xf + ((size_t)j * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
+                double2 *xp = xptr(q);
 #pragma unroll
-                for (int c = 0; c < E::C; c++) {
-                    double2 xv = xp[(size_t)c * g.S];
-                    xp[(size_t)c * g.S] = make_double2(xv.x + dxr[c], xv.y + dxi[c]);
-                }
+                for (int c = 0; c < E::C; c++)
+                    xp[(size_t)c * g.S] = make_double2(xcur[c].x + dxr[c], xcur[c].y + dxi[c]);
+#pragma unroll
+                for (int c = 0; c < E::C; c++) xcur[c] = xnext[c];
             } else {
 #pragma unroll
                 for (int c = 0; c < E::C; c++) {
@@ -278,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
                     yim[c] = fma(sW[q], dxi[c], yim[c]);
                 }
             }
+            pcur = pnext;
         }
         if (!xf) {
             double2 *yp = y + (size_t)r * F64 + site64 + (size_t)(e * E::C) * g.S;

@@ -148,8 +148,9 @@ def main():
             # FP64 iterations until |r|/|b| < sloppy_below ("mixed@<value>", default
             # the library's), then the FP32 bulk with FP64 residual replacement;
             # FP64 verification and refinement of every shift
-            prm = ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=16,
-                                     mode=ovl.SOLVE_MIXED)
+            # block lengths: the library's (FP64 phase 16, FP32 phase 32) unless ":m<k>"
+            # sets the FP32 phase's
+            prm = ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), mode=ovl.SOLVE_MIXED)
             if "@" in form:
                 prm.sloppy_below = float(form.split("@", 1)[1])
             return prm
@@ -297,7 +298,7 @@ def multi_rhs_line(args, ovl, synth, np, torch):
     B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
     out = ovl.Spinor(lat, ovl.F64, B.nrhs)
     tune = ovl.autotune_stencil(lat, G, B.nrhs)
-    prm = ovl.default_params(tol=args.tol, maxiter=5000, block=16, mode=ovl.SOLVE_MIXED)
+    prm = ovl.default_params(tol=args.tol, maxiter=5000, mode=ovl.SOLVE_MIXED)
     ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -154,13 +154,16 @@ typedef struct {
                                 iteration; m = 1..OVL_MAX_BLOCK keeps the last m residuals
                                 and updates each shifted vector once per m
                                 iterations (same iterates, fewer vector passes).
-                                Mixed mode: block length, 0 meaning 16 */
+                                Mixed mode: block length of the FP32 phase,
+                                0 meaning 32 */
     double sloppy_below;     /* mixed: iterate in FP64 (blocked, FP64 x_l) until
                                 the base residual ||r||/||b|| falls below this,
                                 then hand the recurrences over to FP32; rounding
                                 of the sloppy phase then enters the shifted
                                 residuals only at this level.  0: FP32 from the
                                 first iteration */
+    int32_t block_f64;       /* mixed: block length of the FP64 phase,
+                                1..OVL_MAX_BLOCK, 0 meaning 16 */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */
@@ -286,7 +289,8 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
                            int32_t nshift, const ovl_solver_params *prm);
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
- * check_every 10, refine 1, verify 0, profile 0, block 0. */
+ * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 1e-5,
+ * block_f64 0. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 /* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on

@@ -59,7 +59,7 @@ class ovl_zolo(ctypes.Structure):
 class ovl_solver_params(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("maxiter", c_i32), ("mode", c_i32), ("reliable_delta", c_dbl),
                 ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32), ("profile", c_i32),
-                ("block", c_i32), ("sloppy_below", c_dbl)]
+                ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32)]
 
 
 class ovl_solver_stats(ctypes.Structure):

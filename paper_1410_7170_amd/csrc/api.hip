@@ -19,7 +19,7 @@ hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld 
                           bool accumulate = false);
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase);
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase);
 size_t tune_ws_bytes(const Lat &L, int nrhs);
 int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes, hipStream_t st,
                      int32_t *tried, float *times_us, int32_t max_tried);
@@ -77,7 +77,7 @@ bool params_ok(const ovl_solver_params *p)
 {
     return p && p->tol > 0.0 && std::isfinite(p->tol) && p->maxiter >= 1 &&
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED) && p->reliable_delta > 0.0 &&
-           p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
+           p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
            p->sloppy_below < 1.0;
 }
 
@@ -266,7 +266,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS || (prm && !params_ok(prm))) return 0;
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_MIXED)
-            return yb + mixed_ws_bytes(L, nrhs, nshift, prm->block > 0 ? prm->block : 16, prm->sloppy_below > 0.0);
+            return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0);
         if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64);
         return yb + mscg_ws_bytes(L, nrhs, nshift);
     }
@@ -286,6 +286,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->profile = 0;
     p->block = 0;
     p->sloppy_below = 1e-5;
+    p->block_f64 = 0;
 }
 
 int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,

@@ -38,7 +38,7 @@ hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld 
 // workspace grows with nrhs only; refinement is rare and small.
 static int refine_batch(int nrhs) { return std::max(1, std::min(NR, nrhs)); }
 
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase)
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase)
 {
     const size_t F = field_bytes(P_F64, L.V);
     WsCarve c{nullptr, 0, 0};
@@ -55,7 +55,7 @@ size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool f64_phase)
     c.take(sizeof(double) * NR * NS);                 // zeta at the hand-over of each field
     // the FP64 phase's workspace (y mode) stays alive while the FP32 phase takes over
     size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32, true);
-    if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m, false, P_F64);
+    if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m64, false, P_F64);
     size_t b = blocked_ws_bytes(L, nbat, 1, m, true, P_F32);
     return c.off + std::max(a, b) + 256;
 }
@@ -95,11 +95,11 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
                hipStream_t st)
 {
     const int R = b.nrhs;
-    const int m = prm->block > 0 ? prm->block : 16;
+    const int m = mixed_block(prm), m64 = mixed_block_f64(prm);
     const size_t F = field_bytes(P_F64, L.V);
     const bool f64_phase = prm->sloppy_below > 0.0;
     if (!weights) return OVL_ERR_INVALID;
-    if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, f64_phase)) return OVL_ERR_WORKSPACE;
+    if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, m64, f64_phase)) return OVL_ERR_WORKSPACE;
     WsCarve c{ws, 0, ws_bytes};
     const int NB = refine_batch(R);
     Fld X{c.take(F * R * nshift), nullptr, P_F64, R * nshift};
@@ -139,9 +139,9 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     std::vector<double> zeta((size_t)R * nshift, 1.0);             // zeta_j at the hand-over
     std::vector<double> frozen_res((size_t)R * nshift, -1.0);      // shifts frozen in the FP64 phase
     if (f64_phase) {
-        const size_t w64 = blocked_ws_bytes(L, R, nshift, m, false, P_F64);
+        const size_t w64 = blocked_ws_bytes(L, R, nshift, m64, false, P_F64);
         BlkOpts o64;
-        o64.m = m;
+        o64.m = m64;
         o64.switch_rel = prm->sloppy_below;
         MsScratch h64{};
         rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, weights, b, y, o64, prm, stats, sws, w64, st, &h64);

@@ -13,6 +13,12 @@ constexpr int MB = OVL_MAX_BLOCK;   // longest block of the blocked shift update
 
 inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// Block lengths of the mixed solver's phases: FP32 phase (block, default 32)
+// and FP64 phase (block_f64, default 16).  The FP32 pass with 32 slots moves
+// its bytes about as fast as the 16-slot one, the FP64 one does not.
+inline int mixed_block(const ovl_solver_params *p) { return p->block > 0 ? p->block : 32; }
+inline int mixed_block_f64(const ovl_solver_params *p) { return p->block_f64 > 0 ? p->block_f64 : 16; }
+
 // Sequential carving of a workspace into 256-byte aligned pieces; with a null
 // base it only measures.
 struct WsCarve {

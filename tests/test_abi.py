@@ -75,6 +75,13 @@ def test_sizes(ovl):
     assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm) > w16 > 0
     pm.block = ovl.MAX_BLOCK + 1
     assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm) == 0
+    # the FP64 phase's block length of the mixed form, likewise
+    pm.block = 0
+    w0 = ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm)
+    pm.block_f64 = ovl.MAX_BLOCK
+    assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm) > w0 > 0
+    pm.block_f64 = -1
+    assert ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, 1, 20, pm) == 0
 
 
 def test_null_and_alias_rejected_before_launch(ovl):

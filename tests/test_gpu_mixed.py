@@ -155,7 +155,7 @@ def test_mixed_handover_per_rhs_long_blocks(ovl):
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0, 3)
     prm = ovl.default_params(tol=1e-10, maxiter=5000, mode=ovl.SOLVE_MIXED, block=ovl.MAX_BLOCK,
-                             sloppy_below=1e-4)
+                             block_f64=ovl.MAX_BLOCK, sloppy_below=1e-4)
     st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, prm)
     O64 = ovl.Spinor(lat, 0, 3)
     st64 = ovl.overlap_apply(lat, G, RHO, s, w, B, O64,

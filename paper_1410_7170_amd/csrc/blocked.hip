@@ -178,11 +178,13 @@ struct RingPtrs {
 // FP64.  y mode (xf == null): y_r += sum_j w_j dx_j; x mode: x_j += dx_j.
 // first: the first pass of a fresh solve, where every p_j still equals b
 // (ring slot 0): it is read from there, and written for every shift of the
-// block.
+// block.  p64in (FP32 passes): the first pass of a solve that continues FP64
+// recurrences reads the p_j from the FP64 solve's fields, rounded to FP32
+// as a conversion would round them.
 template <int PS, int MBT>
 __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
                                                      ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs,
-                                                     int first)
+                                                     int first, const double2 *p64in)
 {
     using E = El<PS>;
     using V = typename E::V;
@@ -243,7 +245,21 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
         auto xptr = [&](int q) {
             return xf + ((size_t)sj[q] * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
         };
-        V pcur = first ? pb : *pptr(0);
+        auto pload = [&](int q) -> V {
+            if (PS == P_F32 && p64in) {
+                const double2 *b64 = p64in + ((size_t)sj[q] * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
+                double re[E::C], im[E::C];
+#pragma unroll
+                for (int c = 0; c < E::C; c++) {
+                    const double2 v = b64[(size_t)c * g.S];
+                    re[c] = v.x;
+                    im[c] = v.y;
+                }
+                return E::put(re, im);
+            }
+            return *pptr(q);
+        };
+        V pcur = first ? pb : pload(0);
         double2 xcur[E::C];
         if (xf) {
 #pragma unroll
@@ -253,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
             V pnext = pcur;
             double2 xnext[E::C];
             if (q + 1 < n) {
-                if (!first) pnext = *pptr(q + 1);
+                if (!first) pnext = pload(q + 1);
                 if (xf) {
 #pragma unroll
                     for (int c = 0; c < E::C; c++) xnext[c] = xptr(q + 1)[(size_t)c * g.S];
@@ -446,12 +462,13 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         // continue the recurrences of a switched solve: same scalars, the
         // vectors r, p0 and p_j rounded to this precision, x_j kept
         const MsScratch &rs = *o.resume;
-        if (!o.keep_x || rs.r.nrhs != R || rs.pj.nrhs != R * nshift) return OVL_ERR_INVALID;
+        if (!o.keep_x || rs.r.nrhs != R || rs.pj.nrhs != R * nshift || rs.pj.prec != P_F64) return OVL_ERR_INVALID;
         j0 = rs.j0;
         OVL_HIP(hipMemcpyAsync(S, rs.S, sizeof(MState), hipMemcpyDeviceToDevice, st));
         OVL_HIP(launch_convert(L, rs.r, Fld{slot(0), nullptr, PS, R}, st));
         OVL_HIP(launch_convert(L, rs.p0, p0, st));
-        OVL_HIP(launch_convert(L, rs.pj, pj, st));
+        // an FP32 solve's first pass reads the p_j from rs.pj
+        if (PS != P_F32) OVL_HIP(launch_convert(L, rs.pj, pj, st));
         k_resume<<<1, 64, 0, st>>>(S, R);
         OVL_HIP(hipGetLastError());
         OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
@@ -522,8 +539,12 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         // blocks of up to 16 take the build that holds 16 residuals in
         // registers (more waves per SIMD)
         const int first = !o.resume && passes == 0;
-        if (m <= 16) k_blk_pass<PS, 16><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first);
-        else k_blk_pass<PS, MB><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first);
+        const double2 *p64in =
+            PS == P_F32 && o.resume && passes == 0 ? (const double2 *)o.resume->pj.d : nullptr;
+        if (m <= 16)
+            k_blk_pass<PS, 16><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in);
+        else
+            k_blk_pass<PS, MB><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in);
         int e7 = prof.mark();
         k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
         OVL_HIP(hipGetLastError());
@@ -629,7 +650,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             for (int j = 0; j < nshift; j++) {
                 int np = (fz[q][j] + m - 1) / m;
                 double pj_io = fresh ? (np >= 2 ? 2.0 * np - 2.0 : 1.0) : 2.0 * np - 1.0;
-                if (np > 0) pass += pj_io * Fs + (o.keep_x ? 2.0 * np * F8 : 0.0);
+                // an FP32 solve's first pass reads the FP64 p_j it continues
+                const double wide = !fresh && PS == P_F32 ? F8 - Fs : 0.0;
+                if (np > 0) pass += pj_io * Fs + wide + (o.keep_x ? 2.0 * np * F8 : 0.0);
             }
         double other = replacements * (R * (2 * 768.0 * L.V + 6 * F8) + R * Fs);
         stats->kernel_bytes[OVL_K_STENCIL] += sten;

@@ -180,11 +180,13 @@ struct RingPtrs {
 // (ring slot 0): it is read from there, and written for every shift of the
 // block.  p64in (FP32 passes): the first pass of a solve that continues FP64
 // recurrences reads the p_j from the FP64 solve's fields, rounded to FP32
-// as a conversion would round them.
+// as a conversion would round them.  xzero (x mode): the x_j start at zero;
+// the pass writes x_j = dx_j for the block's shifts, and zeros for the others
+// (and for every shift of an RHS with no iteration in the block).
 template <int PS, int MBT>
 __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
                                                      ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs,
-                                                     int first, const double2 *p64in)
+                                                     int first, const double2 *p64in, int xzero)
 {
     using E = El<PS>;
     using V = typename E::V;
@@ -194,7 +196,21 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     __shared__ int sn;
     const int r = blockIdx.y;
     const int T = bk->t[r];
-    if (T == 0) return;
+    const size_t F64 = (size_t)24 * g.S;               // FP64 field, in double2
+    const int b = blockIdx.x;
+    const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
+    const size_t site64 = (size_t)p * 12 * g.S + i;
+    auto zero_x = [&](int j) {
+        double2 *xp = xf + ((size_t)j * nrhs + r) * F64 + site64;
+#pragma unroll
+        for (int c = 0; c < 12; c++) xp[(size_t)c * g.S] = make_double2(0.0, 0.0);
+    };
+    const bool xz = xzero && xf;
+    if (T == 0) {
+        if (xz && i < g.Vh)
+            for (int j = 0; j < st->nshift; j++) zero_x(j);
+        return;
+    }
     if (threadIdx.x == 0) {
         int n = 0;
         for (int j = 0; j < st->nshift; j++)
@@ -216,15 +232,14 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
         sX[q][i] = bk->X[r][sj[q]][i];
     }
     __syncthreads();
-    if (n == 0) return;
-    const int b = blockIdx.x;
-    const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
+    if (xz)
+        for (int j = 0; j < st->nshift; j++)
+            if (!bk->inblk[r][j]) zero_x(j);
+    if (n == 0) return;
     V *pf = (V *)pfv;
     const size_t FS = (size_t)2 * E::N * g.S;          // sloppy field, in elements
-    const size_t F64 = (size_t)24 * g.S;               // FP64 field, in double2
     const size_t site = (size_t)p * E::N * g.S + i;
-    const size_t site64 = (size_t)p * 12 * g.S + i;
     for (int e = 0; e < E::N; e++) {
         const size_t off = site + (size_t)e * g.S;
         // the block's residuals stay in their storage precision in registers
@@ -263,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
         double2 xcur[E::C];
         if (xf) {
 #pragma unroll
-            for (int c = 0; c < E::C; c++) xcur[c] = xptr(0)[(size_t)c * g.S];
+            for (int c = 0; c < E::C; c++) xcur[c] = xz ? make_double2(0.0, 0.0) : xptr(0)[(size_t)c * g.S];
         }
         for (int q = 0; q < n; q++) {
             V pnext = pcur;
@@ -272,7 +287,8 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
                 if (!first) pnext = pload(q + 1);
                 if (xf) {
 #pragma unroll
-                    for (int c = 0; c < E::C; c++) xnext[c] = xptr(q + 1)[(size_t)c * g.S];
+                    for (int c = 0; c < E::C; c++)
+                        xnext[c] = xz ? make_double2(0.0, 0.0) : xptr(q + 1)[(size_t)c * g.S];
                 }
             }
             double pre[E::C], pim[E::C];
@@ -541,10 +557,13 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         const int first = !o.resume && passes == 0;
         const double2 *p64in =
             PS == P_F32 && o.resume && passes == 0 ? (const double2 *)o.resume->pj.d : nullptr;
+        const int xzero = o.x_zero_start && passes == 0;
         if (m <= 16)
-            k_blk_pass<PS, 16><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in);
+            k_blk_pass<PS, 16>
+                <<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in, xzero);
         else
-            k_blk_pass<PS, MB><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in);
+            k_blk_pass<PS, MB>
+                <<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in, xzero);
         int e7 = prof.mark();
         k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
         OVL_HIP(hipGetLastError());

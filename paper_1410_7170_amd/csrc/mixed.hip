@@ -160,8 +160,8 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
         // keep r0 outside the solver workspace, which the refinement reuses
         OVL_HIP(hipMemcpyAsync(R0.d, h64.r.d, F * R, hipMemcpyDeviceToDevice, st));
         r0 = R0;
-        OVL_HIP(launch_zero(L, X, st));
         o.resume = &h64;
+        o.x_zero_start = true;   // the increments dx_j start at zero
         // the base system's true residual during the sloppy phase is r0 - (Q^2 + s0) dx_0
         rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, r0, Fld{}, o, prm, stats, sws + w64,
                                    sws_bytes - w64, st, nullptr);

@@ -21,20 +21,21 @@ static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, h
     }
 }
 
-// Launches of at most 512 blocks (two per CU) take the build for one wave per
-// SIMD, which may use the whole register file and overlaps two time slices;
-// larger grids take the two-wave build (measured at 32^3x64: 447 against
-// 456 us for FP64 with 256 blocks, 223 against 227 us for FP32 with 512).
-// The one-wave build also stages each slice in LDS when blocks hold whole
-// x3 rows of consecutive x2 at one x1.
+// Blocks of whole x3 rows of consecutive x2 at one x1 take the one-wave build
+// that stages each slice in LDS, at any grid size (at 32^3x64 it beats the
+// two-wave build for one field, 411 against 456 us in FP64, and for batches
+// of 7 fields, 2.7 against 2.9 ms).  Otherwise launches of at most 512
+// blocks take the one-wave build without staging, larger grids the two-wave
+// build.
 template <int PREC>
 static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
 {
     const int L2 = a.g.L[2], L3 = a.g.L[3];
     const bool rows = kBlock % L3 == 0 && (L2 * L3) % kBlock == 0;
-    if (grid.x <= 512) {
-        if (rows) wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st);
-        else wilson_ts_dispatch_s<PREC, 1, false>(mode, g5, grid, a, st);
+    if (rows) {
+        wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st);
+    } else if (grid.x <= 512) {
+        wilson_ts_dispatch_s<PREC, 1, false>(mode, g5, grid, a, st);
     } else {
         wilson_ts_dispatch_s<PREC, 2, false>(mode, g5, grid, a, st);
     }

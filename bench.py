@@ -42,6 +42,9 @@ def parse():
                     help="workload recipe of the batched multi-RHS line (3 = 24^3x48, 12 point "
                          "sources); -1 skips it")
     ap.add_argument("--multi-rhs-steps", type=int, default=2)
+    ap.add_argument("--stencil-order", default="",
+                    help="tile_t,stream_t,stream_t64 for the main workload instead of autotuning "
+                         "(profiling runs pin the order the timed run chose)")
     return ap.parse_args()
 
 
@@ -102,7 +105,11 @@ def main():
     shifts, weights, delta = ovl.zolotarev(lo, hi, npoles)
     B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
     out = ovl.Spinor(lat, ovl.F64, B.nrhs)
-    tune = ovl.autotune_stencil(lat, G, B.nrhs)
+    if args.stencil_order:
+        lat.tile_t, lat.stream_t, lat.stream_t64 = (int(v) for v in args.stencil_order.split(","))
+        tune = dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, timings="fixed")
+    else:
+        tune = ovl.autotune_stencil(lat, G, B.nrhs)
     setup_s = time.time() - t_setup
     print(f"[bench] setup {setup_s:.1f}s dims={dims} |Q| in [{lo:.4f}, {hi:.4f}] delta={delta:.2e}",
           file=sys.stderr, flush=True)

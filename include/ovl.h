@@ -300,7 +300,7 @@ OVL_API void ovl_default_params(ovl_solver_params *prm);
  * {0,2,4,8,16,32} on FP32 and lat->stream_t64 likewise on FP64 (lengths that
  * divide dims[0]; streaming only when dims[1]*dims[2]*dims[3] % 256 == 0) --
  * and writes the fastest of each into *lat (a candidate replaces the current
- * value only when more than 2% faster).  Outputs of every operator
+ * value only when more than 5% faster).  Outputs of every operator
  * depend on these fields only through summation order.  ws: device workspace
  * of ovl_workspace_bytes(lat, OVL_OP_TUNE, 0, nrhs, 0, NULL) bytes.
  * tried/times_us (host, optional, max_tried entries): candidate k as

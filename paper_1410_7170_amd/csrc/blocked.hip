@@ -115,6 +115,11 @@ struct El<P_F64> {
     __device__ static void get(const V &v, double *re, double *im) { re[0] = v.x; im[0] = v.y; }
     __device__ static V put(const double *re, const double *im) { return make_double2(re[0], im[0]); }
     __device__ static V fresh(const V &v) { return v; }
+    __device__ static V ldnt(const V *p)
+    {
+        nt_d2 t = __builtin_nontemporal_load((const nt_d2 *)p);
+        return make_double2(t.x, t.y);
+    }
 };
 template <>
 struct El<P_F32> {
@@ -138,10 +143,16 @@ struct El<P_F32> {
         asm volatile("" : "+v"(c.x), "+v"(c.y), "+v"(c.z), "+v"(c.w));
         return c;
     }
+    __device__ static V ldnt(const V *p)
+    {
+        nt_f4 t = __builtin_nontemporal_load((const nt_f4 *)p);
+        return make_float4(t.x, t.y, t.z, t.w);
+    }
 };
 
 // p0 = r_new + beta p0 on RHS that are still iterating or paused in this
-// iteration (run_c)
+// iteration (run_c).  Non-temporal loads: FP64 214 -> 194 us, FP32 89 -> 86 us
+// at 32^3x64 (a non-temporal store as well made it slower).
 template <int PS>
 __global__ __launch_bounds__(kBlock) void k_base_p(Geom g, int nb, const MState *st, const void *rnv, void *p0v)
 {
@@ -159,8 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_base_p(Geom g, int nb, const MState 
 #pragma unroll
     for (int e = 0; e < E::N; e++) {
         double ar[E::C], ai[E::C], qr[E::C], qi[E::C];
-        E::get(rn[off + (size_t)e * g.S], ar, ai);
-        E::get(p0[off + (size_t)e * g.S], qr, qi);
+        E::get(E::ldnt(rn + off + (size_t)e * g.S), ar, ai);
+        E::get(E::ldnt(p0 + off + (size_t)e * g.S), qr, qi);
 #pragma unroll
         for (int c = 0; c < E::C; c++) {
             qr[c] = fma(be, qr[c], ar[c]);

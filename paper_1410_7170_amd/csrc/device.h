@@ -188,6 +188,16 @@ struct SpinorRef<P_F64> {
             s[k / 3][k % 3] = {v.x, v.y};
         }
     }
+    // non-temporal: a centre operand read once
+    __device__ __forceinline__ void load_nt(int p, int i, cplx<double> s[4][3]) const
+    {
+        const double2 *b = d + (size_t)p * 12 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)&b[(size_t)k * Vh]);
+            s[k / 3][k % 3] = {v.x, v.y};
+        }
+    }
     __device__ __forceinline__ void store(int p, int i, const cplx<double> s[4][3]) const
     {
         double2 *b = d + (size_t)p * 12 * Vh + i;
@@ -212,6 +222,16 @@ struct SpinorRef<P_F32> {
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             float4 v = b[(size_t)k * Vh];
+            s[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
+            s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
+        }
+    }
+    __device__ __forceinline__ void load_nt(int p, int i, cplx<float> s[4][3]) const
+    {
+        const float4 *b = d + (size_t)p * 6 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)&b[(size_t)k * Vh]);
             s[(2 * k) / 3][(2 * k) % 3] = {v.x, v.y};
             s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {v.z, v.w};
         }
@@ -260,6 +280,7 @@ struct SpinorRef<P_F16S> {
             }
         }
     }
+    __device__ __forceinline__ void load_nt(int p, int i, cplx<float> s[4][3]) const { load(p, i, s); }
     __device__ __forceinline__ void store_nt(int p, int i, const cplx<float> s[4][3]) const { store(p, i, s); }
     __device__ __forceinline__ void store(int p, int i, const cplx<float> s[4][3]) const
     {

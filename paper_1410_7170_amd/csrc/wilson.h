@@ -292,7 +292,7 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
     if (kShift) {
         const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, r);
         cplx<T> pv[4][3];
-        pf.load(p, i, pv);
+        pf.load_nt(p, i, pv);
         const T sh = (T)shift_r;
 #pragma unroll
         for (int s = 0; s < 4; s++)
@@ -301,7 +301,7 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
     }
     if (MODE == W_RUPDATE) {
         cplx<T> rv[4][3];
-        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load(p, i, rv);
+        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load_nt(p, i, rv);
         const T al = (T)a.alpha[r];
         T n0 = 0;
 #pragma unroll
@@ -315,7 +315,7 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
         q0 += (double)n0;
     } else if (MODE == W_RESNORM) {
         cplx<T> rv[4][3];
-        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load(p, i, rv);
+        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load_nt(p, i, rv);
         const T rs = (T)rin_s;
         T n0 = 0;
 #pragma unroll

@@ -35,14 +35,14 @@ __global__ void k_blk_reset(Blk *bk, const MState *st, int nrhs, int nshift)
 // beta, beta_j, freezing, and the block coefficients; RHS blockIdx.x, shift
 // j in thread j.  sw2 > 0: an RHS with |r|^2 <= sw2 |b|^2 pauses (hand-over).
 __global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const double *partials, int nblk,
-                                                     double sw2)
+                                                     int cnt, double sw2)
 {
     __shared__ double lds[4];
     const int r = blockIdx.x;
     const int j = threadIdx.x;
     if (st->skip[r]) return;
     double a = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += kBlock) a += partials[(size_t)r * nblk + k];
+    for (int k = threadIdx.x; k < cnt; k += kBlock) a += partials[(size_t)r * nblk + k];
     const double rr_new = block_sum_all(a, lds);
     const int it = st->iter[r] + 1;
     if (!isfinite(rr_new)) {
@@ -454,6 +454,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
 {
     const int R = b.nrhs;
     const int nblk = site_blocks(L);
+    const int npart = stencil_partials(L, PS);   // slots the iteration stencils fill
     const int m = o.m;
     if (m < 1 || m > MB || R > NR) return OVL_ERR_INVALID;
     if (o.reliable && !o.keep_x) return OVL_ERR_INVALID;
@@ -542,13 +543,13 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             int e0 = prof.mark();
             OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
             int e1 = prof.mark();
-            k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk);
+            k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
             int e2 = prof.mark();
             B.rin = slot(k);
             B.out = slot(k + 1);
             OVL_HIP(launch_wilson(L, PS, W_RUPDATE, true, B, st));
             int e3 = prof.mark();
-            k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk, sw2);
+            k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk, npart, sw2);
             int e4 = prof.mark();
             k_base_p<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), p0.d);
             int e5 = prof.mark();

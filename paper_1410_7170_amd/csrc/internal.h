@@ -79,5 +79,9 @@ hipError_t launch_zero(const Lat &L, Fld f, hipStream_t st);
 
 int elems_per_field(int prec, int Vh);   // flat vector elements of one RHS
 int site_blocks(const Lat &L);           // blocks of a flat elementwise launch over one field
+// Leading per-RHS partial-sum slots a stencil launch of this precision fills;
+// it zeroes the rest of the site_blocks(L) slots, so a consumer may sum only
+// these (the same sum bit for bit).
+int stencil_partials(const Lat &L, int prec);
 
 }  // namespace ovl

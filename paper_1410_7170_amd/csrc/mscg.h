@@ -111,7 +111,7 @@ struct MsScratch {
 };
 
 // alpha and the shifted zeta_j', alpha_j (one block per RHS); defined in solver.hip
-__global__ void k_ms_alpha(MState *st, const double *partials, int nblk);
+__global__ void k_ms_alpha(MState *st, const double *partials, int nblk, int cnt);
 
 // Upload the constant part of the scalar state (per-RHS base shift and
 // tolerance default to the smallest shift and prm->tol), |b|^2 per RHS and

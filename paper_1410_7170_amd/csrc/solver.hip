@@ -43,8 +43,9 @@ __global__ void k_ms_init(MState *st, const double *bb, int nrhs, int nshift, in
     }
 }
 
-// alpha and the shifted zeta_j', alpha_j for RHS blockIdx.x
-__global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *partials, int nblk)
+// alpha and the shifted zeta_j', alpha_j for RHS blockIdx.x; the partials
+// have row stride nblk, of which the first cnt slots can be nonzero
+__global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *partials, int nblk, int cnt)
 {
     __shared__ double lds[8];
     const int r = blockIdx.x;
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *p
         return;
     }
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += kBlock) {
+    for (int k = threadIdx.x; k < cnt; k += kBlock) {
         a += partials[(size_t)r * nblk + k];
         b += partials[(size_t)(nr + r) * nblk + k];
     }
@@ -88,14 +89,14 @@ __global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *p
 }
 
 // beta, beta_j, freezing; RHS blockIdx.x, shift j in thread j
-__global__ __launch_bounds__(kBlock) void k_ms_beta(MState *st, const double *partials, int nblk)
+__global__ __launch_bounds__(kBlock) void k_ms_beta(MState *st, const double *partials, int nblk, int cnt)
 {
     __shared__ double lds[4];
     const int r = blockIdx.x;
     const int j = threadIdx.x;
     if (st->skip[r]) return;
     double a = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += kBlock) a += partials[(size_t)r * nblk + k];
+    for (int k = threadIdx.x; k < cnt; k += kBlock) a += partials[(size_t)r * nblk + k];
     const double rr_new = block_sum_all(a, lds);
     const int it = st->iter[r] + 1;
     if (!isfinite(rr_new)) {
@@ -281,6 +282,7 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
 {
     const int R = b.nrhs;
     const int nblk = site_blocks(L);
+    const int npart = stencil_partials(L, P_F64);   // slots the iteration stencils fill
     WsCarve c{ws, 0, ws_bytes};
     size_t F = field_bytes(P_F64, L.V);
     MState *S = (MState *)c.take(sizeof(MState));
@@ -339,11 +341,11 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
             int e0 = prof.mark();
             OVL_HIP(launch_wilson(L, P_F64, W_NORM, true, A, st));
             int e1 = prof.mark();
-            k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk);
+            k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
             int e2 = prof.mark();
             OVL_HIP(launch_wilson(L, P_F64, W_RUPDATE, true, B, st));
             int e3 = prof.mark();
-            k_ms_beta<<<R, kBlock, 0, st>>>(S, partials, nblk);
+            k_ms_beta<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
             int e4 = prof.mark();
             k_ms_update<P_F64><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, r.d, nullptr, pfl.d, nullptr, x.d, nullptr, R);
             int e5 = prof.mark();

@@ -342,6 +342,18 @@ struct GaugeRef<P_F64> {
         }
         rebuild_row2(u);
     }
+    // non-temporal: a link read once per launch (the time links of the
+    // streaming stencil)
+    __device__ __forceinline__ void load_nt(int p, int mu, int i, cplx<double> u[3][3]) const
+    {
+        const double2 *b = d + (size_t)(p * 4 + mu) * 6 * Vh + i;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)&b[(size_t)e * Vh]);
+            u[e / 3][e % 3] = {v.x, v.y};
+        }
+        rebuild_row2(u);
+    }
 };
 
 template <>
@@ -352,6 +364,20 @@ struct GaugeRef<P_F32> {
     {
         const float4 *b = d + (size_t)(p * 4 + mu) * 3 * Vh + i;
         float4 v0 = b[0], v1 = b[(size_t)Vh], v2 = b[(size_t)2 * Vh];
+        u[0][0] = {v0.x, v0.y};
+        u[0][1] = {v0.z, v0.w};
+        u[0][2] = {v1.x, v1.y};
+        u[1][0] = {v1.z, v1.w};
+        u[1][1] = {v2.x, v2.y};
+        u[1][2] = {v2.z, v2.w};
+        rebuild_row2(u);
+    }
+    __device__ __forceinline__ void load_nt(int p, int mu, int i, cplx<float> u[3][3]) const
+    {
+        const float4 *b = d + (size_t)(p * 4 + mu) * 3 * Vh + i;
+        nt_f4 v0 = __builtin_nontemporal_load((const nt_f4 *)&b[0]);
+        nt_f4 v1 = __builtin_nontemporal_load((const nt_f4 *)&b[(size_t)Vh]);
+        nt_f4 v2 = __builtin_nontemporal_load((const nt_f4 *)&b[(size_t)2 * Vh]);
         u[0][0] = {v0.x, v0.y};
         u[0][1] = {v0.z, v0.w};
         u[0][2] = {v1.x, v1.y};
@@ -378,6 +404,7 @@ struct GaugeRef<P_F16S> {
         }
         rebuild_row2(u);
     }
+    __device__ __forceinline__ void load_nt(int p, int mu, int i, cplx<float> u[3][3]) const { load(p, mu, i, u); }
 };
 
 // ---------------------------------------------------------------- reductions

@@ -484,7 +484,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
         const int py = (y[0] + sp) & 1, iy = cb_index(g, y);
         cplx<T> sv[4][3], u[3][3];
         in.load(py, iy, sv);
-        U.load(py, 0, iy, u);
+        U.load_nt(py, 0, iy, u);
         tback_half(w, sv, u);
     }
     if (STAGE) {
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
         // U_0(t): the next slice's carry from this centre, then the centre's
         // diagonal term; the centre is then dead before psi(t+1) arrives
         cplx<T> u[3][3];
-        U.load(p, 0, i, u);
+        U.load_nt(p, 0, i, u);   // U_0(t) is read by this thread only
         tback_half(w, cen, u);
         const T dn2 = diag_minus_half(acc, cen, (T)a.diag);
         {

@@ -86,6 +86,20 @@ struct Geom {
     int Ts64;      // time slices per thread of the FP64 streaming stencil (0: Ts)
 };
 
+// Threads (sites) per block of the time-streaming stencil with ts slices per
+// thread: 256, or 192 when whole x3 rows tile 192 sites but not 256 (x3
+// extents such as 24 and 48), so that the LDS-staged build applies.  192 only
+// with ts >= 2, which keeps the block count per RHS within the 2*nb
+// partial-sum slots.
+inline int stream_threads(const Geom &g, int ts)
+{
+    const int L2 = g.L[2], L3 = g.L[3];
+    const long V3 = (long)g.L[1] * L2 * L3;
+    const bool rows256 = kBlock % L3 == 0 && (L2 * L3) % kBlock == 0;
+    const bool rows192 = 192 % L3 == 0 && (L2 * L3) % 192 == 0 && V3 % 192 == 0;
+    return !rows256 && rows192 && ts >= 2 ? 192 : kBlock;
+}
+
 __host__ __device__ inline int padded_stride(int Vh) { return ((Vh + 15) / 16) * 16 + 24; }
 
 __device__ __forceinline__ void site_coords(const Geom &g, int p, int i, int x[4])
@@ -421,6 +435,26 @@ __device__ __forceinline__ double block_sum(double v, double *lds /* >= 4 */)
     if (threadIdx.x == 0) t = (lds[0] + lds[1]) + (lds[2] + lds[3]);
     __syncthreads();
     return t;
+}
+
+// The same over a block of NW waves (block_sum is NW = 4).
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double *lds /* >= 4 */)
+{
+    if constexpr (NW == 4) {
+        return block_sum(v, lds);
+    } else {
+        static_assert(NW == 3, "block_sum_w: 3 or 4 waves");
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) lds[w] = v;
+        __syncthreads();
+        double t = 0.0;
+        if (threadIdx.x == 0) t = (lds[0] + lds[1]) + lds[2];
+        __syncthreads();
+        return t;
+    }
 }
 
 // The same sum, valid in every thread (each adds the four wave sums in the

@@ -37,12 +37,12 @@ int last_hip_error() { return g_last_hip; }
 int site_blocks(const Lat &L) { return 2 * L.nb; }
 
 // The time-streaming stencil (FP64, FP32 with a stream length) runs
-// V / (256 Ts) blocks per RHS, one partial slot each; the one-site form fills
+// V / (NT Ts) blocks per RHS, one partial slot each; the one-site form fills
 // all 2 nb slots.
 int stencil_partials(const Lat &L, int prec)
 {
     const int ts = prec == P_F64 && L.g.Ts64 > 0 ? L.g.Ts64 : L.g.Ts;
-    if (ts > 0 && prec != P_F16S) return (int)(L.V / ((int64_t)kBlock * ts));
+    if (ts > 0 && prec != P_F16S) return (int)(L.V / ((int64_t)stream_threads(L.g, ts) * ts));
     return 2 * L.nb;
 }
 

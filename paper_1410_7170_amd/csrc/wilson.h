@@ -152,14 +152,14 @@ __device__ __forceinline__ void hops_mu(const Geom &g, const SpinorRef<PREC> &in
     hop<T, MU, false>(acc, s, u, ph);
 }
 
-// LDS copy of one time slice of a streaming block: the centres of its 256
+// LDS copy of one time slice of a streaming block: the centres of its NT
 // sites as component arrays indexed by the thread's local site index
 // (double2 per complex in FP64, float4 per complex pair otherwise).
-template <int PREC>
+template <int PREC, int NT = kBlock>
 struct LdsPsi {
     using E = float4;
     static constexpr int NC = 6;
-    E (*d)[kBlock];
+    E (*d)[NT];
     __device__ __forceinline__ void store(int l, const cplx<float> s[4][3]) const
     {
 #pragma unroll
@@ -178,11 +178,11 @@ struct LdsPsi {
         }
     }
 };
-template <>
-struct LdsPsi<P_F64> {
+template <int NT>
+struct LdsPsi<P_F64, NT> {
     using E = double2;
     static constexpr int NC = 12;
-    E (*d)[kBlock];
+    E (*d)[NT];
     __device__ __forceinline__ void store(int l, const cplx<double> s[4][3]) const
     {
 #pragma unroll
@@ -202,18 +202,18 @@ struct LdsPsi<P_F64> {
 // else from memory (parity pn, index jn): one generic-pointer load path for
 // both, so the compiler need not carry both versions.  The LDS and memory
 // layouts share their element type; FP16 (never staged) keeps a branch.
-template <int PREC>
-__device__ __forceinline__ void load_either(const LdsPsi<PREC> &lp, const SpinorRef<PREC> &in, bool inside, int ln,
-                                            int pn, int jn, int S, cplx<typename Real<PREC>::T> s[4][3])
+template <int PREC, int NT>
+__device__ __forceinline__ void load_either(const LdsPsi<PREC, NT> &lp, const SpinorRef<PREC> &in, bool inside,
+                                            int ln, int pn, int jn, int S, cplx<typename Real<PREC>::T> s[4][3])
 {
     if constexpr (PREC == P_F16S) {
         if (inside) lp.load(ln, s);
         else in.load(pn, jn, s);
     } else {
-        using E = typename LdsPsi<PREC>::E;
-        constexpr int NC = LdsPsi<PREC>::NC;
+        using E = typename LdsPsi<PREC, NT>::E;
+        constexpr int NC = LdsPsi<PREC, NT>::NC;
         const E *b = inside ? (const E *)&lp.d[0][ln] : (const E *)in.d + (size_t)pn * NC * S + jn;
-        const size_t stride = inside ? (size_t)kBlock : (size_t)S;
+        const size_t stride = inside ? (size_t)NT : (size_t)S;
         E v[NC];
 #pragma unroll
         for (int k = 0; k < NC; k++) v[k] = b[k * stride];
@@ -234,14 +234,14 @@ __device__ __forceinline__ void load_either(const LdsPsi<PREC> &lp, const Spinor
 // neighbour inside the block (every x3 neighbour; x2 neighbours except from
 // the block's first and last rows) comes from the slice's LDS copy, others
 // from memory.  l: the thread's local site index; rows of L3 sites.
-template <int PREC, int MU>
+template <int PREC, int MU, int NT>
 __device__ __forceinline__ void hops_mu_lds(const Geom &g, const SpinorRef<PREC> &in, const GaugeRef<PREC> &U,
-                                            const LdsPsi<PREC> &lp, int p, int i, const int x[4], int l,
+                                            const LdsPsi<PREC, NT> &lp, int p, int i, const int x[4], int l,
                                             cplx<typename Real<PREC>::T> acc[4][3])
 {
     using T = typename Real<PREC>::T;
     const int L3 = g.L[3];
-    const int row = l / L3, rows = kBlock / L3;
+    const int row = l / L3, rows = NT / L3;
     cplx<T> s[4][3], u[3][3];
     int y[4] = {x[0], x[1], x[2], x[3]};
     T ph = (T)1;
@@ -430,26 +430,27 @@ __device__ __forceinline__ void tback_add(cplx<T> acc[4][3], const cplx<T> w[2][
 // Time-streaming form of the stencil.  A thread owns one spatial site
 // (x1, x2, x3) and walks Ts consecutive time slices (g.Ts64 for FP64 when
 // set, else g.Ts); block lb covers the
-// 256 consecutive spatial sites of spatial block lb % nsb (x3 fastest, so a
+// NT consecutive spatial sites of spatial block lb % nsb (x3 fastest, so a
 // wave reads whole x3 rows of both parities) in time chunk lb / nsb.  The
 // time hops need no neighbour loads after the first slice: psi(t+1), loaded
 // for the forward hop, is the centre of the next slice, and the backward
 // hop's U_0(t)^H (1 + gamma_0) psi(t) is formed while slice t holds U_0(t)
-// and psi(t) in registers.  Requires L1*L2*L3 % 256 == 0 and Ts | L0.
+// and psi(t) in registers.  Requires L1*L2*L3 % NT == 0 and Ts | L0.
 // WPE is the minimum number of waves per SIMD the build allows for (1 or 2);
 // the one-wave build overlaps pairs of time slices.  STAGE (blocks of whole
-// x3 rows of consecutive x2 at one x1: kBlock % L3 == 0 and
-// L2*L3 % kBlock == 0) keeps each slice's centres in LDS, where the next
-// slice reads its x3 and in-block x2 neighbours.
+// x3 rows of consecutive x2 at one x1: NT % L3 == 0 and L2*L3 % NT == 0)
+// keeps each slice's centres in LDS, where the next slice reads its x3 and
+// in-block x2 neighbours.  NT = 256, or 192 for x3 extents such as 24 and 48
+// whose rows do not tile 256 sites (stream_threads).
 // Partial sums: slot lb holds the block's sum and the block zeroes the slots
 // lb + m*nblk_ts (m >= 1) below a.nblk, so all 2*nb slots per RHS are valid.
-template <int PREC, int MODE, bool G5, int WPE, bool STAGE>
-__global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
+template <int PREC, int MODE, bool G5, int WPE, bool STAGE, int NT = kBlock>
+__global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
 {
     using T = typename Real<PREC>::T;
     __shared__ double lds[8];
-    __shared__ typename LdsPsi<PREC>::E lds_psi[STAGE ? LdsPsi<PREC>::NC : 1][kBlock];
-    const LdsPsi<PREC> lp{lds_psi};
+    __shared__ typename LdsPsi<PREC, NT>::E lds_psi[STAGE ? LdsPsi<PREC, NT>::NC : 1][NT];
+    const LdsPsi<PREC, NT> lp{lds_psi};
     const Geom &g = a.g;
     const int lbr = xcd_remap(blockIdx.x, gridDim.x);
     const int r = lbr % a.nrhs;
@@ -463,9 +464,9 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
     // more values live across the hops and spill)
     const double rin_s = MODE == W_RESNORM && a.rin_scale ? a.rin_scale[r] : 1.0;
     const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
-    const int nsb = L1 * L2 * L3 / kBlock;
+    const int nsb = L1 * L2 * L3 / NT;
     const int sb = lb % nsb, tc = lb / nsb;
-    const int sidx = sb * kBlock + threadIdx.x;
+    const int sidx = sb * NT + threadIdx.x;
     int x[4];
     x[3] = sidx % L3;
     x[2] = (sidx / L3) % L2;
@@ -543,9 +544,9 @@ __global__ __launch_bounds__(kBlock, WPE) void k_wilson_ts(WArgs a)
     }
     if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
         const int nq = MODE == W_NORM ? 2 : 1;
-        double t0s = block_sum(q0, lds);
-        double t1s = MODE == W_NORM ? block_sum(q1, lds + 4) : 0.0;
-        for (int m = threadIdx.x; lb + (size_t)m * nbt < (size_t)a.nblk; m += kBlock) {
+        double t0s = block_sum_w<NT / 64>(q0, lds);
+        double t1s = MODE == W_NORM ? block_sum_w<NT / 64>(q1, lds + 4) : 0.0;
+        for (int m = threadIdx.x; lb + (size_t)m * nbt < (size_t)a.nblk; m += NT) {
             const size_t slot = (size_t)lb + (size_t)m * nbt;
             a.partials[(size_t)r * a.nblk + slot] = m == 0 ? t0s : 0.0;
             if (nq == 2) a.partials[(size_t)(a.nrhs + r) * a.nblk + slot] = m == 0 ? t1s : 0.0;

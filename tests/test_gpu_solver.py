@@ -228,11 +228,12 @@ def test_nonfinite_input_reported(ovl):
 @pytest.mark.parametrize("dims,block,ts,ts64", [((8, 8, 8, 8), 0, 2, 0), ((8, 8, 8, 8), 8, 4, 0),
                                                ((8, 8, 8, 8), 16, 8, 0), ((8, 8, 8, 8), 0, 2, 4),
                                                ((8, 8, 8, 8), 16, 4, 8), ((8, 4, 8, 32), 16, 4, 8),
-                                               ((8, 2, 16, 16), 0, 2, 8)])
+                                               ((8, 2, 16, 16), 0, 2, 8), ((4, 4, 24, 24), 16, 2, 4)])
 def test_solvers_with_streaming_stencil(ovl, dims, block, ts, ts64):
     """Multishift CG and the overlap apply with the time-streaming stencil: its
     partial sums (fewer blocks than slots) feed the same reductions.  The
-    last two lattices take the LDS-staged form."""
+    last three lattices take the LDS-staged form, the last one with blocks of
+    192 sites (rows of 24)."""
     note(f"solvers with streaming stencil block={block} stream_t={ts} stream_t64={ts64}")
     U = synth.gauge(dims, 0.3, 61, n_stout=2)
     lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)

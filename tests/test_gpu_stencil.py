@@ -306,7 +306,9 @@ def test_autotune_keeps_results(ovl, dims, nrhs):
 
 # LDS-staged streaming form: blocks of whole x3 rows of consecutive x2 at one
 # x1 (256 % L3 == 0, L2*L3 % 256 == 0) and launches of at most 512 blocks
-STAGED_CASES = [((4, 2, 16, 16), 2), ((4, 4, 8, 32), 4), ((6, 2, 32, 8), 3), ((8, 2, 16, 16), 8), ((4, 4, 16, 16), 1)]
+# the last three have x3 extents (24, 48) whose rows tile 192-site blocks, not 256
+STAGED_CASES = [((4, 2, 16, 16), 2), ((4, 4, 8, 32), 4), ((6, 2, 32, 8), 3), ((8, 2, 16, 16), 8), ((4, 4, 16, 16), 1),
+                ((4, 8, 24, 24), 2), ((4, 4, 48, 48), 2), ((8, 4, 24, 24), 4)]
 
 
 @pytest.mark.parametrize("dims,ts", STAGED_CASES)

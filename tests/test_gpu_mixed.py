@@ -166,3 +166,25 @@ def test_mixed_handover_per_rhs_long_blocks(ovl):
         assert (tr > 0).all() and (tr <= 1e-10).all(), (r, tr)
         assert rel(got[r], ref[r]) < 1e-9, r
         assert abs(st["iterations"][r] - st64["iterations"][r]) <= 8, (r, st["iterations"], st64["iterations"])
+
+
+def test_mixed_zero_rhs_in_batch(ovl):
+    """A zero right-hand side next to a Gaussian one: it is finished before
+    the first iteration, so every pass skips it and the FP32 phase's first
+    pass must leave its increments at zero; D_ov of it is exactly zero and
+    the other RHS agrees with the FP64 blocked form."""
+    dims = (8, 4, 4, 8)
+    note(f"mixed zero RHS {dims}")
+    U, lat, olat, G, (s, w), _ = setup(ovl, dims, 351)
+    b = synth.gaussian_spinor(lat.V, 352, 2)
+    b[1] = 0.0
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0, 2)
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-10, maxiter=5000,
+                                                                       mode=ovl.SOLVE_MIXED, sloppy_below=1e-3))
+    O64 = ovl.Spinor(lat, 0, 2)
+    ovl.overlap_apply(lat, G, RHO, s, w, B, O64, ovl.default_params(tol=1e-10, maxiter=5000, block=8))
+    got, ref = O.to_canonical().cpu().numpy(), O64.to_canonical().cpu().numpy()
+    assert not np.any(got[1]) and not np.any(ref[1])
+    assert (np.array(st["true_residual"][0]) <= 1e-10).all()
+    assert rel(got[0], ref[0]) < 1e-9

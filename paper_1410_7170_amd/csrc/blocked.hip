@@ -191,9 +191,10 @@ struct RingPtrs {
 // (ring slot 0): it is read from there, and written for every shift of the
 // block.  p64in (FP32 passes): the first pass of a solve that continues FP64
 // recurrences reads the p_j from the FP64 solve's fields, rounded to FP32
-// as a conversion would round them.  xzero (x mode): the x_j start at zero;
-// the pass writes x_j = dx_j for the block's shifts, and zeros for the others
-// (and for every shift of an RHS with no iteration in the block).
+// as a conversion would round them.  xzero (x mode): the x_j of shifts
+// j < xzero start at zero; the pass writes x_j = dx_j for the block's shifts
+// and zeros for the others below xzero (for every one of an RHS with no
+// iteration in the block).  The block's shifts all lie below xzero.
 template <int PS, int MBT>
 __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
                                                      ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs,
@@ -216,10 +217,11 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
 #pragma unroll
         for (int c = 0; c < 12; c++) xp[(size_t)c * g.S] = make_double2(0.0, 0.0);
     };
-    const bool xz = xzero && xf;
+    const bool xz = xzero > 0 && xf;
+    const int nzs = xzero < st->nshift ? xzero : st->nshift;
     if (T == 0) {
         if (xz && i < g.Vh)
-            for (int j = 0; j < st->nshift; j++) zero_x(j);
+            for (int j = 0; j < nzs; j++) zero_x(j);
         return;
     }
     if (threadIdx.x == 0) {
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     __syncthreads();
     if (i >= g.Vh) return;
     if (xz)
-        for (int j = 0; j < st->nshift; j++)
+        for (int j = 0; j < nzs; j++)
             if (!bk->inblk[r][j]) zero_x(j);
     if (n == 0) return;
     V *pf = (V *)pfv;
@@ -569,7 +571,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         const int first = !o.resume && passes == 0;
         const double2 *p64in =
             PS == P_F32 && o.resume && passes == 0 ? (const double2 *)o.resume->pj.d : nullptr;
-        const int xzero = o.x_zero_start && passes == 0;
+        const int xzero = passes == 0 ? o.x_zero_shifts : 0;
         if (m <= 16)
             k_blk_pass<PS, 16>
                 <<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in, xzero);

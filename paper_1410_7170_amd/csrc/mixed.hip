@@ -138,6 +138,10 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     Fld r0 = b;                                                    // residual at the hand-over
     std::vector<double> zeta((size_t)R * nshift, 1.0);             // zeta_j at the hand-over
     std::vector<double> frozen_res((size_t)R * nshift, -1.0);      // shifts frozen in the FP64 phase
+    // shifts j >= nz froze in the FP64 phase for every RHS (shifts ascend, and
+    // the largest converge first): their increments stay zero, so nothing
+    // writes, verifies or combines them unless a refinement touches one
+    int nz = nshift;
     if (f64_phase) {
         const size_t w64 = blocked_ws_bytes(L, R, nshift, m64, false, P_F64);
         BlkOpts o64;
@@ -157,11 +161,15 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
                 if (!hs.act[q][j] && bn[q] > 0)
                     frozen_res[(size_t)j * R + q] = std::sqrt(hs.frozen_rr[q][j]) / bn[q];
             }
+        nz = 0;
+        for (int j = 0; j < nshift; j++)
+            for (int q = 0; q < R; q++)
+                if (frozen_res[(size_t)j * R + q] < 0.0) nz = j + 1;
         // keep r0 outside the solver workspace, which the refinement reuses
         OVL_HIP(hipMemcpyAsync(R0.d, h64.r.d, F * R, hipMemcpyDeviceToDevice, st));
         r0 = R0;
         o.resume = &h64;
-        o.x_zero_start = true;   // the increments dx_j start at zero
+        o.x_zero_shifts = nz;   // the increments dx_j (j < nz) start at zero
         // the base system's true residual during the sloppy phase is r0 - (Q^2 + s0) dx_0
         rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, r0, Fld{}, o, prm, stats, sws + w64,
                                    sws_bytes - w64, st, nullptr);
@@ -218,17 +226,13 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     };
     {
         // shifts frozen for every RHS in the FP64 phase need no stencils
-        // (shifts ascend, and the largest converge first)
-        int jmax = -1;
-        for (int j = 0; j < nshift; j++)
-            for (int q = 0; q < R; q++)
-                if (frozen_res[(size_t)j * R + q] < 0.0) jmax = j;
-        for (int f = (jmax + 1) * R; f < R * nshift; f++) res[f] = frozen_res[f];
-        if (jmax >= 0) {
-            int e = verify(0, (jmax + 1) * R);
+        for (int f = nz * R; f < R * nshift; f++) res[f] = frozen_res[f];
+        if (nz > 0) {
+            int e = verify(0, nz * R);
             if (e) return e;
         }
     }
+    int ncomb = nz;   // shifts whose increments enter y
     int refine_iters = 0;
     for (int round = 0; round < 3 && prm->refine; round++) {
         std::vector<std::pair<int, int>> bad;   // (shift, rhs)
@@ -236,6 +240,14 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             for (int q = 0; q < R; q++)
                 if (res[(size_t)j * R + q] > prm->tol) bad.push_back({j, q});
         if (bad.empty()) break;
+        // a bad shift with no increment so far (frozen for every RHS in the
+        // FP64 phase, its increment never written): start its fields at zero
+        int jbad = -1;
+        for (auto &pr : bad) jbad = std::max(jbad, pr.first);
+        if (jbad >= ncomb) {
+            OVL_HIP(launch_zero(L, sub(X, L.V, ncomb * R, (jbad + 1 - ncomb) * R), st));
+            ncomb = jbad + 1;
+        }
         for (size_t b0 = 0; b0 < bad.size(); b0 += NB) {
             const int nbat = (int)std::min<size_t>(NB, bad.size() - b0);
             double bshift[NR], btol[NR];
@@ -292,7 +304,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             if (!(res[(size_t)j * R + q] <= prm->tol)) status = OVL_NOT_CONVERGED;
         }
     if (stats) stats->refine_iterations += refine_iters;
-    OVL_HIP(launch_combine(L, weights, nshift, X, y, st, switched));
+    OVL_HIP(launch_combine(L, weights, ncomb, X, y, st, switched));
     return status;
 }
 

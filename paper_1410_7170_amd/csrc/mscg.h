@@ -82,7 +82,7 @@ struct BlkOpts {
     const double *rhs_shift = nullptr;  // per-RHS base shift (host), default the smallest shift
     const double *rhs_tol = nullptr;    // per-RHS tolerance (host), default prm->tol
     Fld x_ext{};                        // x mode: caller's FP64 x_j (field j*nrhs + r)
-    bool x_zero_start = false;          // x mode: the x_j start at zero (set by the first pass)
+    int x_zero_shifts = 0;              // x mode: x_j (j < this) start at zero (set by the first pass)
     int *iters_out = nullptr;           // per-RHS iteration counts (host)
     // Each RHS stops at the iteration at which |r| <= switch_rel |b| (the
     // block pass then covers the iterations it did); once no unfinished RHS

@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, help="workload recipe index (2 = 32^3x64)")
+    ap.add_argument("--workload", type=int, default=2, help="workload recipe index (2 = 32^3x64)")
     ap.add_argument("--form", default="auto", help="overlap form for the timed steps")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -90,16 +90,16 @@ def main():
     import paper_1410_7170_amd as ovl
 
     torch.cuda.set_device(0)
-    cfg = synth.CONFIGS[args.config]
+    cfg = synth.WORKLOADS[args.workload]
     dims = cfg["dims"]
     npoles = cfg["poles"]
     t_setup = time.time()
-    U = synth.config_gauge(args.config)
-    b = synth.config_sources(args.config)
+    U = synth.workload_gauge(args.workload)
+    b = synth.workload_sources(args.workload)
     lat = ovl.Lattice(dims)
     V = lat.V
     G = ovl.Gauge(lat, torch.from_numpy(U).cuda())
-    v0 = synth.gaussian_spinor(V, synth.SEED_BASE + 10 * args.config + 3)[0]
+    v0 = synth.gaussian_spinor(V, synth.SEED_BASE + 10 * args.workload + 3)[0]
     start = ovl.Spinor.from_canonical(lat, torch.from_numpy(v0).cuda(), ovl.F64)
     lo, hi = ovl.spectral_bounds(lat, G, -RHO, 300, start)
     shifts, weights, delta = ovl.zolotarev(lo, hi, npoles)
@@ -291,17 +291,17 @@ def multi_rhs_line(args, ovl, synth, np, torch):
     apply (one link load serves all 12 RHS in every stencil), against the
     plain FP64 single-RHS form on the first of them."""
     cfg = args.multi_rhs
-    c = synth.CONFIGS[cfg]
+    c = synth.WORKLOADS[cfg]
     dims = c["dims"]
     lat = ovl.Lattice(dims)
-    U = synth.config_gauge(cfg)
+    U = synth.workload_gauge(cfg)
     G = ovl.Gauge(lat, torch.from_numpy(U).cuda())
     del U
     v0 = synth.gaussian_spinor(lat.V, synth.SEED_BASE + 10 * cfg + 3)[0]
     lo, hi = ovl.spectral_bounds(lat, G, -RHO, 300, ovl.Spinor.from_canonical(lat, torch.from_numpy(v0).cuda(),
                                                                                 ovl.F64))
     shifts, weights, delta = ovl.zolotarev(lo, hi, c["poles"])
-    b = synth.config_sources(cfg)
+    b = synth.workload_sources(cfg)
     B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
     out = ovl.Spinor(lat, ovl.F64, B.nrhs)
     tune = ovl.autotune_stencil(lat, G, B.nrhs)

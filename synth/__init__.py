@@ -8,7 +8,7 @@ bytes:
 * spinor ``psi[site, spin, colour]`` (``[rhs, site, spin, colour]`` for several),
 * ``site = ((x0*L1 + x1)*L2 + x2)*L3 + x3`` with x0 the (antiperiodic) time axis.
 
-Workload recipes follow the overlap benchmark configurations: links
+Workload recipes (the benchmark workloads, WORKLOADS): links
 ``exp(i*eps0*H)`` with H a seeded traceless Hermitian Gaussian matrix, then
 ``n_stout`` stout-smearing steps at ``rho_stout = 0.1`` (Section "Smearing and
 Normality", eq. (stout)), Gaussian or spin-colour point sources.
@@ -121,7 +121,7 @@ def point_sources(V: int, site: int) -> np.ndarray:
 
 # Workload recipes: lattice (L0=t, L1, L2, L3), link eps0, stout steps,
 # sources, Zolotarev poles.
-CONFIGS = {
+WORKLOADS = {
     0: dict(name="4^4 fp64 dense check", dims=(4, 4, 4, 4), eps0=0.5, n_stout=0,
             source="gaussian", nrhs=1, poles=20),
     1: dict(name="16^3x32 fp64/fp32", dims=(32, 16, 16, 16), eps0=0.3, n_stout=2,
@@ -135,13 +135,13 @@ CONFIGS = {
 }
 
 
-def config_gauge(cfg: int, dims=None) -> np.ndarray:
-    c = CONFIGS[cfg]
+def workload_gauge(cfg: int, dims=None) -> np.ndarray:
+    c = WORKLOADS[cfg]
     return gauge(dims or c["dims"], c["eps0"], SEED_BASE + 10 * cfg, c["n_stout"])
 
 
-def config_sources(cfg: int, dims=None) -> np.ndarray:
-    c = CONFIGS[cfg]
+def workload_sources(cfg: int, dims=None) -> np.ndarray:
+    c = WORKLOADS[cfg]
     V = volume(dims or c["dims"])
     if c["source"] == "point":
         return point_sources(V, random_site(V, SEED_BASE + 10 * cfg + 2))

@@ -59,7 +59,7 @@ def both_sides(ovl, dims, U, npoles=20, start_seed=99):
 def test_spectral_bounds_bracket_exact_spectrum(ovl):
     dims = (4, 4, 4, 4)
     note("spectral bounds 4^4")
-    U = synth.config_gauge(0)
+    U = synth.workload_gauge(0)
     lat = ovl.Lattice(dims)
     G = ovl.Gauge(lat, dev(U))
     v0 = synth.gaussian_spinor(lat.V, 5)[0]
@@ -97,13 +97,13 @@ def test_sign_q_matches_exact_dense_sign(ovl):
     """4^4 workload: Zolotarev + multishift CG on the GPU against W sign(Delta) W^H."""
     dims = (4, 4, 4, 4)
     note("sign(Q) vs dense 4^4")
-    U = synth.config_gauge(0)
+    U = synth.workload_gauge(0)
     lat = ovl.Lattice(dims)
     G = ovl.Gauge(lat, dev(U))
     S, w = dense.sign_q_exact(oracle.Lattice(dims), U, M0)
     aw = np.abs(w)
     s, wt, delta = ovl.zolotarev(0.99 * aw.min(), 1.01 * aw.max(), 20)
-    b = synth.config_sources(0)[0]
+    b = synth.workload_sources(0)[0]
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0)
     ovl.sign_q_apply(lat, G, M0, s, wt, B, O, ovl.default_params(tol=1e-13))
@@ -191,7 +191,7 @@ def test_ginsparg_wilson_gpu(ovl):
 
 def test_not_converged_and_zero_rhs(ovl):
     dims = (4, 4, 4, 4)
-    U = synth.config_gauge(0)
+    U = synth.workload_gauge(0)
     lat = ovl.Lattice(dims)
     G = ovl.Gauge(lat, dev(U))
     s, w, d = ovl.zolotarev(0.4, 6.0, 12)
@@ -212,7 +212,7 @@ def test_not_converged_and_zero_rhs(ovl):
 
 def test_nonfinite_input_reported(ovl):
     dims = (4, 4, 4, 4)
-    U = synth.config_gauge(0)
+    U = synth.workload_gauge(0)
     lat = ovl.Lattice(dims)
     G = ovl.Gauge(lat, dev(U))
     s, w, d = ovl.zolotarev(0.4, 6.0, 8)

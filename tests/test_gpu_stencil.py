@@ -175,13 +175,13 @@ def test_q2_diagonal_gpu(ovl):
 
 def test_wilson_apply_16x32_full(ovl):
     """The 16^3x32 workload (links exp(i 0.3 H), 2 stout steps), every site."""
-    dims = synth.CONFIGS[1]["dims"]
+    dims = synth.WORKLOADS[1]["dims"]
     note(f"wilson_apply full {dims}")
     lat = ovl.Lattice(dims)
     olat = oracle.Lattice(dims)
-    U = synth.config_gauge(1)
+    U = synth.workload_gauge(1)
     G = ovl.Gauge(lat, dev(U))
-    psi = synth.config_sources(1)[0]
+    psi = synth.workload_sources(1)[0]
     ref = oracle.dw(olat, U, M0, psi)
     for prec in (0, 1, 2):
         inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
@@ -193,12 +193,12 @@ def test_wilson_apply_16x32_full(ovl):
 def test_wilson_apply_32x64_full(ovl):
     """The 32^3x64 workload in the benchmark's launch shape, every site against
     the oracle."""
-    dims = synth.CONFIGS[2]["dims"]
+    dims = synth.WORKLOADS[2]["dims"]
     note(f"wilson_apply sampled {dims}")
     lat = ovl.Lattice(dims)
-    U = synth.config_gauge(2)
+    U = synth.workload_gauge(2)
     G = ovl.Gauge(lat, dev(U))
-    psi = synth.config_sources(2)[0]
+    psi = synth.workload_sources(2)[0]
     inp = ovl.Spinor.from_canonical(lat, dev(psi), 0)
     out = ovl.Spinor(lat, 0)
     ovl.wilson_apply(lat, G, M0, inp, out)
@@ -251,14 +251,14 @@ def test_stream_boundary_phases_and_q2(ovl, bc, ts):
 def test_wilson_stream_full_workloads(ovl, cfg, ts):
     """Every site of the 16^3x32 and 32^3x64 fields in the streaming form, all
     three precisions against the oracle."""
-    dims = synth.CONFIGS[cfg]["dims"]
+    dims = synth.WORKLOADS[cfg]["dims"]
     note(f"wilson_apply streaming full {dims} stream_t={ts}")
     lat = ovl.Lattice(dims)
     lat.stream_t = ts
     olat = oracle.Lattice(dims)
-    U = synth.config_gauge(cfg)
+    U = synth.workload_gauge(cfg)
     G = ovl.Gauge(lat, dev(U))
-    psi = synth.config_sources(cfg)[0]
+    psi = synth.workload_sources(cfg)[0]
     ref = oracle.dw(olat, U, M0, psi)
     for prec in (0, 1, 2):
         inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)

@@ -55,12 +55,12 @@ def bounds(ovl, lat, G, cfg, npoles):
 
 def test_point_sources_24x48_batched(ovl):
     cfg = 3
-    dims = synth.CONFIGS[cfg]["dims"]
+    dims = synth.WORKLOADS[cfg]["dims"]
     note(f"12 point sources {dims}, mixed vs FP64 blocked")
     lat = ovl.Lattice(dims)
-    G = ovl.Gauge(lat, dev(synth.config_gauge(cfg)))
+    G = ovl.Gauge(lat, dev(synth.workload_gauge(cfg)))
     s, w, d = bounds(ovl, lat, G, cfg, 20)
-    b = synth.config_sources(cfg)
+    b = synth.workload_sources(cfg)
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0, 12)
     st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-10, maxiter=5000,
@@ -76,12 +76,12 @@ def test_point_sources_24x48_batched(ovl):
 
 def test_48x96_stencil_and_overlap(ovl):
     cfg = 4
-    dims = synth.CONFIGS[cfg]["dims"]
+    dims = synth.WORKLOADS[cfg]["dims"]
     note(f"full-size workload {dims}: stencil vs oracle, 24-pole overlap")
     lat = ovl.Lattice(dims)
-    U = synth.config_gauge(cfg)
+    U = synth.workload_gauge(cfg)
     G = ovl.Gauge(lat, dev(U))
-    psi = synth.config_sources(cfg)[0]
+    psi = synth.workload_sources(cfg)[0]
     ref = oracle.dw(oracle.Lattice(dims), U, M0, psi)
     del U
     for prec, tol in ((0, 1e-12), (1, 1e-6)):

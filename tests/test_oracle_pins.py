@@ -27,7 +27,7 @@ def lat44():
 @pytest.fixture(scope="module")
 def U44():
     # the dense-check workload: 4^4, links exp(i 0.5 H), no smearing
-    return synth.config_gauge(0)
+    return synth.workload_gauge(0)
 
 
 @pytest.fixture(scope="module")
@@ -271,7 +271,7 @@ def test_zolotarev_mscg_matches_exact_sign(lat44, U44, dense44):
     w = np.abs(dense44["w"])
     s, wt, delta = oracle.zolotarev(0.99 * w.min(), 1.01 * w.max(), 20)
     assert delta < 1e-13
-    b = synth.config_sources(0)[0]
+    b = synth.workload_sources(0)[0]
     out, iters, _ = oracle.sign_q(lat44, U44, M0, s, wt, b, 1e-13, 5000)
     exact = (dense44["S"] @ b.reshape(-1)).reshape(b.shape)
     assert rel(out, exact) < 1e-12

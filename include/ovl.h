@@ -156,8 +156,9 @@ typedef struct {
                                 iterations (same iterates, fewer vector passes).
                                 Mixed mode: block length of the FP32 phase,
                                 0 meaning 32 */
-    double sloppy_below;     /* mixed: iterate in FP64 (blocked, FP64 x_l) until
-                                the base residual ||r||/||b|| falls below this,
+    double sloppy_below;     /* mixed: iterate in FP64 (blocked, accumulating the
+                                weighted sum directly) until each RHS's base
+                                residual ||r||/||b|| falls below this,
                                 then hand the recurrences over to FP32; rounding
                                 of the sloppy phase then enters the shifted
                                 residuals only at this level.  0: FP32 from the

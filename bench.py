@@ -6,7 +6,16 @@ source, 20 Zolotarev poles over Lanczos bounds of |Q|, multishift CG to a
 1e-10 relative residual on every shifted system): the whole hot path -- field
 packing is done once, the stencil, Q^2, the multishift iteration with its
 reductions, the combination and the final FP64 stencil run inside every step.
-Inputs are synthetic and seeded; nothing is read from disk.
+Inputs are synthetic and seeded; nothing is read from disk except the
+oracle's stored samples of the same apply (tests/golden), for the error line.
+
+Besides the timed steps the line reports: the stencil's bandwidth in each
+precision; the FP64 forms' applies/s (the speedups are against the fastest of
+them, with the plain form's ratio kept as a second key); the timed result's
+error against the FP64 oracle at the sampled sites and its Ginsparg-Wilson
+residual; the 16^3x32 workload (operator bandwidth, overlap applies); the
+batched 24^3x48 point-source workload; and the oracle's own speed on the
+host cores.
 
 Prints one JSON line.  Single GPU only.
 """
@@ -16,6 +25,8 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -24,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 RHO = 1.6
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def parse():
@@ -37,7 +49,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--forms", default="fp64,fp64_blocked",
-                    help="comma-separated forms timed once each besides the timed form")
+                    help="comma-separated forms timed besides the timed form")
+    ap.add_argument("--form-steps", type=int, default=2, help="timed applies of each form in --forms")
+    ap.add_argument("--no-checks", action="store_true",
+                    help="skip the Ginsparg-Wilson residual and the oracle-sample error")
+    ap.add_argument("--small", type=int, default=1,
+                    help="workload recipe of the small line (1 = 16^3x32); -1 skips it")
     ap.add_argument("--multi-rhs", type=int, default=3,
                     help="workload recipe of the batched multi-RHS line (3 = 24^3x48, 12 point "
                          "sources); -1 skips it")
@@ -76,6 +93,77 @@ def load_traffic(kernel: str, src: str, workload: str):
     return None
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def median_event_us(torch, fn, n=20, warm=3):
+    """Median over n launches of fn, each bracketed by HIP events on the
+    current stream (the library launches on it)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warm):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in ev) * 1e3
+
+
+# compulsory bytes per site of one stencil (12-real links): in + out + 4 links
+SITE_BYTES = {0: 192 + 192 + 4 * 96, 1: 96 + 96 + 4 * 48, 2: 52 + 52 + 4 * 24}
+
+
+def operator_bandwidth(ovl, torch, lat, G, b, q2=False):
+    """Median time and algorithmic GB/s of wilson_apply (and q2_apply: two
+    stencils, the second also reading the input for the shift term) per
+    storage precision."""
+    out = {}
+    for prec in (ovl.F64, ovl.F32, ovl.F16S):
+        inp = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), prec)
+        o = ovl.Spinor(lat, prec)
+        us = median_event_us(torch, lambda: ovl.wilson_apply(lat, G, -RHO, inp, o))
+        gbps = SITE_BYTES[prec] * lat.V / (us * 1e-6) / 1e9
+        d = dict(us=round(us, 2), GBps=round(gbps, 1), frac=round(gbps / HBM_PEAK_GBPS, 4),
+                 bytes_per_site=SITE_BYTES[prec])
+        if q2:
+            ws = ovl.workspace(lat, ovl.OP_Q2, prec, 1)
+            us2 = median_event_us(torch, lambda: ovl.q2_apply(lat, G, -RHO, 0.41, inp, o, ws))
+            # two stencils, plus the second's read of the input for the shift term
+            b2 = 2 * SITE_BYTES[prec] + (192 >> prec if prec < 2 else 52)
+            g2 = b2 * lat.V / (us2 * 1e-6) / 1e9
+            d["q2"] = dict(us=round(us2, 2), GBps=round(g2, 1), frac=round(g2 / HBM_PEAK_GBPS, 4), bytes_per_site=b2)
+        out[ovl.PREC_NAMES[prec]] = d
+        log(f"{lat.dims} stencil {ovl.PREC_NAMES[prec]}: {us:.1f} us {gbps:.0f} GB/s")
+    return out
+
+
+def params_for(ovl, form, tol, profile=False):
+    # an optional ":m<k>" suffix sets the block length of the blocked forms
+    if ":m" in form:
+        form, m = form.split(":m", 1)
+        prm = params_for(ovl, form, tol, profile)
+        prm.block = int(m)
+        return prm
+    if form == "fp64":       # plain FP64: every shifted vector updated every iteration
+        return ovl.default_params(tol=tol, maxiter=5000, profile=int(profile))
+    if form == "fp64_blocked":
+        return ovl.default_params(tol=tol, maxiter=5000, profile=int(profile), block=16)
+    if form.startswith("mixed"):
+        # FP64 iterations until |r|/|b| < sloppy_below ("mixed@<value>", default
+        # the library's), then the FP32 bulk with FP64 residual replacement;
+        # FP64 verification and refinement of every shift.  Block lengths: the
+        # library's (FP64 phase 16, FP32 phase 32) unless ":m<k>" sets the FP32
+        # phase's
+        prm = ovl.default_params(tol=tol, maxiter=5000, profile=int(profile), mode=ovl.SOLVE_MIXED)
+        if "@" in form:
+            prm.sloppy_below = float(form.split("@", 1)[1])
+        return prm
+    raise ValueError(form)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -110,79 +198,33 @@ def main():
         tune = dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, timings="fixed")
     else:
         tune = ovl.autotune_stencil(lat, G, B.nrhs)
-    setup_s = time.time() - t_setup
-    print(f"[bench] setup {setup_s:.1f}s dims={dims} |Q| in [{lo:.4f}, {hi:.4f}] delta={delta:.2e}",
-          file=sys.stderr, flush=True)
-
-    stream = torch.cuda.current_stream()
+    log(f"setup {time.time() - t_setup:.1f}s dims={dims} |Q| in [{lo:.4f}, {hi:.4f}] delta={delta:.2e}")
 
     # ---- Wilson stencil bandwidth, one launch = D_W on every site
-    site_bytes = {ovl.F64: 192 + 192 + 4 * 96, ovl.F32: 96 + 96 + 4 * 48, ovl.F16S: 52 + 52 + 4 * 24}
-    stencil = {}
-    for prec in (ovl.F64, ovl.F32, ovl.F16S):
-        inp = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), prec)
-        o = ovl.Spinor(lat, prec)
-        for _ in range(3):
-            ovl.wilson_apply(lat, G, -RHO, inp, o)
-        n = 20
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(n):
-            ovl.wilson_apply(lat, G, -RHO, inp, o)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) * 1e-3 / n
-        gbps = site_bytes[prec] * V / sec / 1e9
-        stencil[ovl.PREC_NAMES[prec]] = dict(us=round(sec * 1e6, 2), GBps=round(gbps, 1),
-                                             frac=round(gbps / HBM_PEAK_GBPS, 4),
-                                             bytes_per_site=site_bytes[prec])
-        print(f"[bench] stencil {ovl.PREC_NAMES[prec]}: {sec*1e6:.1f} us {gbps:.0f} GB/s", file=sys.stderr, flush=True)
+    stencil = operator_bandwidth(ovl, torch, lat, G, b)
 
-    # ---- overlap applies
-    def params(form, profile=False):
-        # an optional ":m<k>" suffix sets the block length of the blocked forms
-        if ":m" in form:
-            form, m = form.split(":m", 1)
-            prm = params(form, profile)
-            prm.block = int(m)
-            return prm
-        if form == "fp64":       # plain FP64: every shifted vector updated every iteration
-            return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile))
-        if form == "fp64_blocked":
-            return ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), block=16)
-        if form.startswith("mixed"):
-            # FP64 iterations until |r|/|b| < sloppy_below ("mixed@<value>", default
-            # the library's), then the FP32 bulk with FP64 residual replacement;
-            # FP64 verification and refinement of every shift
-            # block lengths: the library's (FP64 phase 16, FP32 phase 32) unless ":m<k>"
-            # sets the FP32 phase's
-            prm = ovl.default_params(tol=args.tol, maxiter=5000, profile=int(profile), mode=ovl.SOLVE_MIXED)
-            if "@" in form:
-                prm.sloppy_below = float(form.split("@", 1)[1])
-            return prm
-        raise ValueError(form)
+    def overlap(form, profile=False, src=B, dst=out):
+        return ovl.overlap_apply(lat, G, RHO, shifts, weights, src, dst, params_for(ovl, form, args.tol, profile))
 
-    def overlap(form, profile=False):
-        return ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, params(form, profile))
-
+    # ---- the reference forms, each timed over a few applies
     forms = [f for f in args.forms.split(",") if f]
     timed_form = "mixed" if args.form == "auto" else args.form
     if "fp64" not in forms:
         forms.insert(0, "fp64")
-    results = {}
-    outputs = {}
+    results, outputs = {}, {}
     for form in forms:
         st = overlap(form)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = overlap(form)
+        for _ in range(args.form_steps):
+            st = overlap(form)
         torch.cuda.synchronize()
-        results[form] = dict(seconds=time.perf_counter() - t0, iterations=st["iterations"],
+        results[form] = dict(seconds=(time.perf_counter() - t0) / args.form_steps, iterations=st["iterations"],
                              shift_iters=st["shift_iters"][0], reliable_updates=st["reliable_updates"],
                              refine_iterations=st["refine_iterations"],
                              max_true_residual=max(st["true_residual"][0]))
         outputs[form] = out.to_canonical().cpu().numpy()
+        log(f"form {form}: {len(b) / results[form]['seconds']:.3f} applies/s, {st['iterations']} iterations")
     ref = outputs["fp64"]
     for form in forms:
         results[form]["rel_diff_vs_fp64"] = float(np.linalg.norm(outputs[form] - ref) / np.linalg.norm(ref))
@@ -227,24 +269,33 @@ def main():
                     algorithmic_bytes_per_launch=round(bytes_per_launch),
                     share_of_step=round(ksec[dom] / (elapsed), 3), source=src)
 
-    # ---- batched multi-RHS workload (its own lattice, after the timed region)
-    mrhs = None
-    if args.multi_rhs >= 0:
-        del G, B, out
-        torch.cuda.empty_cache()
-        mrhs = multi_rhs_line(args, ovl, synth, np, torch)
+    # ---- accuracy of the timed form: oracle samples and the Ginsparg-Wilson relation
+    checks = None
+    if not args.no_checks:
+        checks = accuracy_checks(args, ovl, torch, np, lat, B, out, got, overlap, timed_form)
+
+    nrhs = len(b)
+    fp64_rate = nrhs / results["fp64"]["seconds"]
+    best64 = min((f for f in results if f.startswith("fp64")), key=lambda f: results[f]["seconds"])
+    best64_rate = nrhs / results[best64]["seconds"]
+
+    # ---- the small workload and the batched multi-RHS workload (own lattices)
+    del G, B, out, start
+    torch.cuda.empty_cache()
+    small = small_line(args, ovl, synth, np, torch) if args.small >= 0 else None
+    torch.cuda.empty_cache()
+    mrhs = multi_rhs_line(args, ovl, synth, np, torch) if args.multi_rhs >= 0 else None
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, dims, U, b[0], shifts, weights, results["fp64"]["shift_iters"])
 
-    nrhs = len(b)
-    fp64_rate = nrhs / results["fp64"]["seconds"]
     # one unpack and one pack of a packed FP64 field: plain streaming kernels
     # of known size for counter calibration
-    Bc = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), ovl.F64)
-    ovl.unpack_spinor(lat, Bc, torch.empty((1, V, 4, 3), dtype=torch.complex128, device="cuda"))
+    lat2 = ovl.Lattice(dims)
+    Bc = ovl.Spinor.from_canonical(lat2, torch.from_numpy(b[:1]).cuda(), ovl.F64)
+    ovl.unpack_spinor(lat2, Bc, torch.empty((1, V, 4, 3), dtype=torch.complex128, device="cuda"))
     torch.cuda.synchronize()
     line = {
         "metric": "Wilson stencil HBM GB/s + D_ov applies/sec @32^3x64, mixed vs FP64, 1e-10 res",
@@ -270,26 +321,104 @@ def main():
                           refine_iterations=v["refine_iterations"], max_true_residual=v["max_true_residual"])
                   for k, v in results.items()},
         "timed_rel_diff_vs_fp64": timed_diff,
-        "fp64_applies_per_s": round(fp64_rate, 4),
-        "speedup_vs_fp64": round(applies_per_s / fp64_rate, 3),
-        "speedup_vs_fp64_blocked": (round(applies_per_s * results["fp64_blocked"]["seconds"] / nrhs, 3)
-                                    if "fp64_blocked" in results else None),
+        "fp64_applies_per_s": round(best64_rate, 4),
+        "fp64_form": best64,
+        "speedup_vs_fp64": round(applies_per_s / best64_rate, 3),
+        "speedup_vs_fp64_plain": round(applies_per_s / fp64_rate, 3),
         "iterations": last["iterations"],
         "timed_max_true_residual": max(max(r) for r in last["true_residual"][:nrhs]),
         "timed_refine_iterations": last["refine_iterations"],
+        "accuracy": checks,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "small": small,
         "multi_rhs": mrhs,
         "autotune": tune["timings"],
     }
     print(json.dumps(line))
 
 
+def accuracy_checks(args, ovl, torch, np, lat, B, out, got, overlap, form):
+    """Error of the timed form's D_ov b against the oracle's at the sampled
+    sites (tests/golden, written from the oracle alone), and the
+    Ginsparg-Wilson residual |g5 D b + D g5 b - (1/rho) D g5 D b| / |b| of
+    eq. (GW) in this normalisation."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import load_golden
+
+    res = {}
+    path = os.path.join(GOLDEN, f"overlap_{lat.dims[1]}x{lat.dims[2]}x{lat.dims[3]}x{lat.dims[0]}_gaussian.txt")
+    if os.path.exists(path):
+        gold = load_golden(path)
+        sites = gold["sites"]
+        g = gold["rhs"][0]
+        mine = got[0].reshape(-1, 12)[sites]
+        err = np.linalg.norm(mine - g["vals"], axis=-1)
+        res["oracle_samples"] = dict(
+            sites=len(sites), max_site_err_over_rms=float(err.max() / g["rms"]),
+            max_site_rel_err=float((err / np.linalg.norm(g["vals"], axis=-1)).max()),
+            rel_l2_sampled=float(np.linalg.norm(mine - g["vals"]) / np.linalg.norm(g["vals"])),
+            oracle_tol=float(gold["meta"].get("tol", "nan")))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def g5(v):
+        w = v.copy()
+        w[..., :2, :] *= -1
+        return w
+
+    def D(v):
+        src = ovl.Spinor.from_canonical(lat, dev(v), ovl.F64)
+        overlap(form, src=src, dst=out)
+        return out.to_canonical().cpu().numpy()
+
+    b = B.to_canonical().cpu().numpy()
+    Db = got
+    lhs = g5(Db) + D(g5(b))
+    rhs = D(g5(Db)) / RHO
+    res["ginsparg_wilson_residual"] = float(np.linalg.norm(lhs - rhs) / np.linalg.norm(b))
+    log(f"accuracy: {res}")
+    return res
+
+
+def small_line(args, ovl, synth, np, torch):
+    """The 16^3x32 workload: wilson_apply and q2_apply bandwidth in every
+    precision and the overlap apply's rate in the FP64 and mixed forms."""
+    cfg = args.small
+    c = synth.WORKLOADS[cfg]
+    dims = c["dims"]
+    lat = ovl.Lattice(dims)
+    G = ovl.Gauge(lat, torch.from_numpy(synth.workload_gauge(cfg)).cuda())
+    b = synth.workload_sources(cfg)
+    v0 = synth.gaussian_spinor(lat.V, synth.SEED_BASE + 10 * cfg + 3)[0]
+    lo, hi = ovl.spectral_bounds(lat, G, -RHO, 300, ovl.Spinor.from_canonical(lat, torch.from_numpy(v0).cuda(),
+                                                                                ovl.F64))
+    shifts, weights, delta = ovl.zolotarev(lo, hi, c["poles"])
+    ovl.autotune_stencil(lat, G, 1)
+    ops = operator_bandwidth(ovl, torch, lat, G, b, q2=True)
+    B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
+    out = ovl.Spinor(lat, ovl.F64)
+    rates = {}
+    for form in ("fp64", "fp64_blocked", "mixed"):
+        prm = params_for(ovl, form, args.tol)
+        ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 3
+        for _ in range(n):
+            st = ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
+        torch.cuda.synchronize()
+        rates[form] = dict(applies_per_s=round(n / (time.perf_counter() - t0), 3), iterations=st["iterations"][0],
+                           max_true_residual=max(st["true_residual"][0]))
+    log(f"small {dims}: {rates}")
+    return dict(workload=f"{dims[1]}^3x{dims[0]}, {c['poles']} Zolotarev poles, tol {args.tol:g}",
+                operators=ops, overlap=rates)
+
+
 def multi_rhs_line(args, ovl, synth, np, torch):
     """The batched multi-RHS workload: the 12 spin-colour point sources of one
     seeded site on 24^3x48 (20 poles), solved together in one mixed overlap
-    apply (one link load serves all 12 RHS in every stencil), against the
-    plain FP64 single-RHS form on the first of them."""
+    apply, against the FP64 single-RHS forms (blocked, the faster, and plain)
+    on the first of them."""
     cfg = args.multi_rhs
     c = synth.WORKLOADS[cfg]
     dims = c["dims"]
@@ -305,7 +434,7 @@ def multi_rhs_line(args, ovl, synth, np, torch):
     B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
     out = ovl.Spinor(lat, ovl.F64, B.nrhs)
     tune = ovl.autotune_stencil(lat, G, B.nrhs)
-    prm = ovl.default_params(tol=args.tol, maxiter=5000, mode=ovl.SOLVE_MIXED)
+    prm = params_for(ovl, "mixed", args.tol)
     ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -314,60 +443,111 @@ def multi_rhs_line(args, ovl, synth, np, torch):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rate = B.nrhs * args.multi_rhs_steps / el
-    # plain FP64, one RHS at a time
+    got = out.to_canonical().cpu().numpy()[0]
+    del out
+    # FP64, one RHS at a time: both FP64 forms, each over two applies
     B1 = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), ovl.F64)
     out1 = ovl.Spinor(lat, ovl.F64)
-    p64 = ovl.default_params(tol=args.tol, maxiter=5000)
-    ovl.overlap_apply(lat, G, RHO, shifts, weights, B1, out1, p64)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st64 = ovl.overlap_apply(lat, G, RHO, shifts, weights, B1, out1, p64)
-    torch.cuda.synchronize()
-    el64 = time.perf_counter() - t1
-    got = out.to_canonical().cpu().numpy()[0]
+    single = {}
+    for form in ("fp64_blocked", "fp64"):
+        p64 = params_for(ovl, form, args.tol)
+        ovl.overlap_apply(lat, G, RHO, shifts, weights, B1, out1, p64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(2):
+            ovl.overlap_apply(lat, G, RHO, shifts, weights, B1, out1, p64)
+        torch.cuda.synchronize()
+        single[form] = 2.0 / (time.perf_counter() - t1)
     ref = out1.to_canonical().cpu().numpy()[0]
     line = dict(workload=f"overlap apply {dims[1]}^3x{dims[0]}, 12 spin-colour point sources at one site, "
                          f"{c['poles']} Zolotarev poles, tol {args.tol:g}",
-                nrhs=B.nrhs, form="mixed (FP64 until 1e-5, FP32 bulk, FP64 verification)",
+                nrhs=B.nrhs, form="mixed (FP64 until the hand-over, FP32 bulk, FP64 verification)",
                 applies_per_s=round(rate, 4), seconds_per_batch=round(el / args.multi_rhs_steps, 4),
-                fp64_single_rhs_applies_per_s=round(1.0 / el64, 4),
-                speedup_vs_fp64_single_rhs=round(rate * el64, 3),
+                fp64_single_rhs_applies_per_s=round(single["fp64_blocked"], 4),
+                fp64_plain_single_rhs_applies_per_s=round(single["fp64"], 4),
+                speedup_vs_fp64_single_rhs=round(rate / single["fp64_blocked"], 3),
+                speedup_vs_fp64_plain_single_rhs=round(rate / single["fp64"], 3),
                 iterations=st["iterations"], max_true_residual=max(max(r) for r in st["true_residual"]),
                 refine_iterations=st["refine_iterations"],
                 rel_diff_rhs0_vs_fp64=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
                 stencil_order={k: tune[k] for k in ("tile_t", "stream_t", "stream_t64")},
                 autotune=tune["timings"])
-    print(f"[bench] multi-rhs {dims}: {rate:.3f} RHS-applies/s, FP64 single {1.0/el64:.3f}/s, "
-          f"max residual {line['max_true_residual']:.2e}", file=sys.stderr, flush=True)
+    log(f"multi-rhs {dims}: {rate:.3f} RHS-applies/s, FP64 single {single}, "
+        f"max residual {line['max_true_residual']:.2e}")
     return line
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(args, dims, U, b, shifts, weights, shift_iters):
-    """Oracle timing on a bounded sample: the FP64 oracle's multishift CG on
-    the full 32^3x64 field, capped at a few iterations with every shift
-    active, plus one oracle stencil; the full apply is then priced with the
-    per-shift iteration counts of the same solve."""
+    """The oracle as it stands, timed on the host cores (medians).  At 32^3x64
+    one oracle apply takes minutes, so the sample is: Q^2 (5 runs) and k
+    multishift iterations with every shift active (3 runs) on the full
+    32^3x64 field, which price one apply from the per-shift iteration counts of
+    the same solve; a whole oracle apply at 16^3x32 checks that pricing; Q^2 at
+    16^3x32 on one core gives the single-core rate."""
     import numpy as np
     import oracle
+    import synth
 
     lat = oracle.Lattice(dims)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.max_threads()
+    med = lambda f, n: statistics.median(_t(f) for _ in range(n))
+    s0 = float(min(shifts))
     k = args.cpu_sample_iters
-    t0 = time.perf_counter()
-    oracle.q2(lat, U, -RHO, b, float(min(shifts)))
-    t_q2 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.mscg(lat, U, -RHO, shifts, b, 1e-300, k)
-    t_k = time.perf_counter() - t0
+    t_q2 = med(lambda: oracle.q2(lat, U, -RHO, b, s0), 5)
+    t_k = med(lambda: oracle.mscg(lat, U, -RHO, shifts, b, 1e-300, k), 3)
     t_shift = max(t_k / k - t_q2, 0.0) / len(shifts)
-    n_iter = max(shift_iters)
-    act_iters = sum(shift_iters)
-    est = n_iter * t_q2 + act_iters * t_shift + t_q2 / 2
+
+    def price(t_q2, t_shift, shift_iters):
+        return max(shift_iters) * t_q2 + sum(shift_iters) * t_shift + t_q2 / 2
+
+    est = price(t_q2, t_shift, shift_iters)
+    # the 16^3x32 workload: a whole oracle apply against its pricing
+    c1 = synth.WORKLOADS[1]
+    lat1 = oracle.Lattice(c1["dims"])
+    U1 = synth.workload_gauge(1)
+    b1 = synth.workload_sources(1)[0]
+    v1 = synth.gaussian_spinor(lat1.V, synth.SEED_BASE + 13)[0]
+    lo1, hi1 = oracle.spectral_interval(lat1, U1, -RHO, v1, 100)
+    s1, w1, _ = oracle.zolotarev(lo1, hi1, c1["poles"])
+    t0 = time.perf_counter()
+    _, it1, _ = oracle.overlap(lat1, U1, RHO, s1, w1, b1, args.tol, 5000)
+    t_full1 = time.perf_counter() - t0
+    t_q2_1 = med(lambda: oracle.q2(lat1, U1, -RHO, b1, float(min(s1))), 3)
+    t_k1 = med(lambda: oracle.mscg(lat1, U1, -RHO, s1, b1, 1e-300, k), 3)
+    est1 = price(t_q2_1, max(t_k1 / k - t_q2_1, 0.0) / len(s1), list(it1))
+    # one core
+    oracle.set_threads(1)
+    try:
+        t_q2_1c = med(lambda: oracle.q2(lat1, U1, -RHO, b1, float(min(s1))), 3)
+    finally:
+        oracle.set_threads(cores)
     return dict(value=round(1.0 / est, 6), unit="D_ov applies/s", cores=cores, kind="oracle",
-                sample=f"oracle multishift CG, {k} iterations with all {len(shifts)} shifts active on the "
-                       f"full {dims[1]}^3x{dims[0]} field ({t_k:.1f}s) and one oracle Q^2 ({t_q2:.2f}s); "
-                       f"apply priced as {n_iter} Q^2 + {act_iters} shift updates + 1 stencil",
-                seconds_per_apply=round(est, 2))
+                cpu_model=cpu_model(),
+                sample=f"oracle Q^2 (median of 5, {t_q2:.2f}s) and {k} multishift iterations with all "
+                       f"{len(shifts)} shifts active (median of 3, {t_k:.1f}s) on the full {dims[1]}^3x{dims[0]} "
+                       f"field; one apply priced as {max(shift_iters)} Q^2 + {sum(shift_iters)} shift updates + "
+                       f"1 stencil",
+                seconds_per_apply=round(est, 2),
+                check_16x32=dict(measured_apply_s=round(t_full1, 2), priced_apply_s=round(est1, 2),
+                                 iterations=int(max(it1))),
+                single_core=dict(q2_16x32_s=round(t_q2_1c, 3), q2_16x32_all_cores_s=round(t_q2_1, 3),
+                                 parallel_speedup=round(t_q2_1c / t_q2_1, 2)))
+
+
+def _t(f):
+    t0 = time.perf_counter()
+    f()
+    return time.perf_counter() - t0
 
 
 if __name__ == "__main__":

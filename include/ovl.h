@@ -87,8 +87,9 @@ enum ovl_prec { OVL_F64 = 0, OVL_F32 = 1, OVL_F16S = 2 };
 /* solver precision modes */
 enum ovl_solve_mode {
     OVL_SOLVE_F64 = 0,   /* every vector, link and stencil in FP64 */
-    OVL_SOLVE_MIXED = 1  /* sloppy FP32/FP16 Krylov bulk, FP64 reliable updates,
-                            FP64 per-shift verification and final combination */
+    OVL_SOLVE_MIXED = 1  /* sloppy FP32 Krylov bulk, FP64 reliable updates,
+                            FP64 per-shift verification and final combination;
+                            reads the FP64 and FP32 links (gauge f64, f32) */
 };
 
 typedef struct {

@@ -28,8 +28,12 @@ DEFAULT_BC = (-1, 1, 1, 1)   # antiperiodic time, periodic space
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
+        # -O3 on the x86-64-v3 baseline (AVX2, FMA): the library is built once
+        # and may run on another host's CPU, so not -march=native.  ISO C mode
+        # (-std=c11) keeps floating-point contraction off, so the arithmetic is
+        # the plain loops' whatever the vector width.
         subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+            "gcc", "-O3", "-march=x86-64-v3", "-std=c11", "-fopenmp", "-fPIC", "-shared",
             os.path.join(_HERE, "oracle.c"), "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -65,6 +69,8 @@ def _load():
         lib.orc_sign_q.restype = I
         lib.orc_plaquette_sum.argtypes = [P, P]
         lib.orc_plaquette_sum.restype = D
+        lib.orc_set_threads.argtypes = [I]
+        lib.orc_max_threads.restype = I
         _lib = lib
     return _lib
 
@@ -227,6 +233,15 @@ def sign_q(lat: Lattice, U, m0: float, shifts, weights, b, tol: float, maxit: in
                             shifts.size, shifts.ctypes.data, weights.ctypes.data, b.ctypes.data,
                             out.ctypes.data, float(tol), int(maxit), iters.ctypes.data)
     return out, iters, it
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's site loops (for timing runs)."""
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
 
 
 def plaquette_sum(lat: Lattice, U) -> float:

@@ -16,6 +16,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -571,3 +572,8 @@ double orc_plaquette_sum(const int *L, const double *Ud)
     }
     return total;
 }
+
+/* ------------------------------------------------------------------ */
+/* OpenMP thread count of the loops above (timing runs on one core or all). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

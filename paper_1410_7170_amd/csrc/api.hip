@@ -327,7 +327,8 @@ static int solve_y(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     Fld y{ws, nullptr, P_F64, R};
     *y_out = y;
     if (prm->mode == OVL_SOLVE_MIXED) {
-        if (!U->f32 || !U->f16 || !U->f64 || !weights) return OVL_ERR_INVALID;
+        // the mixed solver reads FP64 and FP32 links only
+        if (!U->f32 || !U->f64 || !weights) return OVL_ERR_INVALID;
         return mscg_mixed(L, U, m0, nshift, shifts, weights, b, y, prm, stats, ws + yb, ws_bytes - yb, st);
     }
     int rc;

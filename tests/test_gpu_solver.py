@@ -14,6 +14,7 @@ import torch
 
 import oracle
 import synth
+from parity import field_check
 from oracle import dense
 
 pytestmark = pytest.mark.gpu
@@ -38,9 +39,13 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def rel(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+def close(got, ref, dims, tol):
+    """Site-wise check of a solver output against its reference
+    (tests/parity.py field_check); returns the worst site's error over its
+    bound and the relative L2 difference."""
+    ratio, r2 = field_check(got, ref, dims, tol)
+    assert ratio <= 1.0, (ratio, r2)
+    return ratio, r2
 
 
 def both_sides(ovl, dims, U, npoles=20, start_seed=99):
@@ -87,7 +92,7 @@ def test_multishift_cg_matches_oracle(ovl, block):
                            ovl.default_params(tol=1e-12, verify=1, check_every=7, block=block))
     x = X.to_canonical().cpu().numpy()
     for j in range(len(s)):
-        assert rel(x[j], x_ref[j]) < 1e-10, j
+        close(x[j], x_ref[j], dims, 1e-10)
         assert abs(st["shift_iters"][0][j] - it_ref[j]) <= 1
         assert st["true_residual"][0][j] < 1e-11
     assert st["iterations"][0] == max(st["shift_iters"][0])
@@ -108,11 +113,11 @@ def test_sign_q_matches_exact_dense_sign(ovl):
     O = ovl.Spinor(lat, 0)
     ovl.sign_q_apply(lat, G, M0, s, wt, B, O, ovl.default_params(tol=1e-13))
     exact = (S @ b.reshape(-1)).reshape(b.shape)
-    assert rel(O.to_canonical().cpu().numpy()[0], exact) < 1e-12 + 2 * delta
+    close(O.to_canonical().cpu().numpy()[0], exact, dims, 1e-12 + 2 * delta)
     # overlap against the dense overlap matrix
     Dov = RHO * (np.eye(3072) + dense.gamma5_matrix(lat.V) @ S)
     ovl.overlap_apply(lat, G, RHO, s, wt, B, O, ovl.default_params(tol=1e-13))
-    assert rel(O.to_canonical().cpu().numpy()[0], (Dov @ b.reshape(-1)).reshape(b.shape)) < 1e-12
+    close(O.to_canonical().cpu().numpy()[0], (Dov @ b.reshape(-1)).reshape(b.shape), dims, 1e-12)
 
 
 @pytest.mark.parametrize("block", [0, 8])
@@ -122,14 +127,15 @@ def test_overlap_apply_matches_oracle(ovl, dims, block):
     U = synth.gauge(dims, 0.3, 31, n_stout=2)
     lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
     # the smallest Ritz value is not fully converged after 300 steps, so two
-    # implementations with different rounding agree on it only to ~1e-8
+    # implementations with different rounding agree on it only to a few
+    # parts in 1e8 here; the bound leaves a factor of about 100
     assert abs(lo - olo) < 1e-6 * lo and abs(hi - ohi) < 1e-8 * hi
     b = synth.gaussian_spinor(lat.V, 32)[0]
     ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b, 1e-13, 5000)
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0)
     st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000, block=block))
-    assert rel(O.to_canonical().cpu().numpy()[0], ref) < 1e-12
+    close(O.to_canonical().cpu().numpy()[0], ref, dims, 1e-12)
     assert st["iterations"][0] > 10
 
 
@@ -147,24 +153,26 @@ def test_overlap_multi_rhs(ovl, block):
     got = O.to_canonical().cpu().numpy()
     for r in range(3):
         ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b[r], 1e-13, 5000)
-        assert rel(got[r], ref) < 1e-12
+        close(got[r], ref, dims, 1e-12)
 
 
-def test_point_sources_batch(ovl):
-    """12 spin-colour point sources in one batched solve (the multi-RHS workload shape)."""
+@pytest.mark.parametrize("block", [0, 16])
+def test_point_sources_batch(ovl, block):
+    """All 12 spin-colour point sources in one batched solve (the multi-RHS
+    workload shape), each against the oracle at the FP64 path's 1e-12."""
     dims = (8, 4, 4, 4)
-    note("point sources")
+    note(f"point sources block={block}")
     U = synth.gauge(dims, 0.3, 51, n_stout=2)
     lat, olat, G, (s, w, d, lo, hi), (os_, ow, od, olo, ohi) = both_sides(ovl, dims, U)
     site = synth.random_site(lat.V, 52)
     b = synth.point_sources(lat.V, site)
     B = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0, 12)
-    ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-12, maxiter=5000))
+    ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(tol=1e-13, maxiter=5000, block=block))
     got = O.to_canonical().cpu().numpy()
-    for r in (0, 5, 11):
-        ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b[r], 1e-12, 5000)
-        assert rel(got[r], ref) < 1e-10
+    for r in range(12):
+        ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b[r], 1e-13, 5000)
+        close(got[r], ref, dims, 1e-12)
 
 
 def test_ginsparg_wilson_gpu(ovl):
@@ -246,7 +254,7 @@ def test_solvers_with_streaming_stencil(ovl, dims, block, ts, ts64):
     st = ovl.multishift_cg(lat, G, M0, s, None, B, X, ovl.default_params(tol=1e-12, verify=1, block=block))
     x = X.to_canonical().cpu().numpy()
     for j in range(len(s)):
-        assert rel(x[j], x_ref[j]) < 1e-10, j
+        close(x[j], x_ref[j], dims, 1e-10)
         assert abs(st["shift_iters"][0][j] - it_ref[j]) <= 1
     B2 = ovl.Spinor.from_canonical(lat, dev(b), 0)
     O = ovl.Spinor(lat, 0, 2)
@@ -254,11 +262,11 @@ def test_solvers_with_streaming_stencil(ovl, dims, block, ts, ts64):
     got = O.to_canonical().cpu().numpy()
     for r in range(2):
         ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b[r], 1e-13, 5000)
-        assert rel(got[r], ref) < 1e-12
+        close(got[r], ref, dims, 1e-12)
     # mixed form on the streaming stencil: every shift verified at 1e-10
     O3 = ovl.Spinor(lat, 0, 2)
     st3 = ovl.overlap_apply(lat, G, RHO, s, w, B2, O3, ovl.default_params(tol=1e-10, maxiter=5000,
                                                                           mode=ovl.SOLVE_MIXED, block=block))
     for r in range(2):
         assert max(st3["true_residual"][r][:len(s)]) <= 1e-10
-        assert rel(O3.to_canonical().cpu().numpy()[r], got[r]) < 1e-8
+        close(O3.to_canonical().cpu().numpy()[r], got[r], dims, 1e-8)

@@ -234,6 +234,25 @@ OVL_API int ovl_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0,
 OVL_API int ovl_q2_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, double shift,
                  const ovl_spinor *in, ovl_spinor *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Bytes of the scratch array of ovl_q2_apply_noalloc, per GPU. */
+#define OVL_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* ovl_q2_apply without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that forbid hipMalloc).  The intermediate field Q in lives in
+ * a library-owned device array of OVL_NOALLOC_SCRATCH_BYTES on each GPU,
+ * held from the library's load until the process ends.  The call needs
+ * ovl_workspace_bytes(lat, OVL_OP_Q2, in->prec, in->nrhs, 0, NULL) to fit it
+ * (one FP64 field up to 24^3x48 and two there, one FP32 field at 32^3x64)
+ * and returns OVL_ERR_WORKSPACE otherwise, before any device work.  All calls
+ * on one GPU share its array: calls that overlap on one GPU (other streams or
+ * threads) race.  The first call on a device looks up the array's address on
+ * the current device (not a stream operation); every call then only launches
+ * the two stencils on `stream`.  Arguments, layouts and other errors as
+ * ovl_q2_apply. */
+OVL_API int ovl_q2_apply_noalloc(const ovl_lattice *lat, const ovl_gauge *U, double m0, double shift,
+                                 const ovl_spinor *in, ovl_spinor *out, void *stream);
+
 /* ---- sign function and overlap ------------------------------------------ */
 
 /* Zolotarev coefficients (host only): shifts[n], weights[n] with

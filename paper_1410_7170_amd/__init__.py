@@ -96,6 +96,8 @@ _sig = {
     "ovl_q_apply": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, P(ovl_spinor), P(ovl_spinor), c_vp]),
     "ovl_q2_apply": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, c_dbl, P(ovl_spinor), P(ovl_spinor),
                              c_vp, ctypes.c_size_t, c_vp]),
+    "ovl_q2_apply_noalloc": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, c_dbl, P(ovl_spinor), P(ovl_spinor),
+                                     c_vp]),
     "ovl_zolotarev": (c_i32, [c_dbl, c_dbl, c_i32, P(c_dbl), P(c_dbl), P(c_dbl)]),
     "ovl_spectral_bounds": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, c_i32, P(ovl_spinor), c_dbl, c_dbl,
                                     P(c_dbl), P(c_dbl), c_vp, ctypes.c_size_t, c_vp]),
@@ -301,6 +303,15 @@ def q2_apply(lat: Lattice, U: Gauge, m0: float, shift: float, inp: Spinor, out: 
         ws = workspace(lat, OP_Q2, inp.prec, inp.nrhs, device=inp.data.device)
     _check(_lib.ovl_q2_apply(lat.ref, U.ref, float(m0), float(shift), inp.ref, out.ref, c_vp(ws.data_ptr()),
                              ws.numel(), _stream(stream)), "ovl_q2_apply")
+
+
+def q2_apply_noalloc(lat: Lattice, U: Gauge, m0: float, shift: float, inp: Spinor, out: Spinor, stream=None):
+    """(Q^2 + shift) inp with the library's own scratch array (no workspace)."""
+    _check(_lib.ovl_q2_apply_noalloc(lat.ref, U.ref, float(m0), float(shift), inp.ref, out.ref, _stream(stream)),
+           "ovl_q2_apply_noalloc")
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 def zolotarev(lambda_min: float, lambda_max: float, npoles: int):

@@ -104,6 +104,47 @@ void clear_stats(ovl_solver_stats *st)
 
 }  // namespace
 
+namespace ovl {
+
+// (Q^2 + shift) in: Q = Gamma_5 D_W(m0) into the scratch field t (ws), then
+// Q t + shift in into out.  Shared by ovl_q2_apply (caller workspace) and the
+// entry point without allocation (a library-owned scratch array).
+int q2_apply_body(const ovl_lattice *lat, const ovl_gauge *U, double m0, double shift, const ovl_spinor *in,
+                  ovl_spinor *out, char *ws, size_t ws_bytes, hipStream_t st)
+{
+    if (!lat_ok(lat) || !spinor_ok(in) || !spinor_ok(out)) return OVL_ERR_INVALID;
+    if (in->prec != out->prec || in->nrhs != out->nrhs || in->d == out->d) return OVL_ERR_INVALID;
+    if (!std::isfinite(m0) || !std::isfinite(shift)) return OVL_ERR_INVALID;
+    const void *Ud = gauge_for(U, in->prec);
+    if (!Ud || !ws) return OVL_ERR_INVALID;
+    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_Q2, in->prec, in->nrhs, 0, nullptr)) return OVL_ERR_WORKSPACE;
+    Lat L = make_lat(lat);
+    size_t F = field_bytes(in->prec, L.V) * in->nrhs;
+    void *tmp = ws;
+    float *tsc = in->prec == OVL_F16S ? (float *)(ws + ((F + 255) & ~(size_t)255)) : nullptr;
+    WArgs a{};
+    a.in = in->d;
+    a.in_sc = in->scale;
+    a.out = tmp;
+    a.out_sc = tsc;
+    a.U = Ud;
+    a.diag = m0 + 4.0;
+    a.nrhs = in->nrhs;
+    OVL_HIP(launch_wilson(L, in->prec, W_PLAIN, true, a, st));
+    WArgs b = a;
+    b.in = tmp;
+    b.in_sc = tsc;
+    b.p = in->d;
+    b.p_sc = in->scale;
+    b.shift = shift;
+    b.out = out->d;
+    b.out_sc = out->scale;
+    OVL_HIP(launch_wilson(L, in->prec, W_SHIFT, true, b, st));
+    return OVL_OK;
+}
+
+}  // namespace ovl
+
 extern "C" {
 
 int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4])
@@ -218,36 +259,8 @@ int ovl_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl
 int ovl_q2_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, double shift, const ovl_spinor *in,
                  ovl_spinor *out, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!lat_ok(lat) || !spinor_ok(in) || !spinor_ok(out)) return OVL_ERR_INVALID;
-    if (in->prec != out->prec || in->nrhs != out->nrhs || in->d == out->d) return OVL_ERR_INVALID;
-    if (!std::isfinite(m0) || !std::isfinite(shift)) return OVL_ERR_INVALID;
-    const void *Ud = gauge_for(U, in->prec);
-    if (!Ud || !ws) return OVL_ERR_INVALID;
-    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_Q2, in->prec, in->nrhs, 0, nullptr)) return OVL_ERR_WORKSPACE;
-    Lat L = make_lat(lat);
-    char *w = (char *)ws;
-    size_t F = field_bytes(in->prec, L.V) * in->nrhs;
-    void *tmp = w;
-    float *tsc = in->prec == OVL_F16S ? (float *)(w + ((F + 255) & ~(size_t)255)) : nullptr;
-    WArgs a{};
-    a.in = in->d;
-    a.in_sc = in->scale;
-    a.out = tmp;
-    a.out_sc = tsc;
-    a.U = Ud;
-    a.diag = m0 + 4.0;
-    a.nrhs = in->nrhs;
-    OVL_HIP(launch_wilson(L, in->prec, W_PLAIN, true, a, S(stream)));
-    WArgs b = a;
-    b.in = tmp;
-    b.in_sc = tsc;
-    b.p = in->d;
-    b.p_sc = in->scale;
-    b.shift = shift;
-    b.out = out->d;
-    b.out_sc = out->scale;
-    OVL_HIP(launch_wilson(L, in->prec, W_SHIFT, true, b, S(stream)));
-    return OVL_OK;
+    if (!ws) return OVL_ERR_INVALID;
+    return q2_apply_body(lat, U, m0, shift, in, out, (char *)ws, ws_bytes, S(stream));
 }
 
 size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int32_t nrhs, int32_t nshift,

@@ -60,7 +60,7 @@ def parse():
                          "sources); -1 skips it")
     ap.add_argument("--multi-rhs-steps", type=int, default=2)
     ap.add_argument("--stencil-order", default="",
-                    help="tile_t,stream_t,stream_t64 for the main workload instead of autotuning "
+                    help="tile_t,stream_t,stream_t64[,rhs_tile] for the main workload instead of autotuning "
                          "(profiling runs pin the order the timed run chose)")
     return ap.parse_args()
 
@@ -194,8 +194,12 @@ def main():
     B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
     out = ovl.Spinor(lat, ovl.F64, B.nrhs)
     if args.stencil_order:
-        lat.tile_t, lat.stream_t, lat.stream_t64 = (int(v) for v in args.stencil_order.split(","))
-        tune = dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, timings="fixed")
+        vals = [int(v) for v in args.stencil_order.split(",")]
+        lat.tile_t, lat.stream_t, lat.stream_t64 = vals[:3]
+        if len(vals) > 3:
+            lat.rhs_tile = vals[3]
+        tune = dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, rhs_tile=lat.rhs_tile,
+                    timings="fixed")
     else:
         tune = ovl.autotune_stencil(lat, G, B.nrhs)
     log(f"setup {time.time() - t_setup:.1f}s dims={dims} |Q| in [{lo:.4f}, {hi:.4f}] delta={delta:.2e}")
@@ -313,7 +317,7 @@ def main():
         "config": {"workload": f"overlap apply {dims[1]}^3x{dims[0]}, {npoles} Zolotarev poles, "
                                f"tol {args.tol:g}, rho {RHO}",
                    "lattice": list(dims), "nrhs": nrhs, "poles": npoles, "form": timed_form,
-                   "stencil_order": {k: tune[k] for k in ("tile_t", "stream_t", "stream_t64")},
+                   "stencil_order": {k: tune[k] for k in ("tile_t", "stream_t", "stream_t64", "rhs_tile")},
                    "spectral_interval": [lo, hi], "zolotarev_delta": delta},
         "stencil": stencil,
         "forms": {k: dict(applies_per_s=round(nrhs / v["seconds"], 4), iterations=v["iterations"],
@@ -470,7 +474,7 @@ def multi_rhs_line(args, ovl, synth, np, torch):
                 iterations=st["iterations"], max_true_residual=max(max(r) for r in st["true_residual"]),
                 refine_iterations=st["refine_iterations"],
                 rel_diff_rhs0_vs_fp64=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-                stencil_order={k: tune[k] for k in ("tile_t", "stream_t", "stream_t64")},
+                stencil_order={k: tune[k] for k in ("tile_t", "stream_t", "stream_t64", "rhs_tile")},
                 autotune=tune["timings"])
     log(f"multi-rhs {dims}: {rate:.3f} RHS-applies/s, FP64 single {single}, "
         f"max residual {line['max_true_residual']:.2e}")

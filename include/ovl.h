@@ -111,6 +111,13 @@ typedef struct {
     int32_t stream_t64;/* time slices per thread of the FP64 stencil in the
                           streaming form (same conditions as stream_t);
                           0: FP64 follows stream_t.  Set by ovl_lattice_init */
+    int32_t rhs_tile;  /* 1, 2, 4 or 8: the streaming stencil on several RHS
+                          gives each site K consecutive lanes holding K RHS, so
+                          one link load serves K RHS; K is this value capped at
+                          the next power of two of the RHS count, and halved
+                          while a block's sites times the stream length are
+                          fewer than 256.  1 (one RHS per block) is set by
+                          ovl_lattice_init; results do not depend on it */
 } ovl_lattice;
 
 /* A gauge field packed in up to three precisions (device pointers).  An
@@ -316,20 +323,37 @@ OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 /* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on
  * nrhs fields of a fixed pattern in every precision whose links U provides,
- * over the candidate site orders -- lat->tile_t in {1,2,4,8,16} for the one-site form
- * (timed on FP16 links when given, else FP32), lat->stream_t in
- * {0,2,4,8,16,32} on FP32 and lat->stream_t64 likewise on FP64 (lengths that
- * divide dims[0]; streaming only when dims[1]*dims[2]*dims[3] % 256 == 0) --
- * and writes the fastest of each into *lat (a candidate replaces the current
- * value only when more than 5% faster).  Outputs of every operator
- * depend on these fields only through summation order.  ws: device workspace
- * of ovl_workspace_bytes(lat, OVL_OP_TUNE, 0, nrhs, 0, NULL) bytes.
- * tried/times_us (host, optional, max_tried entries): candidate k as
- * 1000*what + value (what 0 tile_t, 1 stream_t, 2 stream_t64) and its average
- * launch time in microseconds.  Returns the number of candidates timed (>= 0)
- * or a negative error.  Synchronises the stream. */
+ * over the candidate site orders -- lat->tile_t in {1,2,4,8,16} for the
+ * one-site form (timed on FP16 links when given, else FP32); then, for each
+ * RHS tile lat->rhs_tile in {1,2,4,8} (only 1 for one RHS; tiles up to the
+ * next power of two of nrhs), lat->stream_t in {0,2,4,8,16,32} on FP32 and
+ * lat->stream_t64 likewise on FP64 (lengths that divide dims[0]; streaming
+ * only when dims[1]*dims[2]*dims[3] % 256 == 0), keeping the tile whose FP32
+ * and FP64 times add up least -- and writes the fastest into *lat (a
+ * candidate replaces the current value only when more than 5% faster).
+ * Outputs of every operator depend on these fields only through summation
+ * order.  ws: device workspace of ovl_workspace_bytes(lat, OVL_OP_TUNE, 0,
+ * nrhs, 0, NULL) bytes.  tried/times_us (host, optional, max_tried entries):
+ * candidate k as 10000*what + 100*tile + value (what 0 tile_t, 1 stream_t,
+ * 2 stream_t64; tile the RHS tile it ran with) and its average launch time in
+ * microseconds.  Returns the number of candidates timed (>= 0) or a negative
+ * error.  Synchronises the stream. */
 OVL_API int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
                                  int32_t *tried, float *times_us, int32_t max_tried, void *stream);
+
+/* ovl_autotune_stencil with a file of earlier choices: cache_path (host
+ * string, may be NULL for none) holds one JSON object per line,
+ *   {"key": "<arch> <L0>x<L1>x<L2>x<L3> bc<b0>,<b1>,<b2>,<b3> nrhs<n> links<f64><f32><f16>",
+ *    "tile_t": t, "stream_t": s, "stream_t64": s64, "rhs_tile": k}
+ * keyed by the current device's architecture name, the lattice, its boundary
+ * phases, nrhs and which link copies U holds.  If a line matches (the last
+ * one wins) and its values are valid for *lat, they are written into *lat
+ * and 0 is returned without timing; otherwise the autotuner runs and its
+ * choice is appended to the file (not locked: concurrent writers may
+ * interleave lines).  Returns as ovl_autotune_stencil. */
+OVL_API int ovl_autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws,
+                                        size_t ws_bytes, const char *cache_path, int32_t *tried, float *times_us,
+                                        int32_t max_tried, void *stream);
 
 OVL_API const char *ovl_status_string(int status);
 OVL_API int ovl_last_hip_error(void);

@@ -41,7 +41,7 @@ c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, cty
 
 class ovl_lattice(ctypes.Structure):
     _fields_ = [("dims", c_i32 * 4), ("bc", c_i32 * 4), ("vol", c_i64), ("tile_t", c_i32), ("stream_t", c_i32),
-                ("stream_t64", c_i32)]
+                ("stream_t64", c_i32), ("rhs_tile", c_i32)]
 
 
 class ovl_gauge(ctypes.Structure):
@@ -112,6 +112,8 @@ _sig = {
     "ovl_default_params": (None, [P(ovl_solver_params)]),
     "ovl_autotune_stencil": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_i32, c_vp, ctypes.c_size_t, P(c_i32),
                                      P(ctypes.c_float), c_i32, c_vp]),
+    "ovl_autotune_stencil_cached": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_i32, c_vp, ctypes.c_size_t,
+                                            ctypes.c_char_p, P(c_i32), P(ctypes.c_float), c_i32, c_vp]),
     "ovl_status_string": (ctypes.c_char_p, [c_i32]),
     "ovl_last_hip_error": (c_i32, []),
     "ovl_version": (ctypes.c_char_p, []),
@@ -191,6 +193,16 @@ class Lattice:
         if s and (s < 0 or s > 256 or self.dims[0] % s or (self.dims[1] * self.dims[2] * self.dims[3]) % 256):
             raise ValueError(f"stream_t64={s} needs s | L0 and L1*L2*L3 % 256 == 0")
         self.c.stream_t64 = int(s)
+
+    @property
+    def rhs_tile(self) -> int:
+        return int(self.c.rhs_tile)
+
+    @rhs_tile.setter
+    def rhs_tile(self, k: int):
+        if k not in (1, 2, 4, 8):
+            raise ValueError("rhs_tile must be 1, 2, 4 or 8")
+        self.c.rhs_tile = int(k)
 
     @property
     def ref(self):
@@ -324,20 +336,29 @@ def zolotarev(lambda_min: float, lambda_max: float, npoles: int):
     return np.array(s[:]), np.array(w[:]), d.value
 
 
-def autotune_stencil(lat: Lattice, U: Gauge, nrhs: int = 1, ws=None, stream=None) -> dict:
-    """Time the stencil's candidate site orders (ovl_autotune_stencil) and keep
-    the fastest in `lat`; returns the choices and every timing (microseconds)."""
+def autotune_stencil(lat: Lattice, U: Gauge, nrhs: int = 1, ws=None, stream=None, cache=None) -> dict:
+    """Time the stencil's candidate site orders and RHS tiles
+    (ovl_autotune_stencil) and keep the fastest in `lat`; with `cache` (a file
+    path) earlier choices for the same device, lattice, RHS count and links are
+    reused (ovl_autotune_stencil_cached).  Returns the choices and every
+    timing (microseconds): (what, rhs tile, value, us)."""
     if ws is None:
         ws = workspace(lat, OP_TUNE, F64, nrhs)
-    n = 64
+    n = 256
     tried = (c_i32 * n)()
     times = (ctypes.c_float * n)()
-    rc = _lib.ovl_autotune_stencil(lat.ref, U.ref, int(nrhs), c_vp(ws.data_ptr()), ws.numel(), tried, times, n,
-                                   _stream(stream))
+    if cache is not None:
+        rc = _lib.ovl_autotune_stencil_cached(lat.ref, U.ref, int(nrhs), c_vp(ws.data_ptr()), ws.numel(),
+                                              os.fsencode(cache), tried, times, n, _stream(stream))
+    else:
+        rc = _lib.ovl_autotune_stencil(lat.ref, U.ref, int(nrhs), c_vp(ws.data_ptr()), ws.numel(), tried, times, n,
+                                       _stream(stream))
     _check(rc, "ovl_autotune_stencil")
     names = ("tile_t", "stream_t", "stream_t64")
-    table = [(names[tried[k] // 1000], tried[k] % 1000, round(float(times[k]), 2)) for k in range(min(rc, n))]
-    return dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, timings=table)
+    table = [(names[tried[k] // 10000], (tried[k] // 100) % 100, tried[k] % 100, round(float(times[k]), 2))
+             for k in range(min(rc, n))]
+    return dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, rhs_tile=lat.rhs_tile,
+                timings=table if rc > 0 or cache is None else "cache")
 
 
 def spectral_bounds(lat: Lattice, U: Gauge, m0: float, iters: int, start: Spinor,

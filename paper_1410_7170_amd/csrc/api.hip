@@ -23,6 +23,8 @@ size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f
 size_t tune_ws_bytes(const Lat &L, int nrhs);
 int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes, hipStream_t st,
                      int32_t *tried, float *times_us, int32_t max_tried);
+int autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes,
+                            hipStream_t st, const char *path, int32_t *tried, float *times_us, int32_t max_tried);
 int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
                Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
                hipStream_t st);
@@ -50,6 +52,7 @@ bool lat_ok(const ovl_lattice *lat)
     if (lat->stream_t64 > 0 && (lat->dims[0] % lat->stream_t64 ||
                                 ((int64_t)lat->dims[1] * lat->dims[2] * lat->dims[3]) % 256))
         return false;
+    if (lat->rhs_tile != 1 && lat->rhs_tile != 2 && lat->rhs_tile != 4 && lat->rhs_tile != 8) return false;
     return V < ((int64_t)1 << 31) && lat->vol == V;
 }
 
@@ -170,6 +173,7 @@ int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4
     // 16; beyond that too few blocks are left to hide memory latency)
     lat->stream_t = 0;
     lat->stream_t64 = 0;
+    lat->rhs_tile = 1;
     const int64_t V3 = (int64_t)dims[1] * dims[2] * dims[3];
     if (V3 % 256 == 0) {
         for (int s : {16, 8, 4, 2})
@@ -308,6 +312,16 @@ int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, voi
     if (!lat_ok(lat) || !U || !ws || nrhs < 1 || nrhs > OVL_MAX_RHS || max_tried < 0) return OVL_ERR_INVALID;
     if (!U->f64 && !U->f32 && !U->f16) return OVL_ERR_INVALID;
     return autotune_stencil(lat, U, nrhs, (char *)ws, ws_bytes, (hipStream_t)stream, tried, times_us, max_tried);
+}
+
+int ovl_autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
+                                const char *cache_path, int32_t *tried, float *times_us, int32_t max_tried,
+                                void *stream)
+{
+    if (!lat_ok(lat) || !U || !ws || nrhs < 1 || nrhs > OVL_MAX_RHS || max_tried < 0) return OVL_ERR_INVALID;
+    if (!U->f64 && !U->f32 && !U->f16) return OVL_ERR_INVALID;
+    return autotune_stencil_cached(lat, U, nrhs, (char *)ws, ws_bytes, (hipStream_t)stream, cache_path, tried,
+                                   times_us, max_tried);
 }
 
 int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, double m0, int32_t iters,

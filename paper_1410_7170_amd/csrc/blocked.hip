@@ -456,7 +456,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
 {
     const int R = b.nrhs;
     const int nblk = site_blocks(L);
-    const int npart = stencil_partials(L, PS);   // slots the iteration stencils fill
+    const int npart = stencil_partials(L, PS, R);   // slots the iteration stencils fill
     const int m = o.m;
     if (m < 1 || m > MB || R > NR) return OVL_ERR_INVALID;
     if (o.reliable && !o.keep_x) return OVL_ERR_INVALID;

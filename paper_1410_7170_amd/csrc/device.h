@@ -84,6 +84,7 @@ struct Geom {
     int T;         // time-tile length of the stencil's site order (divides L0)
     int Ts;        // time slices per thread of the time-streaming stencil (0: not used)
     int Ts64;      // time slices per thread of the FP64 streaming stencil (0: Ts)
+    int Kr;        // log2 of the RHS tile of the streaming stencil (lanes per site)
 };
 
 // Threads (sites) per block of the time-streaming stencil with ts slices per
@@ -455,6 +456,30 @@ __device__ __forceinline__ double block_sum_w(double v, double *lds /* >= 4 */)
         __syncthreads();
         return t;
     }
+}
+
+// Sums over the lanes of a block of NW waves whose RHS is the lane index
+// modulo K = 2^kr (K <= 8): the sum for RHS q is valid in thread q < K.  The
+// shuffles skip the offsets below K, then thread q adds the NW wave sums in
+// the fixed order of block_sum_w, so K = 1 gives block_sum_w's bits.
+template <int NW>
+__device__ __forceinline__ double block_sum_k(double v, double *lds /* >= NW * 8 */, int kr)
+{
+    const int K = 1 << kr;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        if (off >= K) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    if (ln < K) lds[w * K + ln] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < K) {
+        const int q = threadIdx.x;
+        if constexpr (NW == 4) t = (lds[q] + lds[K + q]) + (lds[2 * K + q] + lds[3 * K + q]);
+        else t = (lds[q] + lds[K + q]) + lds[2 * K + q];
+    }
+    __syncthreads();
+    return t;
 }
 
 // The same sum, valid in every thread (each adds the four wave sums in the

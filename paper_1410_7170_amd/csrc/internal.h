@@ -79,9 +79,18 @@ hipError_t launch_zero(const Lat &L, Fld f, hipStream_t st);
 
 int elems_per_field(int prec, int Vh);   // flat vector elements of one RHS
 int site_blocks(const Lat &L);           // blocks of a flat elementwise launch over one field
-// Leading per-RHS partial-sum slots a stencil launch of this precision fills;
-// it zeroes the rest of the site_blocks(L) slots, so a consumer may sum only
-// these (the same sum bit for bit).
-int stencil_partials(const Lat &L, int prec);
+// Launch shape of a stencil of precision prec on nrhs fields.  ts > 0: the
+// time-streaming form with ts slices per thread, blocks of nt threads, K = 2^kr
+// lanes per site (RHS tile) and nt >> kr sites per block; ts = 0: one thread
+// per site and RHS.  blocks_per_tile: blocks of one RHS tile (each fills one
+// partial-sum slot per RHS of the tile).
+struct StencilShape {
+    int ts, nt, kr, blocks_per_tile, ntile;
+};
+StencilShape stencil_shape(const Lat &L, int prec, int nrhs);
+// Leading per-RHS partial-sum slots a stencil launch of this precision on
+// nrhs fields fills; it zeroes the rest of the site_blocks(L) slots, so a
+// consumer may sum only these (the same sum bit for bit).
+int stencil_partials(const Lat &L, int prec, int nrhs);
 
 }  // namespace ovl

@@ -22,6 +22,7 @@ Lat make_lat(const ovl_lattice *lat)
     L.g.T = lat->tile_t;
     L.g.Ts = lat->stream_t;
     L.g.Ts64 = lat->stream_t64;
+    L.g.Kr = lat->rhs_tile >= 8 ? 3 : lat->rhs_tile >= 4 ? 2 : lat->rhs_tile >= 2 ? 1 : 0;
     L.nb = (L.Vh + kBlock - 1) / kBlock;
     return L;
 }
@@ -37,13 +38,12 @@ int last_hip_error() { return g_last_hip; }
 int site_blocks(const Lat &L) { return 2 * L.nb; }
 
 // The time-streaming stencil (FP64, FP32 with a stream length) runs
-// V / (NT Ts) blocks per RHS, one partial slot each; the one-site form fills
-// all 2 nb slots.
-int stencil_partials(const Lat &L, int prec)
+// blocks_per_tile blocks per RHS tile, one partial slot each; the one-site
+// form fills all 2 nb slots.
+int stencil_partials(const Lat &L, int prec, int nrhs)
 {
-    const int ts = prec == P_F64 && L.g.Ts64 > 0 ? L.g.Ts64 : L.g.Ts;
-    if (ts > 0 && prec != P_F16S) return (int)(L.V / ((int64_t)stream_threads(L.g, ts) * ts));
-    return 2 * L.nb;
+    const StencilShape sh = stencil_shape(L, prec, nrhs);
+    return sh.ts > 0 ? sh.blocks_per_tile : 2 * L.nb;
 }
 
 // ---------------------------------------------------------------- pack

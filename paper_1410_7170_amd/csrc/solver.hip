@@ -282,7 +282,7 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
 {
     const int R = b.nrhs;
     const int nblk = site_blocks(L);
-    const int npart = stencil_partials(L, P_F64);   // slots the iteration stencils fill
+    const int npart = stencil_partials(L, P_F64, R);   // slots the iteration stencils fill
     WsCarve c{ws, 0, ws_bytes};
     size_t F = field_bytes(P_F64, L.V);
     MState *S = (MState *)c.take(sizeof(MState));

@@ -6,15 +6,20 @@
 //     dividing L0;
 //   FP32: stream_t = 0 (one site per thread) or a divisor of L0 in
 //     {2, 4, 8, 16, 32} when L1*L2*L3 % 256 == 0;
-//   FP64: stream_t64 = 0 (follow stream_t) or such a divisor.
+//   FP64: stream_t64 = 0 (follow stream_t) or such a divisor;
+//   several RHS: the RHS tile rhs_tile in {1, 2, 4, 8} (K lanes per site
+//     share each link load), jointly with the two stream lengths.
 // tile_t is tuned first (on the FP16 stencil when those links are given,
-// else on FP32), then stream_t on FP32, then stream_t64 on FP64.  A candidate
-// replaces the lattice's current value only when it is more than 5% faster,
-// so near-ties (within run-to-run noise) keep the defaults and repeated
-// tuning gives the same choices.
+// else on FP32); then, for each RHS tile, stream_t on FP32 and stream_t64 on
+// FP64, and the tile with the least sum of the two best times wins.  A
+// candidate replaces the lattice's current value only when it is more than
+// 5% faster, so near-ties (within run-to-run noise) keep the defaults and
+// repeated tuning gives the same choices.
 // Input fields hold a fixed hashed pattern in [-1/2, 1/2), like the data of
 // a solve (all-zero fields measured faster than real data).
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "internal.h"
@@ -114,9 +119,9 @@ int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, s
     }
     const int reps = 5;
     int n = 0, rc = OVL_OK;
-    auto record = [&](int what, int value, float us) {
+    auto record = [&](int what, int k, int value, float us) {
         if (tried && times_us && n < max_tried) {
-            tried[n] = what * 1000 + value;
+            tried[n] = what * 10000 + k * 100 + value;
             times_us[n] = us;
         }
         n++;
@@ -139,7 +144,7 @@ int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, s
                 float us;
                 rc = time_stencil(make_lat(lat), Up[prec], prec, fl[prec], reps, e0, e1, st, &us);
                 if (rc) break;
-                record(0, t, us);
+                record(0, 1, t, us);
                 if (t == cur) tcur = us;
                 if (us < tb) { tb = us; best = t; }
             }
@@ -148,28 +153,129 @@ int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, s
             lat->stream_t64 = s64;
         }
     }
-    // 2. stream_t on FP32, 3. stream_t64 on FP64
-    for (int prec : {P_F32, P_F64}) {
-        if (rc || !Up[prec]) continue;
-        int *field = prec == P_F32 ? &lat->stream_t : &lat->stream_t64;
-        const int cur = *field;
-        int best = cur;
-        float tb = INFINITY, tcur = INFINITY;
-        for (int s : {0, 2, 4, 8, 16, 32}) {
-            if (s && (!can_stream || L0 % s)) continue;
-            *field = s;
-            float us;
-            rc = time_stencil(make_lat(lat), Up[prec], prec, fl[prec], reps, e0, e1, st, &us);
-            if (rc) break;
-            record(prec == P_F32 ? 1 : 2, s, us);
-            if (s == cur) tcur = us;
-            if (us < tb) { tb = us; best = s; }
+    // 2. for each RHS tile K (several RHS only): stream_t on FP32 and
+    // stream_t64 on FP64; the tile whose two best times add up least wins
+    const int cur_k = lat->rhs_tile, cur_s = lat->stream_t, cur_s64 = lat->stream_t64;
+    float score_cur = INFINITY, score_best = INFINITY;
+    int best_k = cur_k, best_s = cur_s, best_s64 = cur_s64;
+    for (int k : {1, 2, 4, 8}) {
+        if (rc) break;
+        if (k > 1 && (nrhs < 2 || k / 2 >= nrhs || !can_stream)) continue;
+        lat->rhs_tile = k;
+        float score = 0.f;
+        int bs[2] = {cur_s, cur_s64};
+        float at_cur[2] = {INFINITY, INFINITY};
+        for (int prec : {P_F32, P_F64}) {
+            if (rc || !Up[prec]) continue;
+            int *field = prec == P_F32 ? &lat->stream_t : &lat->stream_t64;
+            const int cur = prec == P_F32 ? cur_s : cur_s64;
+            float tb = INFINITY, tcur = INFINITY;
+            int best = cur;
+            for (int s : {0, 2, 4, 8, 16, 32}) {
+                if (s && (!can_stream || L0 % s)) continue;
+                if (k > 1 && !s) continue;   // tiles exist in the streaming form only
+                *field = s;
+                float us;
+                rc = time_stencil(make_lat(lat), Up[prec], prec, fl[prec], reps, e0, e1, st, &us);
+                if (rc) break;
+                record(prec == P_F32 ? 1 : 2, k, s, us);
+                if (s == cur) tcur = us;
+                if (us < tb) { tb = us; best = s; }
+            }
+            // within a tile, a stream length replaces the current one only
+            // when more than 5% faster; the FP64 search then runs with the
+            // tile's FP32 choice (stream_t64 = 0 follows it)
+            const bool keep = tcur < INFINITY && !(tb < 0.95f * tcur);
+            bs[prec == P_F32 ? 0 : 1] = keep ? cur : best;
+            *field = prec == P_F32 ? bs[0] : cur;
+            score += keep ? tcur : tb;
+            at_cur[prec == P_F32 ? 0 : 1] = tcur;
         }
-        *field = tb < 0.95f * tcur ? best : cur;
+        if (k == cur_k) score_cur = (Up[P_F32] ? at_cur[0] : 0.f) + (Up[P_F64] ? at_cur[1] : 0.f);
+        if (score < score_best) {
+            score_best = score;
+            best_k = k;
+            best_s = bs[0];
+            best_s64 = bs[1];
+        }
+    }
+    lat->rhs_tile = cur_k;
+    lat->stream_t = cur_s;
+    lat->stream_t64 = cur_s64;
+    if (!rc && score_best < INFINITY) {
+        // another tile replaces the current one only when more than 5% faster
+        if (best_k == cur_k || score_best < 0.95f * score_cur) {
+            lat->rhs_tile = best_k;
+            if (Up[P_F32]) lat->stream_t = best_s;
+            if (Up[P_F64]) lat->stream_t64 = best_s64;
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return rc ? rc : n;
+}
+
+// ---- persistent choices: one JSON object per line, keyed by the device
+// architecture, the lattice, its boundary phases, the RHS count and the link
+// copies present
+static void cache_key(const ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *key, size_t n)
+{
+    char arch[64] = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    }
+    std::snprintf(key, n, "%s %dx%dx%dx%d bc%d,%d,%d,%d nrhs%d links%d%d%d", arch, lat->dims[0], lat->dims[1],
+                  lat->dims[2], lat->dims[3], lat->bc[0], lat->bc[1], lat->bc[2], lat->bc[3], nrhs, U->f64 ? 1 : 0,
+                  U->f32 ? 1 : 0, U->f16 ? 1 : 0);
+}
+
+int autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes,
+                            hipStream_t st, const char *path, int32_t *tried, float *times_us, int32_t max_tried)
+{
+    char key[256];
+    cache_key(lat, U, nrhs, key, sizeof key);
+    if (path) {
+        if (FILE *f = std::fopen(path, "r")) {
+            char line[512], k2[256];
+            int t = 0, s = 0, s64 = 0, rt = 0;
+            bool hit = false;
+            while (std::fgets(line, sizeof line, f)) {
+                if (std::sscanf(line,
+                                "{\"key\": \"%255[^\"]\", \"tile_t\": %d, \"stream_t\": %d, \"stream_t64\": %d, "
+                                "\"rhs_tile\": %d}",
+                                k2, &t, &s, &s64, &rt) == 5 &&
+                    std::strcmp(k2, key) == 0) {
+                    hit = true;   // the last matching line wins
+                }
+            }
+            std::fclose(f);
+            if (hit) {
+                ovl_lattice c = *lat;
+                c.tile_t = t;
+                c.stream_t = s;
+                c.stream_t64 = s64;
+                c.rhs_tile = rt;
+                // a stale or foreign entry that the lattice would reject is ignored
+                const bool ok = t >= 1 && lat->dims[0] % t == 0 && (s == 0 || lat->dims[0] % s == 0) &&
+                                (s64 == 0 || lat->dims[0] % s64 == 0) && (rt == 1 || rt == 2 || rt == 4 || rt == 8);
+                if (ok) {
+                    *lat = c;
+                    return 0;
+                }
+            }
+        }
+    }
+    const int n = autotune_stencil(lat, U, nrhs, ws, ws_bytes, st, tried, times_us, max_tried);
+    if (n >= 0 && path) {
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "{\"key\": \"%s\", \"tile_t\": %d, \"stream_t\": %d, \"stream_t64\": %d, \"rhs_tile\": %d}\n",
+                         key, lat->tile_t, lat->stream_t, lat->stream_t64, lat->rhs_tile);
+            std::fclose(f);
+        }
+    }
+    return n;
 }
 
 }  // namespace ovl

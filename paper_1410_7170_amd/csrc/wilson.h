@@ -42,6 +42,8 @@ struct WArgs {
     const int *skip;        // per-RHS flag: block exits if skip[r] != 0 (may be null)
     int nblk;               // partial-sum slots per RHS and quantity (2 * blocks per parity)
     int nrhs;
+    int kr;                 // streaming form: K = 2^kr consecutive lanes hold K RHS of one
+                            // site (set by launch_wilson)
 };
 
 template <int PREC>
@@ -127,9 +129,12 @@ __device__ __forceinline__ void hop(cplx<T> acc[4][3], const cplx<T> s[4][3], co
     }
 }
 
+// lo: element offset of the thread's RHS field from in's field (RHS tiles of
+// the streaming form, else 0); links are shared by every RHS.
 template <int PREC, int MU>
 __device__ __forceinline__ void hops_mu(const Geom &g, const SpinorRef<PREC> &in, const GaugeRef<PREC> &U,
-                                        int p, int i, const int x[4], cplx<typename Real<PREC>::T> acc[4][3])
+                                        int p, int i, const int x[4], cplx<typename Real<PREC>::T> acc[4][3],
+                                        int lo = 0)
 {
     using T = typename Real<PREC>::T;
     cplx<T> s[4][3], u[3][3];
@@ -139,7 +144,7 @@ __device__ __forceinline__ void hops_mu(const Geom &g, const SpinorRef<PREC> &in
     y[MU] = x[MU] + 1;
     if (y[MU] == g.L[MU]) { y[MU] = 0; ph = (T)g.bc[MU]; }
     int j = cb_index(g, y);
-    in.load(1 - p, j, s);
+    in.load(1 - p, j + lo, s);
     U.load(p, MU, i, u);
     hop<T, MU, true>(acc, s, u, ph);
     // backward neighbour x-mu, link U_mu(x-mu) stored at (1-p, j)
@@ -147,7 +152,7 @@ __device__ __forceinline__ void hops_mu(const Geom &g, const SpinorRef<PREC> &in
     y[MU] = x[MU] - 1;
     if (y[MU] < 0) { y[MU] = g.L[MU] - 1; ph = (T)g.bc[MU]; }
     j = cb_index(g, y);
-    in.load(1 - p, j, s);
+    in.load(1 - p, j + lo, s);
     U.load(1 - p, MU, j, u);
     hop<T, MU, false>(acc, s, u, ph);
 }
@@ -233,31 +238,34 @@ __device__ __forceinline__ void load_either(const LdsPsi<PREC, NT> &lp, const Sp
 // Hops in direction MU = 2 or 3 of the LDS-staged streaming form: a
 // neighbour inside the block (every x3 neighbour; x2 neighbours except from
 // the block's first and last rows) comes from the slice's LDS copy, others
-// from memory.  l: the thread's local site index; rows of L3 sites.
+// from memory.  l: the thread's LDS slot, sl = l >> kr its local site (the K
+// lanes of a site hold K RHS, so a site's slot is l with the site index
+// shifted by kr); rows of L3 sites.
 template <int PREC, int MU, int NT>
 __device__ __forceinline__ void hops_mu_lds(const Geom &g, const SpinorRef<PREC> &in, const GaugeRef<PREC> &U,
-                                            const LdsPsi<PREC, NT> &lp, int p, int i, const int x[4], int l,
-                                            cplx<typename Real<PREC>::T> acc[4][3])
+                                            const LdsPsi<PREC, NT> &lp, int p, int i, const int x[4], int l, int kr,
+                                            int lo, cplx<typename Real<PREC>::T> acc[4][3])
 {
     using T = typename Real<PREC>::T;
     const int L3 = g.L[3];
-    const int row = l / L3, rows = NT / L3;
+    const int row = (l >> kr) / L3, rows = (NT >> kr) / L3;
+    const int drow = L3 << kr;   // slot distance of one x2 row
     cplx<T> s[4][3], u[3][3];
     int y[4] = {x[0], x[1], x[2], x[3]};
     T ph = (T)1;
     y[MU] = x[MU] + 1;
     if (y[MU] == g.L[MU]) { y[MU] = 0; ph = (T)g.bc[MU]; }
     int j = cb_index(g, y);
-    if (MU == 3) lp.load(l - x[3] + y[3], s);
-    else load_either(lp, in, row + 1 < rows, l + L3, 1 - p, j, g.S, s);
+    if (MU == 3) lp.load(l + ((y[3] - x[3]) << kr), s);
+    else load_either(lp, in, row + 1 < rows, l + drow, 1 - p, j + lo, g.S, s);
     U.load(p, MU, i, u);
     hop<T, MU, true>(acc, s, u, ph);
     ph = (T)1;
     y[MU] = x[MU] - 1;
     if (y[MU] < 0) { y[MU] = g.L[MU] - 1; ph = (T)g.bc[MU]; }
     j = cb_index(g, y);
-    if (MU == 3) lp.load(l - x[3] + y[3], s);
-    else load_either(lp, in, row > 0, l - L3, 1 - p, j, g.S, s);
+    if (MU == 3) lp.load(l + ((y[3] - x[3]) << kr), s);
+    else load_either(lp, in, row > 0, l - drow, 1 - p, j + lo, g.S, s);
     U.load(1 - p, MU, j, u);
     hop<T, MU, false>(acc, s, u, ph);
 }
@@ -266,14 +274,23 @@ __device__ __forceinline__ void hops_mu_lds(const Geom &g, const SpinorRef<PREC>
 // site before Gamma_5) and |d|^2 of its centre d: applies Gamma_5, then the
 // mode's shift term, residual update or residual norm; stores the result and
 // adds the site's norms to q0, q1.
+// r: the RHS; its fields are field rb of a.p, a.rin, a.out at element offset
+// lo (RHS tiles: rb the tile's first RHS, lo the lane's offset; else rb = r,
+// lo = 0).  A lane with live false (an idle or finished RHS of a tile)
+// computes like the others, adds no norms and stores into the padding
+// element Vh of its component arrays, which no kernel reads (every array has
+// at least 24 padding elements): a select of the address, not a branch, since
+// a branch around the stores makes the compiler keep far more values live
+// and spill.
 template <int PREC, int MODE, bool G5>
-__device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, double shift_r, double rin_s,
-                                         cplx<typename Real<PREC>::T> o[4][3], typename Real<PREC>::T dn2,
-                                         double &q0, double &q1)
+__device__ __forceinline__ void site_out(const WArgs &a, int r, int rb, int lo, int p, int i, double shift_r,
+                                         double rin_s, cplx<typename Real<PREC>::T> o[4][3],
+                                         typename Real<PREC>::T dn2, double &q0, double &q1, bool live = true)
 {
     using T = typename Real<PREC>::T;
     constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
     const Geom &g = a.g;
+    const int ist = live ? i : g.Vh;   // store index
     if (G5) {
 #pragma unroll
         for (int s = 0; s < 2; s++)
@@ -286,13 +303,13 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
         for (int s = 0; s < 4; s++)
 #pragma unroll
             for (int c = 0; c < 3; c++) n0 += norm2(o[s][c]);
-        q0 += (double)n0;
-        q1 += (double)dn2;
+        q0 += live ? (double)n0 : 0.0;
+        q1 += live ? (double)dn2 : 0.0;
     }
     if (kShift) {
-        const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, r);
+        const SpinorRef<PREC> pf = spinor_ref<PREC>(a.p, a.p_sc, g.S, rb);
         cplx<T> pv[4][3];
-        pf.load_nt(p, i, pv);
+        pf.load_nt(p, i + lo, pv);
         const T sh = (T)shift_r;
 #pragma unroll
         for (int s = 0; s < 4; s++)
@@ -301,7 +318,7 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
     }
     if (MODE == W_RUPDATE) {
         cplx<T> rv[4][3];
-        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, r).load_nt(p, i, rv);
+        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, rb).load_nt(p, i + lo, rv);
         const T al = (T)a.alpha[r];
         T n0 = 0;
 #pragma unroll
@@ -311,20 +328,26 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int p, int i, do
                 rv[s][c] = {fma(-al, o[s][c].x, rv[s][c].x), fma(-al, o[s][c].y, rv[s][c].y)};
                 n0 += norm2(rv[s][c]);
             }
-        spinor_ref<PREC>(a.out, a.out_sc, g.S, r).store_nt(p, i, rv);
-        q0 += (double)n0;
+        spinor_ref<PREC>(a.out, a.out_sc, g.S, rb).store_nt(p, ist + lo, rv);
+        q0 += live ? (double)n0 : 0.0;
     } else if (MODE == W_RESNORM) {
         cplx<T> rv[4][3];
-        spinor_ref<PREC>(a.rin, a.rin_sc, g.S, (a.rin_first + r) % a.rin_count).load_nt(p, i, rv);
+        const int f = (a.rin_first + r) % a.rin_count;
+        if (lo == 0) {
+            spinor_ref<PREC>(a.rin, a.rin_sc, g.S, f).load_nt(p, i, rv);
+        } else {
+            // field f at an element offset from field 0 (RHS tiles)
+            spinor_ref<PREC>(a.rin, a.rin_sc, g.S, 0).load_nt(p, i + f * (int)spinor_elems(PREC, g.S), rv);
+        }
         const T rs = (T)rin_s;
         T n0 = 0;
 #pragma unroll
         for (int s = 0; s < 4; s++)
 #pragma unroll
             for (int c = 0; c < 3; c++) n0 += norm2(rs * rv[s][c] - o[s][c]);
-        q0 += (double)n0;
+        q0 += live ? (double)n0 : 0.0;
     } else {
-        spinor_ref<PREC>(a.out, a.out_sc, g.S, r).store_nt(p, i, o);
+        spinor_ref<PREC>(a.out, a.out_sc, g.S, rb).store_nt(p, ist + lo, o);
     }
 }
 
@@ -386,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         cplx<T> d[4][3];
         in.load(p, i, d);
         const T dn2 = diag_minus_half(acc, d, (T)a.diag);
-        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, rin_s, acc, dn2, q0, q1);
+        site_out<PREC, MODE, G5>(a, r, r, 0, p, i, shift_r, rin_s, acc, dn2, q0, q1);
     }
     if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
         double t0 = block_sum(q0, lds);
@@ -428,35 +451,54 @@ __device__ __forceinline__ void tback_add(cplx<T> acc[4][3], const cplx<T> w[2][
 }
 
 // Time-streaming form of the stencil.  A thread owns one spatial site
-// (x1, x2, x3) and walks Ts consecutive time slices (g.Ts64 for FP64 when
-// set, else g.Ts); block lb covers the
-// NT consecutive spatial sites of spatial block lb % nsb (x3 fastest, so a
-// wave reads whole x3 rows of both parities) in time chunk lb / nsb.  The
-// time hops need no neighbour loads after the first slice: psi(t+1), loaded
-// for the forward hop, is the centre of the next slice, and the backward
-// hop's U_0(t)^H (1 + gamma_0) psi(t) is formed while slice t holds U_0(t)
-// and psi(t) in registers.  Requires L1*L2*L3 % NT == 0 and Ts | L0.
+// (x1, x2, x3) of one RHS and walks Ts consecutive time slices (g.Ts64 for
+// FP64 when set, else g.Ts).  K = 2^a.kr consecutive lanes hold the K RHS of
+// a tile of one site, so every link load serves K RHS within one wave
+// instruction (and a wave reads K runs of consecutive sites, one per RHS
+// field).  Block lb covers the NS = NT/K consecutive spatial sites of spatial
+// block lb % nsb (x3 fastest, so a wave reads whole x3 rows of both
+// parities) in time chunk lb / nsb, for RHS tile rt.  The time hops need no
+// neighbour loads after the first slice: psi(t+1), loaded for the forward
+// hop, is the centre of the next slice, and the backward hop's
+// U_0(t)^H (1 + gamma_0) psi(t) is formed while slice t holds U_0(t) and
+// psi(t) in registers.  Requires L1*L2*L3 % NS == 0 and Ts | L0.
 // WPE is the minimum number of waves per SIMD the build allows for (1 or 2);
 // the one-wave build overlaps pairs of time slices.  STAGE (blocks of whole
-// x3 rows of consecutive x2 at one x1: NT % L3 == 0 and L2*L3 % NT == 0)
+// x3 rows of consecutive x2 at one x1: NS % L3 == 0 and L2*L3 % NS == 0)
 // keeps each slice's centres in LDS, where the next slice reads its x3 and
 // in-block x2 neighbours.  NT = 256, or 192 for x3 extents such as 24 and 48
 // whose rows do not tile 256 sites (stream_threads).
-// Partial sums: slot lb holds the block's sum and the block zeroes the slots
-// lb + m*nblk_ts (m >= 1) below a.nblk, so all 2*nb slots per RHS are valid.
-template <int PREC, int MODE, bool G5, int WPE, bool STAGE, int NT = kBlock>
+// Lanes of an RHS beyond nrhs (last tile) or of a finished RHS (skip) take
+// part in the walk and the barriers but store nothing and add no norms.
+// Partial sums: for each RHS q of the tile, slot lb holds the block's sum and
+// the block zeroes the slots lb + m*nbt (m >= 1) below a.nblk, so all 2*nb
+// slots per RHS are valid.
+// TILED builds take the RHS tile from a.kr; the others have K = 1 at compile
+// time, so the RHS index and everything derived from it stay block-uniform
+// (scalar registers).
+template <int PREC, int MODE, bool G5, int WPE, bool STAGE, int NT = kBlock, bool TILED = false>
 __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
 {
     using T = typename Real<PREC>::T;
-    __shared__ double lds[8];
+    __shared__ double lds[2 * (NT / 64) * 8];
     __shared__ typename LdsPsi<PREC, NT>::E lds_psi[STAGE ? LdsPsi<PREC, NT>::NC : 1][NT];
     const LdsPsi<PREC, NT> lp{lds_psi};
     const Geom &g = a.g;
+    const int kr = TILED ? a.kr : 0;
+    const int K = 1 << kr;
+    const int ntile = (a.nrhs + K - 1) >> kr;
     const int lbr = xcd_remap(blockIdx.x, gridDim.x);
-    const int r = lbr % a.nrhs;
-    const int lb = lbr / a.nrhs;
-    const int nbt = gridDim.x / a.nrhs;   // blocks per RHS
-    if (a.skip && a.skip[r]) return;
+    const int rt = lbr % ntile;
+    const int lb = lbr / ntile;
+    const int nbt = gridDim.x / ntile;   // blocks per RHS tile
+    const int rq = rt * K + (threadIdx.x & (K - 1));
+    const int r = rq < a.nrhs ? rq : a.nrhs - 1;   // idle lanes walk the tile's last RHS
+    const bool live = rq < a.nrhs && !(a.skip && a.skip[rq]);
+    if (!TILED) {
+        if (!live) return;
+    } else if (!__syncthreads_or(live)) {
+        return;   // every RHS of the tile is finished (block-uniform)
+    }
     constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
     const double shift_r = kShift ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
     // the residual norm's scale of rin, likewise read once up front (a load
@@ -464,27 +506,32 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
     // more values live across the hops and spill)
     const double rin_s = MODE == W_RESNORM && a.rin_scale ? a.rin_scale[r] : 1.0;
     const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
-    const int nsb = L1 * L2 * L3 / NT;
+    const int NS = NT >> kr;
+    const int nsb = L1 * L2 * L3 / NS;
     const int sb = lb % nsb, tc = lb / nsb;
-    const int sidx = sb * NT + threadIdx.x;
+    const int sidx = sb * NS + (threadIdx.x >> kr);
     int x[4];
     x[3] = sidx % L3;
     x[2] = (sidx / L3) % L2;
     x[1] = sidx / (L3 * L2);
     const int Ts = PREC == P_F64 && g.Ts64 > 0 ? g.Ts64 : g.Ts;
     const int t0 = tc * Ts;
-    const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.S, r);
+    // tiles: field pointers at the tile's first RHS (uniform), the lane's RHS
+    // as an element offset of the site index (32-bit, in vector registers)
+    const int rb = TILED ? rt * K : r;
+    const int lo = TILED ? (r - rb) * (int)spinor_elems(PREC, g.S) : 0;
+    const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.S, rb);
     const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.S};
     const int sp = x[1] + x[2] + x[3];   // parity of the spatial part
     cplx<T> cen[4][3], w[2][3];   // centre of the current slice, backward-hop carry
     {
         // centre of the first slice and the backward-hop carry from t0 - 1
         x[0] = t0;
-        in.load((t0 + sp) & 1, cb_index(g, x), cen);
+        in.load((t0 + sp) & 1, cb_index(g, x) + lo, cen);
         int y[4] = {t0 == 0 ? L0 - 1 : t0 - 1, x[1], x[2], x[3]};
         const int py = (y[0] + sp) & 1, iy = cb_index(g, y);
         cplx<T> sv[4][3], u[3][3];
-        in.load(py, iy, sv);
+        in.load(py, iy + lo, sv);
         U.load_nt(py, 0, iy, u);
         tback_half(w, sv, u);
     }
@@ -505,24 +552,24 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
 #pragma unroll
             for (int c = 0; c < 3; c++) acc[s][c] = {(T)0, (T)0};
         tback_add(acc, w, t == 0 ? (T)g.bc[0] : (T)1);
-        hops_mu<PREC, 1>(g, in, U, p, i, x, acc);
+        hops_mu<PREC, 1>(g, in, U, p, i, x, acc, lo);
         if (STAGE) {
-            hops_mu_lds<PREC, 2>(g, in, U, lp, p, i, x, threadIdx.x, acc);
-            hops_mu_lds<PREC, 3>(g, in, U, lp, p, i, x, threadIdx.x, acc);
+            hops_mu_lds<PREC, 2>(g, in, U, lp, p, i, x, threadIdx.x, kr, lo, acc);
+            hops_mu_lds<PREC, 3>(g, in, U, lp, p, i, x, threadIdx.x, kr, lo, acc);
         } else {
-            hops_mu<PREC, 2>(g, in, U, p, i, x, acc);
-            hops_mu<PREC, 3>(g, in, U, p, i, x, acc);
+            hops_mu<PREC, 2>(g, in, U, p, i, x, acc, lo);
+            hops_mu<PREC, 3>(g, in, U, p, i, x, acc, lo);
         }
         // U_0(t): the next slice's carry from this centre, then the centre's
         // diagonal term; the centre is then dead before psi(t+1) arrives
         cplx<T> u[3][3];
-        U.load_nt(p, 0, i, u);   // U_0(t) is read by this thread only
+        U.load_nt(p, 0, i, u);   // U_0(t) is read by the K lanes of this site only
         tback_half(w, cen, u);
         const T dn2 = diag_minus_half(acc, cen, (T)a.diag);
         {
             // forward time hop, subtracted with its factor -1/2 straight into v
             int y[4] = {t + 1 == L0 ? 0 : t + 1, x[1], x[2], x[3]};
-            in.load(1 - p, cb_index(g, y), cen);
+            in.load(1 - p, cb_index(g, y) + lo, cen);
             cplx<T> f[4][3];
 #pragma unroll
             for (int s = 0; s < 4; s++)
@@ -534,7 +581,7 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; c++) acc[s][c] = acc[s][c] + f[s][c];
         }
-        site_out<PREC, MODE, G5>(a, r, p, i, shift_r, rin_s, acc, dn2, q0, q1);
+        site_out<PREC, MODE, G5>(a, r, rb, lo, p, i, shift_r, rin_s, acc, dn2, q0, q1, !TILED || live);
         if (STAGE) {
             // every thread has read this slice's copy: replace it by the next slice
             __syncthreads();
@@ -544,12 +591,24 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
     }
     if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
         const int nq = MODE == W_NORM ? 2 : 1;
-        double t0s = block_sum_w<NT / 64>(q0, lds);
-        double t1s = MODE == W_NORM ? block_sum_w<NT / 64>(q1, lds + 4) : 0.0;
-        for (int m = threadIdx.x; lb + (size_t)m * nbt < (size_t)a.nblk; m += NT) {
+        double t0s = block_sum_k<NT / 64>(q0, lds, kr);
+        double t1s = MODE == W_NORM ? block_sum_k<NT / 64>(q1, lds + (NT / 64) * 8, kr) : 0.0;
+        // thread q of the first K holds RHS rt*K + q's sums; the zeroed slots
+        // of the tile's RHS are spread over the block's threads
+        __shared__ double sums[2][8];
+        if (threadIdx.x < K) {
+            sums[0][threadIdx.x] = t0s;
+            sums[1][threadIdx.x] = t1s;
+        }
+        __syncthreads();
+        const int nz = (a.nblk - 1 - lb) / nbt + 1;   // slots lb + m*nbt below nblk
+        for (int idx = threadIdx.x; idx < K * nz; idx += NT) {
+            const int q = idx % K, m = idx / K;
+            const int rr = rt * K + q;
+            if (rr >= a.nrhs || (a.skip && a.skip[rr])) continue;
             const size_t slot = (size_t)lb + (size_t)m * nbt;
-            a.partials[(size_t)r * a.nblk + slot] = m == 0 ? t0s : 0.0;
-            if (nq == 2) a.partials[(size_t)(a.nrhs + r) * a.nblk + slot] = m == 0 ? t1s : 0.0;
+            a.partials[(size_t)rr * a.nblk + slot] = m == 0 ? sums[0][q] : 0.0;
+            if (nq == 2) a.partials[(size_t)(a.nrhs + rr) * a.nblk + slot] = m == 0 ? sums[1][q] : 0.0;
         }
     }
 }

@@ -5,47 +5,82 @@
 
 namespace ovl {
 
-template <int PREC, int WPE, bool STAGE, int NT = kBlock>
+template <int PREC, int WPE, bool STAGE, int NT = kBlock, bool TILED = false>
 static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
 {
     if (g5) {
         switch (mode) {
-        case W_PLAIN: k_wilson_ts<PREC, W_PLAIN, true, WPE, STAGE, NT><<<grid, NT, 0, st>>>(a); break;
-        case W_NORM: k_wilson_ts<PREC, W_NORM, true, WPE, STAGE, NT><<<grid, NT, 0, st>>>(a); break;
-        case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true, WPE, STAGE, NT><<<grid, NT, 0, st>>>(a); break;
-        case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true, WPE, STAGE, NT><<<grid, NT, 0, st>>>(a); break;
-        default: k_wilson_ts<PREC, W_RESNORM, true, WPE, STAGE, NT><<<grid, NT, 0, st>>>(a); break;
+        case W_PLAIN: k_wilson_ts<PREC, W_PLAIN, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
+        case W_NORM: k_wilson_ts<PREC, W_NORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
+        case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
+        case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
+        default: k_wilson_ts<PREC, W_RESNORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         }
     } else {
-        k_wilson_ts<PREC, W_PLAIN, false, WPE, STAGE, NT><<<grid, NT, 0, st>>>(a);
+        k_wilson_ts<PREC, W_PLAIN, false, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a);
     }
 }
 
 // Blocks of whole x3 rows of consecutive x2 at one x1 take the one-wave build
 // that stages each slice in LDS, at any grid size (at 32^3x64 it beats the
 // two-wave build for one field, 411 against 456 us in FP64, and for batches
-// of 7 fields, 2.7 against 2.9 ms); blocks of 192 sites (nt, from
+// of 7 fields, 2.7 against 2.9 ms); blocks of 192 threads (nt, from
 // stream_threads) exist only for that build.  Otherwise launches of at most
 // 512 blocks take the one-wave build without staging, larger grids the
-// two-wave build.
+// two-wave build.  A block holds nt >> kr sites (K = 2^kr lanes per site).
+static bool staged_rows(const Geom &g, int sites)
+{
+    return sites % g.L[3] == 0 && (g.L[2] * g.L[3]) % sites == 0;
+}
+
 template <int PREC>
 static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, int nt, const WArgs &a, hipStream_t st)
 {
-    if constexpr (PREC != P_F16S) {
-        if (nt == 192) {
-            wilson_ts_dispatch_s<PREC, 1, true, 192>(mode, g5, grid, a, st);
-            return;
-        }
+    // 192-thread blocks (three waves) in FP64 take the build capped at two
+    // waves per SIMD: the one-wave build needs more than 256 registers, so a
+    // block holds three of a CU's four SIMDs and the fourth idles (24^3x48,
+    // 12 RHS: 1489 -> 1252 us, with a few spilled registers); FP32 measured the
+    // same either way
+    constexpr int W192 = PREC == P_F64 ? 2 : 1;
+    if (a.kr > 0) {
+        // RHS tiles: staged builds only (stencil_shape guarantees whole rows)
+        if (nt == 192) wilson_ts_dispatch_s<PREC, W192, true, 192, true>(mode, g5, grid, a, st);
+        else wilson_ts_dispatch_s<PREC, 1, true, kBlock, true>(mode, g5, grid, a, st);
+        return;
     }
-    const int L2 = a.g.L[2], L3 = a.g.L[3];
-    const bool rows = kBlock % L3 == 0 && (L2 * L3) % kBlock == 0;
-    if (rows) {
+    if (nt == 192) {
+        wilson_ts_dispatch_s<PREC, W192, true, 192>(mode, g5, grid, a, st);
+        return;
+    }
+    if (staged_rows(a.g, nt)) {
         wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st);
     } else if (grid.x <= 512) {
         wilson_ts_dispatch_s<PREC, 1, false>(mode, g5, grid, a, st);
     } else {
         wilson_ts_dispatch_s<PREC, 2, false>(mode, g5, grid, a, st);
     }
+}
+
+// The streaming form's shape.  The RHS tile K is the lattice's rhs_tile,
+// capped at the next power of two of nrhs, and halved until the block's
+// sites times the stream length cover at least 256 site-slices (so the
+// blocks of one tile fit the 2 nb partial-sum slots per RHS) and the block's
+// sites are whole x3 rows (tiles run in the LDS-staged build only).
+StencilShape stencil_shape(const Lat &L, int prec, int nrhs)
+{
+    StencilShape sh{};
+    const int ts = prec == P_F64 && L.g.Ts64 > 0 ? L.g.Ts64 : L.g.Ts;
+    if (ts <= 0 || prec == P_F16S) return sh;
+    const int nt = stream_threads(L.g, ts);
+    int kr = L.g.Kr;
+    while (kr > 0 && (1 << (kr - 1)) >= nrhs) kr--;   // K <= next power of two of nrhs
+    while (kr > 0 && ((nt >> kr) * ts < 256 || !staged_rows(L.g, nt >> kr))) kr--;
+    sh.ts = ts;
+    sh.nt = nt;
+    sh.kr = kr;
+    sh.blocks_per_tile = (int)(L.V / ((int64_t)(nt >> kr) * ts));
+    sh.ntile = (nrhs + (1 << kr) - 1) >> kr;
+    return sh;
 }
 
 template <int PREC>
@@ -68,15 +103,17 @@ hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hip
 {
     a.g = L.g;
     a.nblk = 2 * L.nb;
-    const int ts = prec == P_F64 && L.g.Ts64 > 0 ? L.g.Ts64 : L.g.Ts;
-    if (ts > 0 && prec != P_F16S) {
-        // time-streaming form (FP64, FP32): V / (NT Ts) blocks per RHS; the
-        // FP16 stencil keeps one site per thread, which measured faster
-        const int nt = stream_threads(L.g, ts);
-        dim3 grid((unsigned)(L.V / ((int64_t)nt * ts)) * a.nrhs);
-        if (prec == P_F64) wilson_ts_dispatch<P_F64>(mode, g5, grid, nt, a, st);
-        else if (prec == P_F32) wilson_ts_dispatch<P_F32>(mode, g5, grid, nt, a, st);
-        else wilson_ts_dispatch<P_F16S>(mode, g5, grid, nt, a, st);
+    a.kr = 0;
+    const StencilShape sh = stencil_shape(L, prec, a.nrhs);
+    if (sh.ts > 0) {
+        // time-streaming form (FP64, FP32): blocks_per_tile blocks per RHS
+        // tile; the FP16 stencil keeps one site per thread, which measured
+        // faster
+        if (sh.blocks_per_tile > a.nblk) return hipErrorInvalidConfiguration;
+        a.kr = sh.kr;
+        dim3 grid((unsigned)sh.blocks_per_tile * sh.ntile);
+        if (prec == P_F64) wilson_ts_dispatch<P_F64>(mode, g5, grid, sh.nt, a, st);
+        else wilson_ts_dispatch<P_F32>(mode, g5, grid, sh.nt, a, st);
         return hipGetLastError();
     }
     dim3 grid(2 * L.nb * a.nrhs);

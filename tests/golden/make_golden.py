@@ -62,7 +62,7 @@ def write(path, cfg, sites, results, meta):
         for r, (vals, rms, iters) in enumerate(results):
             f.write(f"rhs {r} rms {rms!r} iterations {iters}\n")
             for s, v in zip(sites, vals):
-                nums = " ".join(f"{z.real!r} {z.imag!r}" for z in v.reshape(12))
+                nums = " ".join(f"{float(z.real)!r} {float(z.imag)!r}" for z in v.reshape(12))
                 f.write(f"{s} {nums}\n")
 
 
@@ -90,7 +90,7 @@ def run(cfg, name, nsample, seed):
         print(f"[{name}] rhs {r}: {it} iterations, rms site norm {rms:.6e} ({time.time() - t0:.0f}s)", flush=True)
         del out
     meta = dict(dims=" ".join(map(str, dims)), rho=RHO, poles=c["poles"], tol=TOL,
-                interval=f"{lo!r} {hi!r}", lanczos=LANCZOS, delta=repr(delta))
+                interval=f"{float(lo)!r} {float(hi)!r}", lanczos=LANCZOS, delta=repr(float(delta)))
     write(os.path.join(HERE, f"{name}.txt"), cfg, sites, results, meta)
 
 

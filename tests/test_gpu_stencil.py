@@ -298,8 +298,9 @@ def test_autotune_keeps_results(ovl, dims, nrhs):
     note(f"autotune dims={dims} nrhs={nrhs}")
     lat, olat, U, G = setup(ovl, dims, seed=29, n_stout=1)
     res = ovl.autotune_stencil(lat, G, nrhs)
-    assert len(res["timings"]) > 3 and all(t > 0 for _, _, t in res["timings"])
+    assert len(res["timings"]) > 3 and all(t > 0 for _, _, _, t in res["timings"])
     assert dims[0] % lat.tile_t == 0
+    assert lat.rhs_tile in (1, 2, 4, 8) and (nrhs > 1 or lat.rhs_tile == 1)
     assert lat.stream_t == 0 or dims[0] % lat.stream_t == 0
     assert lat.stream_t64 == 0 or dims[0] % lat.stream_t64 == 0
     psi = synth.gaussian_spinor(lat.V, 30, nrhs)
@@ -338,3 +339,33 @@ def test_staged_stream_matches_oracle(ovl, dims, ts, bc):
         got = out.to_canonical().cpu().numpy()
         for r in range(2):
             check(prec, got[r], oracle.q2(olat, U, M0, psi[r], 0.29), psi[r], dims, shift=0.29)
+
+
+# RHS tiles of the streaming form: K lanes per site hold K RHS (one link load
+# serves them); tiles need whole x3 rows per block and at least 256
+# site-slices per block, else the launcher halves K.  nrhs not a multiple of K
+# leaves idle lanes in the last tile.
+TILE_CASES = [((8, 2, 16, 16), 8, 2, 3), ((8, 2, 16, 16), 8, 4, 5), ((8, 2, 16, 16), 8, 8, 12),
+              ((8, 4, 24, 24), 4, 2, 3), ((8, 4, 24, 24), 8, 4, 6), ((16, 4, 24, 24), 16, 8, 9),
+              ((4, 4, 16, 16), 4, 4, 4)]
+
+
+@pytest.mark.parametrize("dims,ts,tile,nrhs", TILE_CASES)
+def test_rhs_tiles_match_oracle(ovl, dims, ts, tile, nrhs):
+    note(f"rhs tiles dims={dims} stream={ts} tile={tile} nrhs={nrhs}")
+    lat, olat, U, G = setup(ovl, dims, seed=41, n_stout=1, bc=(-1, 1, -1, 1))
+    lat.stream_t = ts
+    lat.stream_t64 = ts
+    lat.rhs_tile = tile
+    psi = synth.gaussian_spinor(lat.V, 42, nrhs)
+    for prec in (0, 1):
+        inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+        out = ovl.Spinor(lat, prec, nrhs)
+        ovl.wilson_apply(lat, G, M0, inp, out)
+        got = out.to_canonical().cpu().numpy()
+        for r in range(nrhs):
+            check(prec, got[r], oracle.dw(olat, U, M0, psi[r]), psi[r], dims)
+        ovl.q2_apply(lat, G, M0, 0.23, inp, out)
+        got = out.to_canonical().cpu().numpy()
+        for r in range(nrhs):
+            check(prec, got[r], oracle.q2(olat, U, M0, psi[r], 0.23), psi[r], dims, shift=0.23)

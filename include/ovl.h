@@ -173,6 +173,13 @@ typedef struct {
                                 first iteration */
     int32_t block_f64;       /* mixed: block length of the FP64 phase,
                                 1..OVL_MAX_BLOCK, 0 meaning 16 */
+    int32_t rhs_group;       /* sign_q_apply, overlap_apply and multishift_cg
+                                with weights: solve the RHS of a call in
+                                consecutive groups of this many, one after
+                                another in the same workspace (0: all
+                                together); ovl_workspace_bytes sizes the
+                                workspace for one group.  Ignored by
+                                multishift_cg without weights */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */
@@ -303,6 +310,78 @@ OVL_API int ovl_overlap_apply(const ovl_lattice *lat, const ovl_gauge *U, double
                       const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
                       ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- outer solver ---------------------------------------------------------- */
+
+#define OVL_MAX_RESTART 512   /* longest restart length of ovl_overlap_solve */
+
+/* Parameters of ovl_overlap_solve (defaults from ovl_default_outer_params,
+ * after Table (allparms1)). */
+typedef struct {
+    double tol;              /* eps_outer: required reduction |r|/|eta| (1e-8) */
+    int32_t restart;         /* FGMRES restart length m_restart, 1..OVL_MAX_RESTART (100) */
+    int32_t maxiter;         /* cap on Krylov steps (D_ov applications) (1000) */
+    int32_t relax;           /* 1: at step k the multishift tolerance of the D_ov
+                                application is min(sign_tol_max,
+                                tol * relax_factor / (|r_k|/|eta|)); 0: the fixed
+                                tol * relax_factor (1) */
+    double relax_factor;     /* 1e-2 */
+    double sign_tol_max;     /* cap of the relaxed tolerance (1e-2) */
+    ovl_solver_params inner; /* the D_ov applications' multishift CG (its tol is
+                                set per step; mixed mode scales sloppy_below with
+                                it); defaults of ovl_default_params in mixed mode */
+    int32_t precondition;    /* 1: right preconditioner D_W(prec_m0)^{-1} applied
+                                by ovl_wilson_solve's method (0) */
+    double prec_m0;          /* m0^prec (eq. (default_m)); no default: the caller's */
+    double prec_tol;         /* eps_prec, the preconditioner's relative residual
+                                on its normal equations (1e-1) */
+    int32_t prec_maxiter;    /* cap on each preconditioner solve's CG iterations (200) */
+    int32_t prec_block;      /* block length of that CG, 1..OVL_MAX_BLOCK (16) */
+} ovl_outer_params;
+
+typedef struct {
+    int32_t iterations;        /* Krylov steps (each one D_ov application) */
+    int32_t restarts;          /* FGMRES cycles after the first */
+    int32_t overlap_applies;   /* all D_ov applications (steps and residual checks) */
+    int32_t mscg_iterations;   /* multishift CG iterations over all of them */
+    int32_t prec_iterations;   /* CG iterations over all preconditioner solves */
+    double residual;           /* |eta - D_ov psi| / |eta| of the returned psi, from a
+                                  D_ov applied with multishift tolerance
+                                  tol * relax_factor */
+    double estimated_residual; /* the FGMRES estimate at the last step */
+    double seconds;            /* wall time of the call (it synchronises) */
+} ovl_outer_stats;
+
+OVL_API void ovl_default_outer_params(ovl_outer_params *prm);
+
+/* Workspace bytes of ovl_overlap_solve for npoles Zolotarev poles. */
+OVL_API size_t ovl_overlap_solve_workspace_bytes(const ovl_lattice *lat, int32_t npoles,
+                                                 const ovl_outer_params *prm);
+
+/* psi = D_ov^{-1} eta, D_ov = rho (I + Gamma_5 sign(Q)) as in ovl_overlap_apply
+ * (eq. (linsys) with the overlap operator of eq. (overlap_def)), by restarted
+ * flexible GMRES in FP64 with relaxed D_ov applications and an optional
+ * Wilson-Dirac right preconditioner D_W(m0^prec)^{-1} (Section 3).  eta, psi:
+ * FP64 spinors with nrhs = 1.  The gauge field needs its FP64 and FP32 copies.
+ * Returns OVL_OK when |eta - D_ov psi| <= tol |eta| (the check applies D_ov with
+ * multishift tolerance tol * relax_factor), OVL_NOT_CONVERGED at maxiter with
+ * psi the last iterate, or an error.  Synchronises the stream. */
+OVL_API int ovl_overlap_solve(const ovl_lattice *lat, const ovl_gauge *U, double rho, const ovl_zolo *z,
+                              const ovl_spinor *eta, ovl_spinor *psi, const ovl_outer_params *prm,
+                              ovl_outer_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* x = D_W(m0)^{-1} b (eq. (Wilson-Dirac)) for each RHS, through the normal
+ * equations D_W^H D_W x = D_W^H b with D_W^H = Gamma_5 D_W Gamma_5
+ * (eq. (gamma_5_symmetry)): an FP32 CG (block length prm->block, 0 meaning 16)
+ * with FP64 residual replacement, to prm->tol relative residual of the normal
+ * equations or prm->maxiter iterations.  b, x: FP64 spinors, equal nrhs,
+ * distinct.  stats (optional): iterations[q] and true_residual[q][0] =
+ * |b - D_W x| / |b| in FP64.  ws: ovl_workspace_bytes(lat, OVL_OP_WILSON_SOLVE,
+ * OVL_F64, nrhs, 0, prm) bytes.  Returns OVL_OK, OVL_NOT_CONVERGED or an
+ * error.  Synchronises the stream. */
+OVL_API int ovl_wilson_solve(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_spinor *b,
+                             ovl_spinor *x, const ovl_solver_params *prm, ovl_solver_stats *stats, void *ws,
+                             size_t ws_bytes, void *stream);
+
 /* ---- workspace and diagnostics ------------------------------------------ */
 
 enum ovl_op {
@@ -310,6 +389,7 @@ enum ovl_op {
     OVL_OP_LANCZOS = 1,
     OVL_OP_MSCG = 2,      /* ovl_multishift_cg, sign_q_apply, overlap_apply */
     OVL_OP_TUNE = 3,      /* ovl_autotune_stencil (prec ignored) */
+    OVL_OP_WILSON_SOLVE = 4 /* ovl_wilson_solve (prm: its block length) */
 };
 
 /* Workspace bytes for an operation; prm may be NULL for OVL_OP_Q2/LANCZOS. */
@@ -318,7 +398,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
  * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 1e-5,
- * block_f64 0. */
+ * block_f64 0, rhs_group 0. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 /* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on

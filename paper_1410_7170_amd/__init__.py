@@ -31,7 +31,7 @@ OK, NOT_CONVERGED = 0, 1
 ERR_INVALID, ERR_WORKSPACE, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
 F64, F32, F16S = 0, 1, 2
 SOLVE_F64, SOLVE_MIXED = 0, 1
-OP_Q2, OP_LANCZOS, OP_MSCG, OP_TUNE = 0, 1, 2, 3
+OP_Q2, OP_LANCZOS, OP_MSCG, OP_TUNE, OP_WILSON_SOLVE = 0, 1, 2, 3, 4
 K_STENCIL, K_UPDATE, K_SCALAR, K_OTHER = 0, 1, 2, 3
 MAX_SHIFTS, MAX_RHS, MAX_BLOCK = 32, 16, 32
 PREC_NAMES = {F64: "f64", F32: "f32", F16S: "f16s"}
@@ -59,7 +59,7 @@ class ovl_zolo(ctypes.Structure):
 class ovl_solver_params(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("maxiter", c_i32), ("mode", c_i32), ("reliable_delta", c_dbl),
                 ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32), ("profile", c_i32),
-                ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32)]
+                ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32), ("rhs_group", c_i32)]
 
 
 class ovl_solver_stats(ctypes.Structure):
@@ -81,6 +81,22 @@ class ovl_solver_stats(ctypes.Structure):
             kernel_seconds=[float(v) for v in self.kernel_seconds],
             kernel_bytes=[float(v) for v in self.kernel_bytes],
             kernel_launches=[int(v) for v in self.kernel_launches])
+
+
+class ovl_outer_params(ctypes.Structure):
+    _fields_ = [("tol", c_dbl), ("restart", c_i32), ("maxiter", c_i32), ("relax", c_i32),
+                ("relax_factor", c_dbl), ("sign_tol_max", c_dbl), ("inner", ovl_solver_params),
+                ("precondition", c_i32), ("prec_m0", c_dbl), ("prec_tol", c_dbl), ("prec_maxiter", c_i32),
+                ("prec_block", c_i32)]
+
+
+class ovl_outer_stats(ctypes.Structure):
+    _fields_ = [("iterations", c_i32), ("restarts", c_i32), ("overlap_applies", c_i32),
+                ("mscg_iterations", c_i32), ("prec_iterations", c_i32), ("residual", c_dbl),
+                ("estimated_residual", c_dbl), ("seconds", c_dbl)]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 P = ctypes.POINTER
@@ -114,6 +130,12 @@ _sig = {
                                      P(ctypes.c_float), c_i32, c_vp]),
     "ovl_autotune_stencil_cached": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_i32, c_vp, ctypes.c_size_t,
                                             ctypes.c_char_p, P(c_i32), P(ctypes.c_float), c_i32, c_vp]),
+    "ovl_default_outer_params": (None, [P(ovl_outer_params)]),
+    "ovl_overlap_solve_workspace_bytes": (ctypes.c_size_t, [P(ovl_lattice), c_i32, P(ovl_outer_params)]),
+    "ovl_overlap_solve": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, P(ovl_zolo), P(ovl_spinor), P(ovl_spinor),
+                                  P(ovl_outer_params), P(ovl_outer_stats), c_vp, ctypes.c_size_t, c_vp]),
+    "ovl_wilson_solve": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, P(ovl_spinor), P(ovl_spinor),
+                                 P(ovl_solver_params), P(ovl_solver_stats), c_vp, ctypes.c_size_t, c_vp]),
     "ovl_status_string": (ctypes.c_char_p, [c_i32]),
     "ovl_last_hip_error": (c_i32, []),
     "ovl_version": (ctypes.c_char_p, []),
@@ -422,3 +444,47 @@ def overlap_apply(lat: Lattice, U: Gauge, rho: float, shifts, weights, b: Spinor
                                 ctypes.byref(st), c_vp(ws.data_ptr()), ws.numel(), _stream(stream))
     _check(rc, "ovl_overlap_apply", allow_not_converged)
     return st.to_dict(b.nrhs, z.npoles)
+
+
+def default_outer_params(**kw) -> ovl_outer_params:
+    """ovl_default_outer_params, then keyword overrides; inner=dict(...)
+    overrides fields of the D_ov applications' solver parameters."""
+    p = ovl_outer_params()
+    _lib.ovl_default_outer_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "inner":
+            for ik, iv in v.items():
+                setattr(p.inner, ik, iv)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def overlap_solve(lat: Lattice, U: Gauge, rho: float, shifts, weights, eta: Spinor, psi: Spinor, params=None,
+                  ws=None, stream=None, allow_not_converged=False) -> dict:
+    """psi = D_ov^{-1} eta by FGMRES (ovl_overlap_solve); returns the stats."""
+    params = params or default_outer_params()
+    z, keep = _zolo(shifts, weights)
+    if ws is None:
+        ws = _dev_buffer(_lib.ovl_overlap_solve_workspace_bytes(lat.ref, z.npoles, ctypes.byref(params)),
+                         eta.data.device)
+    st = ovl_outer_stats()
+    rc = _lib.ovl_overlap_solve(lat.ref, U.ref, float(rho), ctypes.byref(z), eta.ref, psi.ref, ctypes.byref(params),
+                                ctypes.byref(st), c_vp(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "ovl_overlap_solve", allow_not_converged)
+    return st.to_dict()
+
+
+def wilson_solve(lat: Lattice, U: Gauge, m0: float, b: Spinor, x: Spinor, params=None, ws=None, stream=None,
+                 allow_not_converged=False) -> dict:
+    """x = D_W(m0)^{-1} b (ovl_wilson_solve); returns iterations and the FP64
+    true residual |b - D_W x|/|b| per RHS."""
+    params = params or default_params()
+    if ws is None:
+        ws = workspace(lat, OP_WILSON_SOLVE, F64, b.nrhs, 0, params, device=b.data.device)
+    st = ovl_solver_stats()
+    rc = _lib.ovl_wilson_solve(lat.ref, U.ref, float(m0), b.ref, x.ref, ctypes.byref(params), ctypes.byref(st),
+                               c_vp(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "ovl_wilson_solve", allow_not_converged)
+    d = st.to_dict(b.nrhs, 1)
+    return dict(iterations=d["iterations"], true_residual=[r[0] for r in d["true_residual"]], seconds=d["seconds"])

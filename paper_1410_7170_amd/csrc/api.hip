@@ -28,6 +28,12 @@ int autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char
 int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
                Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
                hipStream_t st);
+size_t wilson_solve_ws_bytes(const Lat &L, int nrhs, int m);
+int wilson_solve(const Lat &L, const ovl_gauge *U, double m0, Fld b, Fld x, double tol, int maxiter, int m,
+                 double *true_res, int *iters, char *ws, size_t ws_bytes, hipStream_t st);
+size_t outer_ws_bytes(const Lat &L, int npoles, const ovl_outer_params *p, const ovl_lattice *lat);
+int overlap_solve(const ovl_lattice *lat, const ovl_gauge *U, double rho, const ovl_zolo *z, Fld eta, Fld psi,
+                  const ovl_outer_params *prm, ovl_outer_stats *stats, char *ws, size_t ws_bytes, hipStream_t st);
 }  // namespace ovl
 
 using namespace ovl;
@@ -81,7 +87,7 @@ bool params_ok(const ovl_solver_params *p)
     return p && p->tol > 0.0 && std::isfinite(p->tol) && p->maxiter >= 1 &&
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED) && p->reliable_delta > 0.0 &&
            p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
-           p->sloppy_below < 1.0;
+           p->sloppy_below < 1.0 && p->rhs_group >= 0;
 }
 
 bool zolo_ok(const ovl_zolo *z)
@@ -104,6 +110,31 @@ void clear_stats(ovl_solver_stats *st)
     for (int r = 0; r < OVL_MAX_RHS; r++)
         for (int j = 0; j < OVL_MAX_SHIFTS; j++) st->true_residual[r][j] = -1.0;
 }
+
+// Add the stats of a group of RHS (its RHS 0..n-1 are the call's g0..g0+n-1).
+void merge_stats(ovl_solver_stats *dst, const ovl_solver_stats &src, int g0, int n)
+{
+    if (!dst) return;
+    for (int q = 0; q < n; q++) {
+        dst->iterations[g0 + q] = src.iterations[q];
+        for (int j = 0; j < OVL_MAX_SHIFTS; j++) {
+            dst->shift_iters[g0 + q][j] = src.shift_iters[q][j];
+            dst->true_residual[g0 + q][j] = src.true_residual[q][j];
+        }
+    }
+    dst->reliable_updates += src.reliable_updates;
+    dst->refine_iterations += src.refine_iterations;
+    dst->stencil_applies += src.stencil_applies;
+    dst->algorithmic_bytes += src.algorithmic_bytes;
+    for (int c = 0; c < 4; c++) {
+        dst->kernel_seconds[c] += src.kernel_seconds[c];
+        dst->kernel_bytes[c] += src.kernel_bytes[c];
+        dst->kernel_launches[c] += src.kernel_launches[c];
+    }
+}
+
+// RHS per group of a solve returning weighted sums
+int group_size(const ovl_solver_params *prm, int R) { return prm->rhs_group > 0 ? std::min(R, prm->rhs_group) : R; }
 
 }  // namespace
 
@@ -279,8 +310,14 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
     }
     if (op == OVL_OP_LANCZOS) return lanczos_ws_bytes(L);
     if (op == OVL_OP_TUNE) return tune_ws_bytes(L, nrhs);
+    if (op == OVL_OP_WILSON_SOLVE) {
+        const int m = prm && prm->block > 0 ? prm->block : 16;
+        if (m > OVL_MAX_BLOCK) return 0;
+        return wilson_solve_ws_bytes(L, nrhs, m);
+    }
     if (op == OVL_OP_MSCG) {
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS || (prm && !params_ok(prm))) return 0;
+        if (prm && prm->rhs_group > 0) nrhs = std::min(nrhs, (int32_t)prm->rhs_group);   // one group
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_MIXED)
             return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0);
@@ -304,6 +341,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->block = 0;
     p->sloppy_below = 1e-5;
     p->block_f64 = 0;
+    p->rhs_group = 0;
 }
 
 int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
@@ -401,21 +439,33 @@ int ovl_multishift_cg(const ovl_lattice *lat, const ovl_gauge *U, double m0, int
     for (int j = 0; j < nshift; j++)
         if (!(shifts[j] >= 0.0) || !std::isfinite(shifts[j])) return OVL_ERR_INVALID;
     Lat L = make_lat(lat);
-    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_MSCG, OVL_F64, b->nrhs, nshift, prm)) return OVL_ERR_WORKSPACE;
     if (!weights && prm->mode == OVL_SOLVE_MIXED) return OVL_ERR_INVALID;   // the mixed solver returns y only
-    Fld y{};
-    MsScratch scr{};
-    int rc = solve_y(L, U, m0, nshift, shifts, weights, fld(b), prm, stats, (char *)ws, ws_bytes, S(stream), &y, &scr);
-    if (rc >= 0) {
-        size_t F = field_bytes(P_F64, L.V);
+    // every x_l at once: no RHS groups
+    ovl_solver_params p1 = *prm;
+    if (!weights) p1.rhs_group = 0;
+    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_MSCG, OVL_F64, b->nrhs, nshift, &p1)) return OVL_ERR_WORKSPACE;
+    const int R = b->nrhs, G = group_size(&p1, R);
+    const size_t F = field_bytes(P_F64, L.V);
+    int rc_all = OVL_OK;
+    for (int g0 = 0; g0 < R; g0 += G) {
+        const int n = std::min(G, R - g0);
+        ovl_solver_stats cs;
+        clear_stats(&cs);
+        Fld y{};
+        MsScratch scr{};
+        int rc = solve_y(L, U, m0, nshift, shifts, weights, sub(fld(b), L.V, g0, n), &p1, stats ? &cs : nullptr,
+                         (char *)ws, ws_bytes, S(stream), &y, &scr);
+        if (rc < 0) return rc;
         if (weights)
-            OVL_HIP(hipMemcpyAsync(x->d, y.d, F * b->nrhs, hipMemcpyDeviceToDevice, S(stream)));
+            OVL_HIP(hipMemcpyAsync((char *)x->d + F * g0, y.d, F * n, hipMemcpyDeviceToDevice, S(stream)));
         else
-            OVL_HIP(hipMemcpyAsync(x->d, scr.x.d, F * b->nrhs * nshift, hipMemcpyDeviceToDevice, S(stream)));
+            OVL_HIP(hipMemcpyAsync(x->d, scr.x.d, F * R * nshift, hipMemcpyDeviceToDevice, S(stream)));
+        merge_stats(stats, cs, g0, n);
+        if (rc == OVL_NOT_CONVERGED) rc_all = rc;
     }
-    if (rc >= 0) OVL_HIP(hipStreamSynchronize(S(stream)));
+    OVL_HIP(hipStreamSynchronize(S(stream)));
     if (stats) stats->seconds = now() - t0;
-    return rc;
+    return rc_all;
 }
 
 static int sign_or_overlap(const ovl_lattice *lat, const ovl_gauge *U, double m0, double rho, const ovl_zolo *z,
@@ -429,33 +479,41 @@ static int sign_or_overlap(const ovl_lattice *lat, const ovl_gauge *U, double m0
     if (b->prec != OVL_F64 || out->prec != OVL_F64 || b->nrhs != out->nrhs || b->d == out->d) return OVL_ERR_INVALID;
     if (!std::isfinite(m0)) return OVL_ERR_INVALID;
     Lat L = make_lat(lat);
-    const int R = b->nrhs;
+    const int R = b->nrhs, G = group_size(prm, R);
     if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_MSCG, OVL_F64, R, z->npoles, prm)) return OVL_ERR_WORKSPACE;
-    Fld y{};
-    MsScratch scr{};
-    int rc = solve_y(L, U, m0, z->npoles, z->shifts, z->weights, fld(b), prm, stats, (char *)ws, ws_bytes, S(stream),
-                     &y, &scr);
-    if (rc < 0) return rc;
-    WArgs a{};
-    a.in = y.d;
-    a.out = out->d;
-    a.U = U->f64;
-    a.diag = m0 + 4.0;
-    a.nrhs = R;
-    if (overlap) {
-        // out = rho (b + D_W(-rho) y)
-        OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, false, a, S(stream)));
-        OVL_HIP(launch_axpby(L, rho, fld(b), rho, fld(out), S(stream)));
-    } else {
-        OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, true, a, S(stream)));
-    }
-    if (stats) {
-        stats->stencil_applies += 1;
-        stats->algorithmic_bytes += (double)L.V * R * 768.0 + (overlap ? (double)field_bytes(P_F64, L.V) * 3 * R : 0.0);
+    int rc_all = OVL_OK;
+    for (int g0 = 0; g0 < R; g0 += G) {
+        // RHS g0 .. g0+n-1 in one solve; the workspace is reused by the next group
+        const int n = std::min(G, R - g0);
+        const Fld bg = sub(fld(b), L.V, g0, n), og = sub(fld(out), L.V, g0, n);
+        ovl_solver_stats cs;
+        clear_stats(&cs);
+        Fld y{};
+        MsScratch scr{};
+        int rc = solve_y(L, U, m0, z->npoles, z->shifts, z->weights, bg, prm, stats ? &cs : nullptr, (char *)ws,
+                         ws_bytes, S(stream), &y, &scr);
+        if (rc < 0) return rc;
+        WArgs a{};
+        a.in = y.d;
+        a.out = og.d;
+        a.U = U->f64;
+        a.diag = m0 + 4.0;
+        a.nrhs = n;
+        if (overlap) {
+            // out = rho (b + D_W(-rho) y)
+            OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, false, a, S(stream)));
+            OVL_HIP(launch_axpby(L, rho, bg, rho, og, S(stream)));
+        } else {
+            OVL_HIP(launch_wilson(L, P_F64, W_PLAIN, true, a, S(stream)));
+        }
+        cs.stencil_applies += 1;
+        cs.algorithmic_bytes += (double)L.V * n * 768.0 + (overlap ? (double)field_bytes(P_F64, L.V) * 3 * n : 0.0);
+        merge_stats(stats, cs, g0, n);
+        if (rc == OVL_NOT_CONVERGED) rc_all = rc;
     }
     OVL_HIP(hipStreamSynchronize(S(stream)));
     if (stats) stats->seconds = now() - t0;
-    return rc;
+    return rc_all;
 }
 
 int ovl_sign_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_zolo *z, const ovl_spinor *b,
@@ -471,6 +529,84 @@ int ovl_overlap_apply(const ovl_lattice *lat, const ovl_gauge *U, double rho, co
 {
     if (!(rho > 0.0) || !std::isfinite(rho)) return OVL_ERR_INVALID;
     return sign_or_overlap(lat, U, -rho, rho, z, b, out, prm, stats, ws, ws_bytes, stream, true);
+}
+
+void ovl_default_outer_params(ovl_outer_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->tol = 1e-8;
+    p->restart = 100;
+    p->maxiter = 1000;
+    p->relax = 1;
+    p->relax_factor = 1e-2;
+    p->sign_tol_max = 1e-2;
+    ovl_default_params(&p->inner);
+    p->inner.mode = OVL_SOLVE_MIXED;
+    p->precondition = 0;
+    p->prec_m0 = 0.0;
+    p->prec_tol = 1e-1;
+    p->prec_maxiter = 200;
+    p->prec_block = 16;
+}
+
+static bool outer_ok(const ovl_outer_params *p)
+{
+    return p && p->tol > 0.0 && p->tol < 1.0 && p->restart >= 1 && p->restart <= OVL_MAX_RESTART &&
+           p->maxiter >= 1 && (p->relax == 0 || p->relax == 1) && p->relax_factor > 0.0 && p->relax_factor <= 1.0 &&
+           p->sign_tol_max > 0.0 && p->sign_tol_max < 1.0 && params_ok(&p->inner) &&
+           (p->precondition == 0 || p->precondition == 1) && std::isfinite(p->prec_m0) && p->prec_tol > 0.0 &&
+           p->prec_tol < 1.0 && p->prec_maxiter >= 1 && p->prec_block >= 1 && p->prec_block <= OVL_MAX_BLOCK;
+}
+
+size_t ovl_overlap_solve_workspace_bytes(const ovl_lattice *lat, int32_t npoles, const ovl_outer_params *prm)
+{
+    if (!lat_ok(lat) || !outer_ok(prm) || npoles < 1 || npoles > OVL_MAX_SHIFTS) return 0;
+    return outer_ws_bytes(make_lat(lat), npoles, prm, lat);
+}
+
+int ovl_overlap_solve(const ovl_lattice *lat, const ovl_gauge *U, double rho, const ovl_zolo *z,
+                      const ovl_spinor *eta, ovl_spinor *psi, const ovl_outer_params *prm, ovl_outer_stats *stats,
+                      void *ws, size_t ws_bytes, void *stream)
+{
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (!lat_ok(lat) || !outer_ok(prm) || !zolo_ok(z) || !U || !U->f64 || !U->f32 || !ws) return OVL_ERR_INVALID;
+    if (!spinor_ok(eta) || !spinor_ok(psi) || eta->prec != OVL_F64 || psi->prec != OVL_F64 || eta->nrhs != 1 ||
+        psi->nrhs != 1 || eta->d == psi->d)
+        return OVL_ERR_INVALID;
+    if (!(rho > 0.0) || !std::isfinite(rho)) return OVL_ERR_INVALID;
+    const size_t need = ovl_overlap_solve_workspace_bytes(lat, z->npoles, prm);
+    if (need == 0) return OVL_ERR_INVALID;
+    if (ws_bytes < need) return OVL_ERR_WORKSPACE;
+    return overlap_solve(lat, U, rho, z, fld(eta), fld(psi), prm, stats, (char *)ws, ws_bytes, S(stream));
+}
+
+int ovl_wilson_solve(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_spinor *b, ovl_spinor *x,
+                     const ovl_solver_params *prm, ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    const double t0 = now();
+    clear_stats(stats);
+    if (!lat_ok(lat) || !params_ok(prm) || !U || !U->f64 || !U->f32 || !ws || !std::isfinite(m0))
+        return OVL_ERR_INVALID;
+    if (!spinor_ok(b) || !spinor_ok(x) || b->prec != OVL_F64 || x->prec != OVL_F64 || b->nrhs != x->nrhs ||
+        b->d == x->d)
+        return OVL_ERR_INVALID;
+    const size_t need = ovl_workspace_bytes(lat, OVL_OP_WILSON_SOLVE, OVL_F64, b->nrhs, 0, prm);
+    if (need == 0) return OVL_ERR_INVALID;
+    if (ws_bytes < need) return OVL_ERR_WORKSPACE;
+    const Lat L = make_lat(lat);
+    double tr[NR];
+    int it[NR] = {0};
+    int rc = wilson_solve(L, U, m0, fld(b), fld(x), prm->tol, prm->maxiter, prm->block > 0 ? prm->block : 16, tr, it,
+                          (char *)ws, ws_bytes, S(stream));
+    if (rc >= 0 && stats) {
+        for (int q = 0; q < b->nrhs; q++) {
+            stats->iterations[q] = it[q];
+            stats->true_residual[q][0] = tr[q];
+        }
+        stats->seconds = now() - t0;
+    }
+    return rc;
 }
 
 const char *ovl_status_string(int s)

@@ -38,12 +38,27 @@ hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld 
 // workspace grows with nrhs only; refinement is rare and small.
 static int refine_batch(int nrhs) { return std::max(1, std::min(NR, nrhs)); }
 
+// Workspace: [fixed part][region A: the FP64 phase][region B].  Region B
+// holds, one after another, the FP32 phase, the verification's Q x fields and
+// the refinement.  With an FP64 phase the increments dx_j take over that
+// phase's FP64 p_j fields (same count, same layout): the FP32 phase's first
+// pass reads p_j and writes dx_j at the same element in the same thread, and
+// nothing reads p_j afterwards.  At 48^3x96 with 24 poles that saves 24 FP64
+// fields (49 GB) per RHS.
+static size_t region_b_bytes(const Lat &L, int nrhs, int nshift, int m)
+{
+    const size_t F = field_bytes(P_F64, L.V);
+    size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32, true);
+    size_t b = blocked_ws_bytes(L, refine_batch(nrhs), 1, m, true, P_F32);
+    return std::max(std::max(a, b), F);
+}
+
 size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase)
 {
     const size_t F = field_bytes(P_F64, L.V);
     WsCarve c{nullptr, 0, 0};
     const int nbat = refine_batch(nrhs);
-    c.take(F * nrhs * nshift);                        // x_j (or their increments dx_j)
+    if (!f64_phase) c.take(F * nrhs * nshift);        // x_j (no FP64 phase to lend its p_j)
     c.take(F * nbat);                                 // refinement batch right-hand sides
     c.take(F * nbat);                                 // refinement batch corrections
     c.take(F * nrhs);                                 // residual scratch
@@ -53,11 +68,9 @@ size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f
     c.take(sizeof(double) * 4 * NR);
     c.take(sizeof(double) * NR * NS);                 // shift of each (shift, RHS) field
     c.take(sizeof(double) * NR * NS);                 // zeta at the hand-over of each field
-    // the FP64 phase's workspace (y mode) stays alive while the FP32 phase takes over
-    size_t a = blocked_ws_bytes(L, nrhs, nshift, m, true, P_F32, true);
-    if (f64_phase) a += blocked_ws_bytes(L, nrhs, nshift, m64, false, P_F64);
-    size_t b = blocked_ws_bytes(L, nbat, 1, m, true, P_F32);
-    return c.off + std::max(a, b) + 256;
+    if (f64_phase) c.take(blocked_ws_bytes(L, nrhs, nshift, m64, false, P_F64));
+    c.take(region_b_bytes(L, nrhs, nshift, m));
+    return c.off + 256;
 }
 
 // FP64 residuals res = bscale*b - (Q^2 + s) x for the nrhs fields of x (b has
@@ -102,7 +115,9 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, m64, f64_phase)) return OVL_ERR_WORKSPACE;
     WsCarve c{ws, 0, ws_bytes};
     const int NB = refine_batch(R);
-    Fld X{c.take(F * R * nshift), nullptr, P_F64, R * nshift};
+    // the increments dx_j (field j*R + q): their own fields without an FP64
+    // phase, else that phase's p_j (set after it)
+    Fld X{f64_phase ? nullptr : c.take(F * R * nshift), nullptr, P_F64, R * nshift};
     Fld Eb{c.take(F * NB), nullptr, P_F64, NB};
     Fld Ex{c.take(F * NB), nullptr, P_F64, NB};
     Fld T{c.take(F * R), nullptr, P_F64, R};
@@ -112,8 +127,11 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     double *red = (double *)c.take(sizeof(double) * 4 * NR);
     double *fsh = (double *)c.take(sizeof(double) * NR * NS);
     double *fze = (double *)c.take(sizeof(double) * NR * NS);
+    // region A (FP64 phase), then region B
+    const size_t w64 = f64_phase ? align256(blocked_ws_bytes(L, R, nshift, m64, false, P_F64)) : 0;
     char *sws = ws + c.off;
-    size_t sws_bytes = ws_bytes - c.off;
+    char *swb = sws + w64;
+    const size_t swb_bytes = ws_bytes - c.off - w64;
     const int nblk = site_blocks(L);
 
     // |b| per RHS
@@ -132,7 +150,6 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     o.m = m;
     o.keep_x = true;
     o.reliable = true;
-    o.x_ext = X;
     int rc;
     bool switched = false;
     Fld r0 = b;                                                    // residual at the hand-over
@@ -143,7 +160,6 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     // writes, verifies, refines or combines them
     int nz = nshift;
     if (f64_phase) {
-        const size_t w64 = blocked_ws_bytes(L, R, nshift, m64, false, P_F64);
         BlkOpts o64;
         o64.m = m64;
         o64.switch_rel = prm->sloppy_below;
@@ -170,12 +186,17 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
         r0 = R0;
         o.resume = &h64;
         o.x_zero_shifts = nz;   // the increments dx_j (j < nz) start at zero
+        // dx_j take over the FP64 p_j, which the first pass reads in place
+        if (h64.pj.prec != P_F64 || h64.pj.nrhs != R * nshift) return OVL_ERR_INVALID;
+        X.d = h64.pj.d;
+        o.x_ext = X;
         // the base system's true residual during the sloppy phase is r0 - (Q^2 + s0) dx_0
-        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, r0, Fld{}, o, prm, stats, sws + w64,
-                                   sws_bytes - w64, st, nullptr);
+        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, r0, Fld{}, o, prm, stats, swb, swb_bytes, st,
+                                   nullptr);
         if (rc < 0) return rc;
     } else {
-        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, sws, sws_bytes, st,
+        o.x_ext = X;
+        rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, b, Fld{}, o, prm, stats, swb, swb_bytes, st,
                                    nullptr);
         if (rc < 0) return rc;
     }
@@ -189,8 +210,8 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     // f0 .. f0+n-1 of X (field f = j*R + q), up to NV fields per pair of
     // batched stencils: t = Q x (into the solver workspace, free between
     // solves), then the norm without storing the residual
-    const int NV = (int)std::min<size_t>(NR, std::max<size_t>(1, sws_bytes / F));
-    Fld Tv{sws, nullptr, P_F64, NV};
+    const int NV = (int)std::min<size_t>(NR, std::max<size_t>(1, swb_bytes / F));
+    Fld Tv{swb, nullptr, P_F64, NV};
     auto verify = [&](int f0, int n) -> int {
         for (int c0 = f0; c0 < f0 + n; c0 += NV) {
             const int nc = std::min(NV, f0 + n - c0);
@@ -275,7 +296,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
             int its[NR] = {0};
             oc.iters_out = its;
             const double zero = 0.0;
-            int e = mscg_blocked_t<P_F32>(L, U, m0, 1, &zero, nullptr, eb, Fld{}, oc, prm, stats, sws, sws_bytes, st,
+            int e = mscg_blocked_t<P_F32>(L, U, m0, 1, &zero, nullptr, eb, Fld{}, oc, prm, stats, swb, swb_bytes, st,
                                           nullptr);
             if (e < 0) return e;
             int mx = 0;

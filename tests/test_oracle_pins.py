@@ -420,3 +420,41 @@ def test_stout_smearing_lowers_action():
     assert synth.gauge(dims, 0.3, 111, n_stout=3).tobytes() == V.tobytes()
     W = synth.stout(dims, U, -0.1, 1)
     assert oracle.average_plaquette(lat, W) < plaq[0]
+
+
+# ---------------------------------------------------------------- outer solver
+def test_gmres_dense_random_and_restart():
+    """oracle.krylov.gmres against a direct dense solve (LAPACK), for short and
+    long restart cycles: the solution of A x = b does not depend on them."""
+    from oracle import krylov
+    rng = np.random.default_rng(7)
+    n = 80
+    # eigenvalues in a disk of radius about 13 around 30: restarted GMRES converges
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 30.0 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    exact = np.linalg.solve(A, b)
+    for m in (5, 30, 100):
+        x, it, res = krylov.gmres(lambda v: A @ v, b, 1e-12, restart=m)
+        assert res <= 1e-12
+        assert rel(x, exact) < 1e-10, (m, rel(x, exact))
+    x0, it0, _ = krylov.gmres(lambda v: A @ v, np.zeros(n), 1e-12)
+    assert it0 == 0 and not np.any(x0)
+
+
+def test_gmres_overlap_system_vs_dense_solve(lat44, U44, dense44):
+    """eq. (linsys) on the 4^4 dense-check workload: GMRES on the oracle's
+    Zolotarev D_ov against a dense solve with the exact sign (Lemma 2's
+    operator); the difference is bounded by the condition number times the
+    GMRES tolerance plus the Zolotarev error."""
+    from oracle import krylov
+    aw = np.abs(dense44["w"])
+    s, wt, delta = oracle.zolotarev(0.99 * aw.min(), 1.01 * aw.max(), 20)
+    Dov = RHO * (np.eye(3072) + dense44["G5"] @ dense44["S"])
+    b = synth.workload_sources(0)[0]
+    exact = np.linalg.solve(Dov, b.reshape(-1)).reshape(b.shape)
+    cond = np.linalg.cond(Dov)
+    tol = 1e-10
+    x, it, res = krylov.gmres(lambda v: oracle.overlap(lat44, U44, RHO, s, wt, v, 1e-13, 5000)[0], b, tol,
+                              restart=100)
+    assert res <= tol and it > 5
+    assert rel(x, exact) < cond * (tol + 10 * delta) * 10, (rel(x, exact), cond)

@@ -59,6 +59,10 @@ def parse():
                     help="workload recipe of the batched multi-RHS line (3 = 24^3x48, 12 point "
                          "sources); -1 skips it")
     ap.add_argument("--multi-rhs-steps", type=int, default=2)
+    ap.add_argument("--no-outer", action="store_true", help="skip the outer-solve line (16^3x32)")
+    ap.add_argument("--big", type=int, default=-1,
+                    help="workload recipe of the largest line (4 = 48^3x96, 4 Gaussian sources, 24 poles, "
+                         "one call); -1 skips it")
     ap.add_argument("--stencil-order", default="",
                     help="tile_t,stream_t,stream_t64[,rhs_tile] for the main workload instead of autotuning "
                          "(profiling runs pin the order the timed run chose)")
@@ -289,6 +293,8 @@ def main():
     small = small_line(args, ovl, synth, np, torch) if args.small >= 0 else None
     torch.cuda.empty_cache()
     mrhs = multi_rhs_line(args, ovl, synth, np, torch) if args.multi_rhs >= 0 else None
+    torch.cuda.empty_cache()
+    big = big_line(args, ovl, synth, np, torch) if args.big >= 0 else None
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
@@ -337,6 +343,7 @@ def main():
         "cpu_baseline": cpu,
         "small": small,
         "multi_rhs": mrhs,
+        "big": big,
         "autotune": tune["timings"],
     }
     print(json.dumps(line))
@@ -414,8 +421,67 @@ def small_line(args, ovl, synth, np, torch):
         rates[form] = dict(applies_per_s=round(n / (time.perf_counter() - t0), 3), iterations=st["iterations"][0],
                            max_true_residual=max(st["true_residual"][0]))
     log(f"small {dims}: {rates}")
+    outer = None if args.no_outer else outer_line(ovl, torch, lat, G, shifts, weights, B)
     return dict(workload=f"{dims[1]}^3x{dims[0]}, {c['poles']} Zolotarev poles, tol {args.tol:g}",
-                operators=ops, overlap=rates)
+                operators=ops, overlap=rates, outer_solve=outer)
+
+
+def outer_line(ovl, torch, lat, G, shifts, weights, E):
+    """D_ov psi = eta (eq. (linsys)) by FGMRES(100) to 1e-8: with the relaxed
+    sign accuracy of Table (allparms1) and without it, and with the Wilson
+    preconditioner D_W(m0^prec)^{-1} (eps_prec 0.1) at a few masses m0^prec
+    (the paper scans m0^prec, Fig. (prec_eff_m0w))."""
+    psi = ovl.Spinor(lat, ovl.F64)
+    runs = []
+    cases = [dict(relax=1), dict(relax=0)] + [dict(relax=1, precondition=1, prec_m0=m) for m in (-0.1, 0.0, 0.1)]
+    for kw in cases:
+        prm = ovl.default_outer_params(tol=1e-8, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ovl.overlap_solve(lat, G, RHO, shifts, weights, E, psi, prm, allow_not_converged=True)
+        sec = time.perf_counter() - t0
+        runs.append(dict(kw, seconds=round(sec, 3), steps=st["iterations"], overlap_applies=st["overlap_applies"],
+                         mscg_iterations=st["mscg_iterations"], prec_iterations=st["prec_iterations"],
+                         residual=st["residual"]))
+        log(f"outer solve {kw}: {sec:.2f}s, {st['iterations']} steps, {st['mscg_iterations']} MSCG iterations, "
+            f"{st['prec_iterations']} CG iterations, residual {st['residual']:.2e}")
+    return dict(tol=1e-8, restart=100, inner="mixed", runs=runs)
+
+
+def big_line(args, ovl, synth, np, torch):
+    """The 48^3x96 workload: its 4 Gaussian sources in one overlap_apply call
+    (24 poles, groups of one RHS in one workspace), mixed and FP64 blocked."""
+    cfg = args.big
+    c = synth.WORKLOADS[cfg]
+    dims = c["dims"]
+    lat = ovl.Lattice(dims)
+    G = ovl.Gauge(lat, torch.from_numpy(synth.workload_gauge(cfg)).cuda())
+    v0 = synth.gaussian_spinor(lat.V, synth.SEED_BASE + 10 * cfg + 3)[0]
+    lo, hi = ovl.spectral_bounds(lat, G, -RHO, 300, ovl.Spinor.from_canonical(lat, torch.from_numpy(v0).cuda(),
+                                                                                ovl.F64))
+    shifts, weights, delta = ovl.zolotarev(lo, hi, c["poles"])
+    b = synth.workload_sources(cfg)
+    B = ovl.Spinor.from_canonical(lat, torch.from_numpy(b).cuda(), ovl.F64)
+    del b
+    ovl.autotune_stencil(lat, G, 1)
+    out = ovl.Spinor(lat, ovl.F64, B.nrhs)
+    pm = ovl.default_params(tol=args.tol, maxiter=5000, mode=ovl.SOLVE_MIXED, rhs_group=1)
+    p64 = ovl.default_params(tol=args.tol, maxiter=5000, block=16, rhs_group=1)
+    nb = max(ovl.workspace_bytes(lat, ovl.OP_MSCG, ovl.F64, B.nrhs, c["poles"], p) for p in (pm, p64))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    res = {}
+    for name, prm in (("mixed", pm), ("fp64_blocked", p64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ovl.overlap_apply(lat, G, RHO, shifts, weights, B, out, prm, ws=ws)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = dict(seconds=round(el, 3), rhs_applies_per_s=round(B.nrhs / el, 4), iterations=st["iterations"],
+                         max_true_residual=max(max(r) for r in st["true_residual"][:B.nrhs]))
+        log(f"big {dims} {name}: {el:.2f}s for {B.nrhs} RHS")
+    return dict(workload=f"overlap apply {dims[1]}^3x{dims[0]}, {B.nrhs} Gaussian sources in one call, "
+                         f"{c['poles']} Zolotarev poles, tol {args.tol:g}",
+                workspace_GiB=round(nb / 2 ** 30, 1), forms=res)
 
 
 def multi_rhs_line(args, ovl, synth, np, torch):

@@ -87,9 +87,18 @@ enum ovl_prec { OVL_F64 = 0, OVL_F32 = 1, OVL_F16S = 2 };
 /* solver precision modes */
 enum ovl_solve_mode {
     OVL_SOLVE_F64 = 0,   /* every vector, link and stencil in FP64 */
-    OVL_SOLVE_MIXED = 1  /* sloppy FP32 Krylov bulk, FP64 reliable updates,
+    OVL_SOLVE_MIXED = 1, /* sloppy FP32 Krylov bulk, FP64 reliable updates,
                             FP64 per-shift verification and final combination;
                             reads the FP64 and FP32 links (gauge f64, f32) */
+    OVL_SOLVE_LANCZOS = 2 /* sign_q_apply / overlap_apply only: sign(Q) b as the
+                            Lanczos approximation |b| V_k sign(T_k) e_1 on the
+                            Krylov space of Q, in FP64, in two passes (the
+                            first keeps only the Lanczos coefficients, the second
+                            regenerates the basis), without the Zolotarev
+                            function (z is still validated); tol: the relative
+                            change of the coefficient vector between checks
+                            every 32 steps; maxiter: Lanczos steps (< 4096);
+                            stats iterations: the steps of each RHS */
 };
 
 typedef struct {

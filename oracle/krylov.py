@@ -59,3 +59,37 @@ def gmres(apply, b, tol: float, restart: int = 100, maxiter: int = 10000):
         r = bv - A(x)
         beta = np.linalg.norm(r)
     return x.reshape(shape), it, float(beta / bnorm)
+
+
+def lanczos_sign(apply_q, b, steps: int):
+    """The Lanczos approximation of sign(Q) b for Hermitian Q after `steps`
+    steps: |b| V_k sign(T_k) e_1, with V_k the Lanczos basis (kept whole) and
+    sign(T_k) from the eigen-decomposition of the tridiagonal T_k (a Krylov
+    method for the sign function, the kind the paper uses in Section 5).  An
+    exact breakdown stops early.  Returns (approximation, steps taken)."""
+    b = np.asarray(b, dtype=np.complex128)
+    shape = b.shape
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros_like(b), 0
+    Q = lambda v: np.asarray(apply_q(v.reshape(shape)), dtype=np.complex128).reshape(-1)
+    V = [b.reshape(-1) / bn]
+    a, bt = [], []
+    v_prev = np.zeros_like(V[0])
+    beta = 0.0
+    for k in range(steps):
+        w = Q(V[k]) - beta * v_prev
+        alpha = np.vdot(V[k], w).real
+        w = w - alpha * V[k]
+        a.append(alpha)
+        beta = np.linalg.norm(w)
+        if beta <= 1e-14 * abs(alpha) or k == steps - 1:
+            break
+        bt.append(beta)
+        v_prev = V[k]
+        V.append(w / beta)
+    n = len(a)
+    T = np.diag(a) + np.diag(bt[:n - 1], 1) + np.diag(bt[:n - 1], -1)
+    th, Z = np.linalg.eigh(T)
+    c = bn * (Z @ (np.where(th >= 0, 1.0, -1.0) * Z[0]))
+    return (np.array(V[:n]).T @ c).reshape(shape), n

@@ -30,7 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID, ERR_WORKSPACE, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
 F64, F32, F16S = 0, 1, 2
-SOLVE_F64, SOLVE_MIXED = 0, 1
+SOLVE_F64, SOLVE_MIXED, SOLVE_LANCZOS = 0, 1, 2
 OP_Q2, OP_LANCZOS, OP_MSCG, OP_TUNE, OP_WILSON_SOLVE = 0, 1, 2, 3, 4
 K_STENCIL, K_UPDATE, K_SCALAR, K_OTHER = 0, 1, 2, 3
 MAX_SHIFTS, MAX_RHS, MAX_BLOCK = 32, 16, 32

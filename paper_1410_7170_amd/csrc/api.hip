@@ -29,6 +29,10 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
                Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
                hipStream_t st);
 size_t wilson_solve_ws_bytes(const Lat &L, int nrhs, int m);
+size_t lanczos_sign_ws_bytes(const Lat &L, int nrhs);
+int lanczos_sign(const Lat &L, const void *U64, double m0, Fld b, Fld y, double tol, int maxiter, int *iters,
+                 char *ws, size_t ws_bytes, hipStream_t st);
+__global__ void k_gamma5(Geom g, int nb, const double2 *in, double2 *out);
 int wilson_solve(const Lat &L, const ovl_gauge *U, double m0, Fld b, Fld x, double tol, int maxiter, int m,
                  double *true_res, int *iters, char *ws, size_t ws_bytes, hipStream_t st);
 size_t outer_ws_bytes(const Lat &L, int npoles, const ovl_outer_params *p, const ovl_lattice *lat);
@@ -85,7 +89,8 @@ hipStream_t S(void *s) { return (hipStream_t)s; }
 bool params_ok(const ovl_solver_params *p)
 {
     return p && p->tol > 0.0 && std::isfinite(p->tol) && p->maxiter >= 1 &&
-           (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED) && p->reliable_delta > 0.0 &&
+           (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED || p->mode == OVL_SOLVE_LANCZOS) &&
+           p->reliable_delta > 0.0 &&
            p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
            p->sloppy_below < 1.0 && p->rhs_group >= 0;
 }
@@ -319,6 +324,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS || (prm && !params_ok(prm))) return 0;
         if (prm && prm->rhs_group > 0) nrhs = std::min(nrhs, (int32_t)prm->rhs_group);   // one group
         size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
+        if (prm && prm->mode == OVL_SOLVE_LANCZOS) return yb + lanczos_sign_ws_bytes(L, nrhs);
         if (prm && prm->mode == OVL_SOLVE_MIXED)
             return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0);
         if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64);
@@ -439,7 +445,8 @@ int ovl_multishift_cg(const ovl_lattice *lat, const ovl_gauge *U, double m0, int
     for (int j = 0; j < nshift; j++)
         if (!(shifts[j] >= 0.0) || !std::isfinite(shifts[j])) return OVL_ERR_INVALID;
     Lat L = make_lat(lat);
-    if (!weights && prm->mode == OVL_SOLVE_MIXED) return OVL_ERR_INVALID;   // the mixed solver returns y only
+    // the mixed solver returns y only; the Lanczos mode solves no shifted systems
+    if ((!weights && prm->mode == OVL_SOLVE_MIXED) || prm->mode == OVL_SOLVE_LANCZOS) return OVL_ERR_INVALID;
     // every x_l at once: no RHS groups
     ovl_solver_params p1 = *prm;
     if (!weights) p1.rhs_group = 0;
@@ -488,6 +495,34 @@ static int sign_or_overlap(const ovl_lattice *lat, const ovl_gauge *U, double m0
         const Fld bg = sub(fld(b), L.V, g0, n), og = sub(fld(out), L.V, g0, n);
         ovl_solver_stats cs;
         clear_stats(&cs);
+        if (prm->mode == OVL_SOLVE_LANCZOS) {
+            // s = sign(Q) b in the front field set, then out = s or rho (b + Gamma_5 s)
+            const size_t yb = (field_bytes(P_F64, L.V) * G + 255) & ~(size_t)255;
+            Fld sg{ws, nullptr, P_F64, n};
+            int its[NR] = {0};
+            int rc = lanczos_sign(L, U->f64, m0, bg, sg, prm->tol, prm->maxiter, its, (char *)ws + yb,
+                                  ws_bytes - yb, S(stream));
+            if (rc < 0) return rc;
+            if (overlap) {
+                dim3 grid(site_blocks(L), n);
+                k_gamma5<<<grid, kBlock, 0, S(stream)>>>(L.g, L.nb, (const double2 *)sg.d, (double2 *)og.d);
+                OVL_HIP(hipGetLastError());
+                OVL_HIP(launch_axpby(L, rho, bg, rho, og, S(stream)));
+            } else {
+                OVL_HIP(hipMemcpyAsync(og.d, sg.d, field_bytes(P_F64, L.V) * n, hipMemcpyDeviceToDevice,
+                                       S(stream)));
+            }
+            int mx = 0;
+            for (int q = 0; q < n; q++) {
+                cs.iterations[q] = its[q];
+                mx = std::max(mx, its[q]);
+            }
+            cs.stencil_applies = 2 * mx;
+            cs.algorithmic_bytes = 2.0 * mx * (double)L.V * n * 768.0;
+            merge_stats(stats, cs, g0, n);
+            if (rc == OVL_NOT_CONVERGED) rc_all = rc;
+            continue;
+        }
         Fld y{};
         MsScratch scr{};
         int rc = solve_y(L, U, m0, z->npoles, z->shifts, z->weights, bg, prm, stats ? &cs : nullptr, (char *)ws,

@@ -458,3 +458,18 @@ def test_gmres_overlap_system_vs_dense_solve(lat44, U44, dense44):
                               restart=100)
     assert res <= tol and it > 5
     assert rel(x, exact) < cond * (tol + 10 * delta) * 10, (rel(x, exact), cond)
+
+
+def test_lanczos_sign_converges_to_exact_sign(lat44, U44, dense44):
+    """The Lanczos approximation of sign(Q) b (oracle.krylov.lanczos_sign)
+    converges to the exact sign from the dense eigen-decomposition, and with
+    a full Krylov space it is exact."""
+    from oracle import krylov
+    b = synth.workload_sources(0)[0]
+    exact = (dense44["S"] @ b.reshape(-1)).reshape(b.shape)
+    qop = lambda v: oracle.q(lat44, U44, M0, v)
+    errs = [rel(krylov.lanczos_sign(qop, b, k)[0], exact) for k in (50, 150, 400)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-10, errs
+    # a 2x2 diagonal check: sign of diag(3, -2) applied to (1, 1)
+    x, n = krylov.lanczos_sign(lambda v: np.array([3.0, -2.0]) * v, np.array([1.0 + 0j, 1.0]), 5)
+    assert n == 2 and np.allclose(x, [1.0, -1.0], atol=1e-14)

@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--big", type=int, default=-1,
                     help="workload recipe of the largest line (4 = 48^3x96, 4 Gaussian sources, 24 poles, "
                          "one call); -1 skips it")
+    ap.add_argument("--stencil-forms-only", action="store_true",
+                    help="run only the multi-RHS stencil comparison (vector form, RHS tiles, matrix cores) "
+                         "on the batched workload's lattice and print it as the JSON line (profiling runs)")
     ap.add_argument("--stencil-order", default="",
                     help="tile_t,stream_t,stream_t64[,rhs_tile] for the main workload instead of autotuning "
                          "(profiling runs pin the order the timed run chose)")
@@ -182,6 +185,10 @@ def main():
     import paper_1410_7170_amd as ovl
 
     torch.cuda.set_device(0)
+    if args.stencil_forms_only:
+        print(json.dumps(dict(metric="multi-RHS stencil forms", data="synthetic",
+                              stencil_forms=stencil_forms(args, ovl, synth, np, torch))))
+        return
     cfg = synth.WORKLOADS[args.workload]
     dims = cfg["dims"]
     npoles = cfg["poles"]
@@ -540,11 +547,54 @@ def multi_rhs_line(args, ovl, synth, np, torch):
                 iterations=st["iterations"], max_true_residual=max(max(r) for r in st["true_residual"]),
                 refine_iterations=st["refine_iterations"],
                 rel_diff_rhs0_vs_fp64=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-                stencil_order={k: tune[k] for k in ("tile_t", "stream_t", "stream_t64", "rhs_tile")},
-                autotune=tune["timings"])
+                stencil_order={k: tune[k] for k in ("tile_t", "stream_t", "stream_t64", "rhs_tile", "mfma")},
+                autotune=tune["timings"],
+                stencil_forms=stencil_forms(args, ovl, synth, np, torch, lat, G))
     log(f"multi-rhs {dims}: {rate:.3f} RHS-applies/s, FP64 single {single}, "
         f"max residual {line['max_true_residual']:.2e}")
     return line
+
+
+def stencil_forms(args, ovl, synth, np, torch, lat=None, G=None):
+    """D_W on the batched workload's 12 RHS in one launch, per stencil form:
+    one RHS per block (vector ALUs), RHS tiles of 2 and 4 lanes per site
+    sharing each link load, and the matrix-core FP32 form (two sites x four
+    RHS per v_mfma_f32_16x16x4f32).  Algorithmic bytes per site: 12 RHS x
+    (in + out) + the 12-real links once."""
+    cfg = args.multi_rhs if args.multi_rhs >= 0 else 3
+    c = synth.WORKLOADS[cfg]
+    dims = c["dims"]
+    standalone = lat is None
+    if standalone:
+        lat = ovl.Lattice(dims)
+        G = ovl.Gauge(lat, torch.from_numpy(synth.workload_gauge(cfg)).cuda())
+    nrhs = 12
+    psi = torch.from_numpy(synth.gaussian_spinor(lat.V, synth.SEED_BASE + 10 * cfg + 7, nrhs)).cuda()
+    if standalone:
+        ovl.autotune_stencil(lat, G, nrhs)
+    saved = (lat.rhs_tile, lat.mfma)   # the autotuner's choice for 12 RHS
+    res = {}
+    for prec in (ovl.F64, ovl.F32):
+        inp = ovl.Spinor.from_canonical(lat, psi, prec)
+        out = ovl.Spinor(lat, prec, nrhs)
+        algo = lat.V * (nrhs * (SITE_BYTES[prec] - 4 * (96 >> prec)) + 4 * (96 >> prec))
+        forms = [("vector", 1, 0), ("vector_tile2", 2, 0), ("vector_tile4", 4, 0)]
+        if prec == ovl.F32:
+            forms.append(("mfma", 1, 1))
+        for name, tile, mf in forms:
+            lat.rhs_tile, lat.mfma = tile, mf
+            us = median_event_us(torch, lambda: ovl.wilson_apply(lat, G, -RHO, inp, out), n=10, warm=2)
+            res[f"{ovl.PREC_NAMES[prec]}_{name}"] = dict(
+                us=round(us, 1), us_per_rhs=round(us / nrhs, 2),
+                frac=round(algo / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4))
+            log(f"stencil form {ovl.PREC_NAMES[prec]} {name}: {us:.1f} us ({us / nrhs:.1f} us/RHS)")
+        del inp, out
+    lat.rhs_tile, lat.mfma = saved
+    return dict(workload=f"D_W on {nrhs} RHS in one launch, {dims[1]}^3x{dims[0]}", nrhs=nrhs,
+                bytes_per_site={ovl.PREC_NAMES[p]: nrhs * (SITE_BYTES[p] - 4 * (96 >> p)) + 4 * (96 >> p)
+                                for p in (ovl.F64, ovl.F32)},
+                stream_t=lat.stream_t, stream_t64=lat.stream_t64,
+                autotune_choice=dict(rhs_tile=saved[0], mfma=saved[1]), forms=res)
 
 
 def cpu_model() -> str:

@@ -127,6 +127,12 @@ typedef struct {
                           while a block's sites times the stream length are
                           fewer than 256.  1 (one RHS per block) is set by
                           ovl_lattice_init; results do not depend on it */
+    int32_t mfma;      /* 1: FP32 D_W and Gamma_5 D_W (ovl_wilson_apply,
+                          ovl_q_apply and the first stencil of ovl_q2_apply) on
+                          2 or more RHS run on the matrix cores
+                          (v_mfma_f32_16x16x4f32, two sites and four RHS per
+                          wave); 0 (set by ovl_lattice_init): vector ALUs.
+                          Results agree to FP32 rounding */
 } ovl_lattice;
 
 /* A gauge field packed in up to three precisions (device pointers).  An
@@ -425,8 +431,10 @@ OVL_API void ovl_default_params(ovl_solver_params *prm);
  * nrhs, 0, NULL) bytes.  tried/times_us (host, optional, max_tried entries):
  * candidate k as 10000*what + 100*tile + value (what 0 tile_t, 1 stream_t,
  * 2 stream_t64; tile the RHS tile it ran with) and its average launch time in
- * microseconds.  Returns the number of candidates timed (>= 0) or a negative
- * error.  Synchronises the stream. */
+ * microseconds; with FP32 links and nrhs >= 2 the matrix-core FP32 stencil
+ * (lat->mfma) is timed against the chosen vector form as what = 3 (value 1).
+ * Returns the number of candidates timed (>= 0) or a negative error.
+ * Synchronises the stream. */
 OVL_API int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
                                  int32_t *tried, float *times_us, int32_t max_tried, void *stream);
 

@@ -41,7 +41,7 @@ c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, cty
 
 class ovl_lattice(ctypes.Structure):
     _fields_ = [("dims", c_i32 * 4), ("bc", c_i32 * 4), ("vol", c_i64), ("tile_t", c_i32), ("stream_t", c_i32),
-                ("stream_t64", c_i32), ("rhs_tile", c_i32)]
+                ("stream_t64", c_i32), ("rhs_tile", c_i32), ("mfma", c_i32)]
 
 
 class ovl_gauge(ctypes.Structure):
@@ -227,6 +227,14 @@ class Lattice:
         self.c.rhs_tile = int(k)
 
     @property
+    def mfma(self) -> int:
+        return int(self.c.mfma)
+
+    @mfma.setter
+    def mfma(self, v: int):
+        self.c.mfma = 1 if v else 0
+
+    @property
     def ref(self):
         return ctypes.byref(self.c)
 
@@ -376,11 +384,11 @@ def autotune_stencil(lat: Lattice, U: Gauge, nrhs: int = 1, ws=None, stream=None
         rc = _lib.ovl_autotune_stencil(lat.ref, U.ref, int(nrhs), c_vp(ws.data_ptr()), ws.numel(), tried, times, n,
                                        _stream(stream))
     _check(rc, "ovl_autotune_stencil")
-    names = ("tile_t", "stream_t", "stream_t64")
+    names = ("tile_t", "stream_t", "stream_t64", "mfma")
     table = [(names[tried[k] // 10000], (tried[k] // 100) % 100, tried[k] % 100, round(float(times[k]), 2))
              for k in range(min(rc, n))]
     return dict(tile_t=lat.tile_t, stream_t=lat.stream_t, stream_t64=lat.stream_t64, rhs_tile=lat.rhs_tile,
-                timings=table if rc > 0 or cache is None else "cache")
+                mfma=lat.mfma, timings=table if rc > 0 or cache is None else "cache")
 
 
 def spectral_bounds(lat: Lattice, U: Gauge, m0: float, iters: int, start: Spinor,

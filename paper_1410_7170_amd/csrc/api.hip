@@ -63,6 +63,7 @@ bool lat_ok(const ovl_lattice *lat)
                                 ((int64_t)lat->dims[1] * lat->dims[2] * lat->dims[3]) % 256))
         return false;
     if (lat->rhs_tile != 1 && lat->rhs_tile != 2 && lat->rhs_tile != 4 && lat->rhs_tile != 8) return false;
+    if (lat->mfma != 0 && lat->mfma != 1) return false;
     return V < ((int64_t)1 << 31) && lat->vol == V;
 }
 
@@ -210,6 +211,7 @@ int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4
     lat->stream_t = 0;
     lat->stream_t64 = 0;
     lat->rhs_tile = 1;
+    lat->mfma = 0;
     const int64_t V3 = (int64_t)dims[1] * dims[2] * dims[3];
     if (V3 % 256 == 0) {
         for (int s : {16, 8, 4, 2})

@@ -85,6 +85,7 @@ struct Geom {
     int Ts;        // time slices per thread of the time-streaming stencil (0: not used)
     int Ts64;      // time slices per thread of the FP64 streaming stencil (0: Ts)
     int Kr;        // log2 of the RHS tile of the streaming stencil (lanes per site)
+    int Mfma;      // FP32 D_W on several RHS by the matrix-core stencil
 };
 
 // Threads (sites) per block of the time-streaming stencil with ts slices per

@@ -63,6 +63,8 @@ inline Fld sub(const Fld &f, int64_t V, int first, int count)
 
 // ---- launchers (return hipError_t of the launch)
 hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hipStream_t st);
+// FP32 D_W (or Gamma_5 D_W) on the matrix cores (wilson_mfma.hip); a.g set
+hipError_t launch_wilson_mfma(const Lat &L, bool g5, const WArgs &a, hipStream_t st);
 hipError_t launch_pack_spinor(const Lat &L, const void *canon, Fld out, hipStream_t st);
 hipError_t launch_unpack_spinor(const Lat &L, Fld in, void *canon, hipStream_t st);
 hipError_t launch_pack_gauge(const Lat &L, const void *canon, int prec, void *out, hipStream_t st);

@@ -23,6 +23,7 @@ Lat make_lat(const ovl_lattice *lat)
     L.g.Ts = lat->stream_t;
     L.g.Ts64 = lat->stream_t64;
     L.g.Kr = lat->rhs_tile >= 8 ? 3 : lat->rhs_tile >= 4 ? 2 : lat->rhs_tile >= 2 ? 1 : 0;
+    L.g.Mfma = lat->mfma;
     L.nb = (L.Vh + kBlock - 1) / kBlock;
     return L;
 }

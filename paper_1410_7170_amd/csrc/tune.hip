@@ -210,6 +210,26 @@ int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, s
             if (Up[P_F64]) lat->stream_t64 = best_s64;
         }
     }
+    // 3. the matrix-core FP32 stencil against the chosen vector form (FP32 D_W
+    // on several RHS); it replaces it only when more than 5% faster
+    if (!rc && Up[P_F32] && nrhs >= 2) {
+        const int cur_m = lat->mfma;
+        float tv = 0.f, tm = 0.f;
+        lat->mfma = 0;
+        rc = time_stencil(make_lat(lat), Up[P_F32], P_F32, fl[P_F32], reps, e0, e1, st, &tv);
+        if (!rc) {
+            lat->mfma = 1;
+            rc = time_stencil(make_lat(lat), Up[P_F32], P_F32, fl[P_F32], reps, e0, e1, st, &tm);
+        }
+        if (!rc) {
+            record(3, 1, 0, tv);
+            record(3, 1, 1, tm);
+            const float tcur = cur_m ? tm : tv, tother = cur_m ? tv : tm;
+            lat->mfma = tother < 0.95f * tcur ? 1 - cur_m : cur_m;
+        } else {
+            lat->mfma = cur_m;
+        }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return rc ? rc : n;
@@ -239,15 +259,17 @@ int autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char
     if (path) {
         if (FILE *f = std::fopen(path, "r")) {
             char line[512], k2[256];
-            int t = 0, s = 0, s64 = 0, rt = 0;
+            int t = 0, s = 0, s64 = 0, rt = 0, mf = 0;
             bool hit = false;
             while (std::fgets(line, sizeof line, f)) {
+                int t1, s1, s641, rt1, mf1;
                 if (std::sscanf(line,
                                 "{\"key\": \"%255[^\"]\", \"tile_t\": %d, \"stream_t\": %d, \"stream_t64\": %d, "
-                                "\"rhs_tile\": %d}",
-                                k2, &t, &s, &s64, &rt) == 5 &&
+                                "\"rhs_tile\": %d, \"mfma\": %d}",
+                                k2, &t1, &s1, &s641, &rt1, &mf1) == 6 &&
                     std::strcmp(k2, key) == 0) {
                     hit = true;   // the last matching line wins
+                    t = t1, s = s1, s64 = s641, rt = rt1, mf = mf1;
                 }
             }
             std::fclose(f);
@@ -257,9 +279,11 @@ int autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char
                 c.stream_t = s;
                 c.stream_t64 = s64;
                 c.rhs_tile = rt;
+                c.mfma = mf;
                 // a stale or foreign entry that the lattice would reject is ignored
                 const bool ok = t >= 1 && lat->dims[0] % t == 0 && (s == 0 || lat->dims[0] % s == 0) &&
-                                (s64 == 0 || lat->dims[0] % s64 == 0) && (rt == 1 || rt == 2 || rt == 4 || rt == 8);
+                                (s64 == 0 || lat->dims[0] % s64 == 0) && (rt == 1 || rt == 2 || rt == 4 || rt == 8) &&
+                                (mf == 0 || mf == 1);
                 if (ok) {
                     *lat = c;
                     return 0;
@@ -270,8 +294,10 @@ int autotune_stencil_cached(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char
     const int n = autotune_stencil(lat, U, nrhs, ws, ws_bytes, st, tried, times_us, max_tried);
     if (n >= 0 && path) {
         if (FILE *f = std::fopen(path, "a")) {
-            std::fprintf(f, "{\"key\": \"%s\", \"tile_t\": %d, \"stream_t\": %d, \"stream_t64\": %d, \"rhs_tile\": %d}\n",
-                         key, lat->tile_t, lat->stream_t, lat->stream_t64, lat->rhs_tile);
+            std::fprintf(f,
+                         "{\"key\": \"%s\", \"tile_t\": %d, \"stream_t\": %d, \"stream_t64\": %d, \"rhs_tile\": %d, "
+                         "\"mfma\": %d}\n",
+                         key, lat->tile_t, lat->stream_t, lat->stream_t64, lat->rhs_tile, lat->mfma);
             std::fclose(f);
         }
     }

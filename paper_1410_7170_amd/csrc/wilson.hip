@@ -104,6 +104,7 @@ hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hip
     a.g = L.g;
     a.nblk = 2 * L.nb;
     a.kr = 0;
+    if (prec == P_F32 && mode == W_PLAIN && L.g.Mfma && a.nrhs >= 2) return launch_wilson_mfma(L, g5, a, st);
     const StencilShape sh = stencil_shape(L, prec, a.nrhs);
     if (sh.ts > 0) {
         // time-streaming form (FP64, FP32): blocks_per_tile blocks per RHS

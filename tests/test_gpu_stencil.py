@@ -301,6 +301,7 @@ def test_autotune_keeps_results(ovl, dims, nrhs):
     assert len(res["timings"]) > 3 and all(t > 0 for _, _, _, t in res["timings"])
     assert dims[0] % lat.tile_t == 0
     assert lat.rhs_tile in (1, 2, 4, 8) and (nrhs > 1 or lat.rhs_tile == 1)
+    assert lat.mfma in (0, 1) and (nrhs > 1 or lat.mfma == 0)
     assert lat.stream_t == 0 or dims[0] % lat.stream_t == 0
     assert lat.stream_t64 == 0 or dims[0] % lat.stream_t64 == 0
     psi = synth.gaussian_spinor(lat.V, 30, nrhs)
@@ -369,3 +370,59 @@ def test_rhs_tiles_match_oracle(ovl, dims, ts, tile, nrhs):
         got = out.to_canonical().cpu().numpy()
         for r in range(nrhs):
             check(prec, got[r], oracle.q2(olat, U, M0, psi[r], 0.23), psi[r], dims, shift=0.23)
+
+
+# The matrix-core FP32 stencil (lat.mfma): two sites and four RHS per wave,
+# used for FP32 D_W and Gamma_5 D_W on two or more RHS; a ragged last RHS tile
+# (nrhs not a multiple of 4) and both boundary-phase patterns.  FP64, FP16S and
+# single-RHS applies keep the vector form.
+MFMA_CASES = [((4, 4, 4, 4), 2, (-1, 1, 1, 1)), ((6, 4, 2, 4), 3, (1, -1, -1, -1)),
+              ((8, 4, 4, 6), 5, (-1, 1, -1, 1)), ((4, 6, 6, 8), 8, (-1, 1, 1, 1)),
+              ((8, 4, 24, 24), 12, (-1, 1, 1, 1))]
+
+
+@pytest.mark.parametrize("dims,nrhs,bc", MFMA_CASES)
+def test_mfma_stencil_matches_oracle(ovl, dims, nrhs, bc):
+    note(f"mfma stencil dims={dims} nrhs={nrhs} bc={bc}")
+    lat, olat, U, G = setup(ovl, dims, seed=43, n_stout=1, bc=bc)
+    lat.mfma = 1
+    psi = synth.gaussian_spinor(lat.V, 44, nrhs)
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), 1)
+    out = ovl.Spinor(lat, 1, nrhs)
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    got = out.to_canonical().cpu().numpy()
+    for r in range(nrhs):
+        check(1, got[r], oracle.dw(olat, U, M0, psi[r]), psi[r], dims)
+    ovl.q_apply(lat, G, M0, inp, out)
+    got = out.to_canonical().cpu().numpy()
+    for r in range(nrhs):
+        check(1, got[r], oracle.q(olat, U, M0, psi[r]), psi[r], dims)
+    ovl.q2_apply(lat, G, M0, 0.31, inp, out)
+    got = out.to_canonical().cpu().numpy()
+    for r in range(nrhs):
+        check(1, got[r], oracle.q2(olat, U, M0, psi[r], 0.31), psi[r], dims, shift=0.31)
+    # the vector form on the same input agrees to FP32 rounding
+    lat.mfma = 0
+    ref = ovl.Spinor(lat, 1, nrhs)
+    ovl.wilson_apply(lat, G, M0, inp, ref)
+    lat.mfma = 1
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    a, b = out.to_canonical().cpu().numpy(), ref.to_canonical().cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("prec,nrhs", [(0, 3), (2, 3), (1, 1)])
+def test_mfma_flag_other_forms(ovl, prec, nrhs):
+    """With lat.mfma set, FP64, FP16S and single-RHS applies still run the
+    vector stencil and match the oracle."""
+    dims = (6, 4, 2, 4)
+    note(f"mfma flag prec={prec} nrhs={nrhs}")
+    lat, olat, U, G = setup(ovl, dims, seed=45)
+    lat.mfma = 1
+    psi = synth.gaussian_spinor(lat.V, 46, nrhs)
+    inp = ovl.Spinor.from_canonical(lat, dev(psi), prec)
+    out = ovl.Spinor(lat, prec, nrhs)
+    ovl.wilson_apply(lat, G, M0, inp, out)
+    got = out.to_canonical().cpu().numpy()
+    for r in range(nrhs):
+        check(prec, got[r], oracle.dw(olat, U, M0, psi[r]), psi[r], dims)

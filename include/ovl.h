@@ -160,6 +160,21 @@ typedef struct {
     const double *weights;
 } ovl_zolo;
 
+/* Low modes of Q for deflation (Section 5.2, deflation of sign(Gamma_5 D_W)):
+ * the eigenvectors xi_i of Q = Gamma_5 D_W(m0) with the smallest |lambda_i|,
+ * orthonormal, as FP64 fields evecs.d (evecs.nrhs = k of them, field i at
+ * i * ovl_spinor_bytes, same layout as any spinor), and the eigenvalues
+ * lambda_i (host).  With it, sign(Q) chi = sum_i sign(lambda_i) (xi_i^H chi) xi_i
+ * + sign(Q) Pi chi, Pi = I - Xi Xi^H: the Zolotarev/multishift (or Lanczos)
+ * approximation acts on Pi chi only, so its lambda_min may be raised to the
+ * smallest |lambda| outside the deflated set.  Written by ovl_low_modes or by
+ * the caller; read-only to the solvers. */
+#define OVL_MAX_NEV 256
+typedef struct {
+    ovl_spinor evecs;        /* FP64, nrhs = k (1..OVL_MAX_NEV) */
+    const double *evals;     /* host, k eigenvalues of Q (signed) */
+} ovl_deflation;
+
 typedef struct {
     double tol;              /* target relative residual of every shifted system */
     int32_t maxiter;         /* cap on multishift CG iterations */
@@ -195,6 +210,11 @@ typedef struct {
                                 together); ovl_workspace_bytes sizes the
                                 workspace for one group.  Ignored by
                                 multishift_cg without weights */
+    const ovl_deflation *deflation; /* sign_q_apply, overlap_apply (and through
+                                them the outer solver): deflate these low
+                                modes of Q (NULL: none, the default).  The
+                                Zolotarev interval of the call should then
+                                start at the smallest |lambda| not deflated */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */
@@ -300,6 +320,58 @@ OVL_API int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, doub
                         double *lambda_min, double *lambda_max,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* Low modes of Q (for ovl_deflation): the nev eigenpairs of
+ * Q = Gamma_5 D_W(m0) smallest in |lambda|, in FP64.
+ * Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice) on a
+ * Chebyshev polynomial p(Q^2) of the given degree that is bounded by 1 on
+ * [theta_cut, theta_max] and grows steeply below theta_cut, so that the
+ * lowest eigenvalues of Q^2 become the best-separated largest ones of p.  A
+ * first plain Lanczos run on Q^2 (40 steps) gives theta_max and a first
+ * theta_cut; every check_every steps the nev + extra Ritz vectors of p with the
+ * largest |p| are resolved into eigenvectors of Q by Rayleigh-Ritz with Q on
+ * their span (Q^2's eigenvalues pair up as lambda^2 ~ (-lambda')^2, which
+ * only Q separates; H = Y^H Q Y diagonalised on the host by Hermitian Jacobi),
+ * and the nev with the smallest |Q x| are tested against tol.  After `steps`
+ * steps a stage restarts from the sum of the current vectors with theta_cut
+ * lowered to the (nev+extra)-th Rayleigh-Ritz value of Q^2 on their span (an
+ * upper bound of that eigenvalue), at most `stages` times.  evecs: FP64,
+ * nrhs = nev fields, written; evals[nev] (ascending |lambda|) and
+ * residuals[nev] = |Q xi_i - lambda_i xi_i| (|xi_i| = 1) written on the host.
+ * Returns OVL_OK when every residual is <= tol, OVL_NOT_CONVERGED when the
+ * stages ran out first (the best pairs are still returned), or an error.
+ * The start vector's random numbers are the caller's.  Synchronises the
+ * stream. */
+typedef struct {
+    int32_t nev;             /* number of low modes, 1..OVL_MAX_NEV (16) */
+    int32_t extra;           /* additional Rayleigh-Ritz vectors (0: nev/2 + 4) */
+    double tol;              /* residual target |Q xi - lambda xi| (1e-10) */
+    int32_t degree;          /* Chebyshev degree of the filter, 1..200 (40) */
+    int32_t steps;           /* Lanczos steps per stage (0: 2 (nev + extra) + 8) */
+    int32_t stages;          /* cap on filtered Lanczos stages, 1..64 (8) */
+    int32_t check_every;     /* steps between Rayleigh-Ritz tests (10) */
+} ovl_eig_params;
+
+typedef struct {
+    int32_t steps;           /* filtered Lanczos steps over all stages */
+    int32_t stages;          /* stages run */
+    int64_t q2_applies;      /* applications of Q^2 (two stencils each) */
+    int32_t converged;       /* 1 if every residual met tol */
+    int32_t reserved;
+    double max_residual;     /* max_i |Q xi_i - lambda_i xi_i| */
+    double lambda_next;      /* the smallest |lambda| of the Rayleigh-Ritz pairs
+                                not returned: an estimate of |lambda_{nev+1}|,
+                                not a bound (|evals[nev-1]| is a safe lower
+                                edge for the deflated Zolotarev interval) */
+    double theta_cut;        /* the filter's final lower edge */
+    double seconds;
+} ovl_eig_stats;
+
+OVL_API void ovl_default_eig_params(ovl_eig_params *prm);
+OVL_API size_t ovl_low_modes_workspace_bytes(const ovl_lattice *lat, const ovl_eig_params *prm);
+OVL_API int ovl_low_modes(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_spinor *start,
+                          const ovl_eig_params *prm, ovl_spinor *evecs, double *evals, double *residuals,
+                          ovl_eig_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* Multishift CG on (Q^2 + shifts[l]) x_l = b, l = 0..nshift-1, every RHS of b
  * independently.  If weights is NULL, x holds nshift*b->nrhs fields
  * (field index l*nrhs + r, FP64; this count may exceed OVL_MAX_RHS);
@@ -312,7 +384,9 @@ OVL_API int ovl_multishift_cg(const ovl_lattice *lat, const ovl_gauge *U, double
                       ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
 /* out = sign(Q) b ~ Q sum_l w_l (Q^2 + s_l)^{-1} b, Q = Gamma_5 D_W(m0).
- * b, out: FP64 spinors with equal nrhs.  Synchronises the stream. */
+ * b, out: FP64 spinors with equal nrhs.  With prm->deflation the low modes
+ * are projected out first and added back exactly (see ovl_deflation).
+ * Synchronises the stream. */
 OVL_API int ovl_sign_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_zolo *z,
                      const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
                      ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream);
@@ -320,7 +394,8 @@ OVL_API int ovl_sign_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double 
 /* out = D_ov b = rho (b + Gamma_5 sign(Q) b) = rho (b + D_W(-rho) y),
  * y = sum_l w_l (Q^2 + s_l)^{-1} b, Q = Gamma_5 D_W(-rho) (eq. (overlap_def),
  * massless normalisation).  b, out: FP64 spinors with equal nrhs; the final
- * combination and stencil are FP64 in every mode.  Synchronises the stream. */
+ * combination and stencil are FP64 in every mode.  With prm->deflation,
+ * sign(Q) b is formed as for ovl_sign_q_apply.  Synchronises the stream. */
 OVL_API int ovl_overlap_apply(const ovl_lattice *lat, const ovl_gauge *U, double rho, const ovl_zolo *z,
                       const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
                       ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream);
@@ -413,7 +488,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
  * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 1e-5,
- * block_f64 0, rhs_group 0. */
+ * block_f64 0, rhs_group 0, deflation NULL. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 /* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on

@@ -56,10 +56,26 @@ class ovl_zolo(ctypes.Structure):
     _fields_ = [("npoles", c_i32), ("shifts", ctypes.POINTER(c_dbl)), ("weights", ctypes.POINTER(c_dbl))]
 
 
+class ovl_deflation(ctypes.Structure):
+    _fields_ = [("evecs", ovl_spinor), ("evals", ctypes.POINTER(c_dbl))]
+
+
 class ovl_solver_params(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("maxiter", c_i32), ("mode", c_i32), ("reliable_delta", c_dbl),
                 ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32), ("profile", c_i32),
-                ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32), ("rhs_group", c_i32)]
+                ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32), ("rhs_group", c_i32),
+                ("deflation", ctypes.POINTER(ovl_deflation))]
+
+
+class ovl_eig_params(ctypes.Structure):
+    _fields_ = [("nev", c_i32), ("extra", c_i32), ("tol", c_dbl), ("degree", c_i32), ("steps", c_i32),
+                ("stages", c_i32), ("check_every", c_i32)]
+
+
+class ovl_eig_stats(ctypes.Structure):
+    _fields_ = [("steps", c_i32), ("stages", c_i32), ("q2_applies", ctypes.c_int64), ("converged", c_i32),
+                ("reserved", c_i32), ("max_residual", c_dbl), ("lambda_next", c_dbl), ("theta_cut", c_dbl),
+                ("seconds", c_dbl)]
 
 
 class ovl_solver_stats(ctypes.Structure):
@@ -136,6 +152,10 @@ _sig = {
                                   P(ovl_outer_params), P(ovl_outer_stats), c_vp, ctypes.c_size_t, c_vp]),
     "ovl_wilson_solve": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, P(ovl_spinor), P(ovl_spinor),
                                  P(ovl_solver_params), P(ovl_solver_stats), c_vp, ctypes.c_size_t, c_vp]),
+    "ovl_default_eig_params": (None, [P(ovl_eig_params)]),
+    "ovl_low_modes_workspace_bytes": (ctypes.c_size_t, [P(ovl_lattice), P(ovl_eig_params)]),
+    "ovl_low_modes": (c_i32, [P(ovl_lattice), P(ovl_gauge), c_dbl, P(ovl_spinor), P(ovl_eig_params),
+                              P(ovl_spinor), P(c_dbl), P(c_dbl), P(ovl_eig_stats), c_vp, ctypes.c_size_t, c_vp]),
     "ovl_status_string": (ctypes.c_char_p, [c_i32]),
     "ovl_last_hip_error": (c_i32, []),
     "ovl_version": (ctypes.c_char_p, []),
@@ -307,11 +327,45 @@ class Gauge:
 
 
 def default_params(**kw) -> ovl_solver_params:
+    """ovl_default_params, then keyword overrides; deflation=Deflation(...)
+    points the parameters at its low modes (the Deflation object is kept
+    alive by the returned structure)."""
     p = ovl_solver_params()
     _lib.ovl_default_params(ctypes.byref(p))
     for k, v in kw.items():
-        setattr(p, k, v)
+        if k == "deflation":
+            set_deflation(p, v)
+        else:
+            setattr(p, k, v)
     return p
+
+
+class Deflation:
+    """Low modes of Q for deflated sign/overlap applies: eigenvectors evecs
+    (an FP64 Spinor with nrhs = k) and eigenvalues evals (float64, k)."""
+
+    def __init__(self, evecs: "Spinor", evals, residuals=None, stats=None):
+        assert evecs.prec == F64 and len(evals) == evecs.nrhs
+        self.evecs = evecs
+        self.evals = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+        self.residuals = residuals
+        self.stats = stats
+        self.c = ovl_deflation(evecs.c, self.evals.ctypes.data_as(ctypes.POINTER(c_dbl)))
+
+    @property
+    def nev(self) -> int:
+        return self.evecs.nrhs
+
+
+def set_deflation(params: ovl_solver_params, defl):
+    """Point params (an ovl_solver_params, e.g. outer params' .inner) at a
+    Deflation, or clear it with None."""
+    if defl is None:
+        params.deflation = ctypes.POINTER(ovl_deflation)()
+        params._defl = None
+    else:
+        params.deflation = ctypes.pointer(defl.c)
+        params._defl = defl
 
 
 # ---------------------------------------------------------------- C ABI
@@ -402,6 +456,33 @@ def spectral_bounds(lat: Lattice, U: Gauge, m0: float, iters: int, start: Spinor
     return lo.value, hi.value
 
 
+def low_modes(lat: Lattice, U: Gauge, m0: float, start: Spinor, nev: int = 16, ws=None, stream=None,
+              allow_not_converged=False, **kw) -> Deflation:
+    """ovl_low_modes: the nev eigenpairs of Q = Gamma_5 D_W(m0) smallest in
+    |lambda|, as a Deflation (evals ascending in |lambda|, residuals
+    |Q xi - lambda xi|, stats).  Keywords override ovl_eig_params fields
+    (extra, tol, degree, steps, stages, check_every)."""
+    p = ovl_eig_params()
+    _lib.ovl_default_eig_params(ctypes.byref(p))
+    p.nev = int(nev)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    if ws is None:
+        nbytes = int(_lib.ovl_low_modes_workspace_bytes(lat.ref, ctypes.byref(p)))
+        if nbytes == 0:
+            raise OvlError(ERR_INVALID, "ovl_low_modes_workspace_bytes")
+        ws = _dev_buffer(nbytes, start.data.device)
+    evecs = Spinor(lat, F64, int(nev), start.data.device)
+    evals = np.zeros(int(nev))
+    res = np.zeros(int(nev))
+    st = ovl_eig_stats()
+    rc = _lib.ovl_low_modes(lat.ref, U.ref, float(m0), start.ref, ctypes.byref(p), evecs.ref,
+                            evals.ctypes.data_as(P(c_dbl)), res.ctypes.data_as(P(c_dbl)), ctypes.byref(st),
+                            c_vp(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "ovl_low_modes", allow_not_converged)
+    return Deflation(evecs, evals, res, {k: getattr(st, k) for k, _ in st._fields_})
+
+
 def _dvec(a):
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
     return a, a.ctypes.data_as(P(c_dbl))
@@ -462,7 +543,11 @@ def default_outer_params(**kw) -> ovl_outer_params:
     for k, v in kw.items():
         if k == "inner":
             for ik, iv in v.items():
-                setattr(p.inner, ik, iv)
+                if ik == "deflation":
+                    set_deflation(p.inner, iv)
+                    p._defl = iv
+                else:
+                    setattr(p.inner, ik, iv)
         else:
             setattr(p, k, v)
     return p

@@ -2,7 +2,9 @@
 // the stream-ordered launches.  Nothing here throws; every failure is a status.
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
+#include <vector>
 
 #include "mscg.h"
 
@@ -32,12 +34,19 @@ size_t wilson_solve_ws_bytes(const Lat &L, int nrhs, int m);
 size_t lanczos_sign_ws_bytes(const Lat &L, int nrhs);
 int lanczos_sign(const Lat &L, const void *U64, double m0, Fld b, Fld y, double tol, int maxiter, int *iters,
                  char *ws, size_t ws_bytes, hipStream_t st);
-__global__ void k_gamma5(Geom g, int nb, const double2 *in, double2 *out);
 int wilson_solve(const Lat &L, const ovl_gauge *U, double m0, Fld b, Fld x, double tol, int maxiter, int m,
                  double *true_res, int *iters, char *ws, size_t ws_bytes, hipStream_t st);
 size_t outer_ws_bytes(const Lat &L, int npoles, const ovl_outer_params *p, const ovl_lattice *lat);
 int overlap_solve(const ovl_lattice *lat, const ovl_gauge *U, double rho, const ovl_zolo *z, Fld eta, Fld psi,
                   const ovl_outer_params *prm, ovl_outer_stats *stats, char *ws, size_t ws_bytes, hipStream_t st);
+size_t low_modes_ws_bytes(const Lat &L, const ovl_eig_params *p);
+int low_modes(const Lat &L, const void *U64, double m0, Fld start, const ovl_eig_params *p, Fld evecs, double *evals,
+              double *resid, ovl_eig_stats *S, char *ws, size_t ws_bytes, hipStream_t st);
+size_t deflation_ws_bytes(const Lat &L, int nrhs, int k);
+int deflate_project(const Lat &L, const ovl_deflation *D, Fld b, Fld proj, std::vector<std::complex<double>> &cr,
+                    char *ws, hipStream_t st);
+int deflate_restore(const Lat &L, const ovl_deflation *D, const std::vector<std::complex<double>> &cr, double rho,
+                    bool overlap, Fld out, char *ws, hipStream_t st);
 }  // namespace ovl
 
 using namespace ovl;
@@ -94,6 +103,22 @@ bool params_ok(const ovl_solver_params *p)
            p->reliable_delta > 0.0 &&
            p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
            p->sloppy_below < 1.0 && p->rhs_group >= 0;
+}
+
+bool defl_ok(const ovl_deflation *D)
+{
+    if (!D || !D->evals || !spinor_ok(&D->evecs, OVL_MAX_NEV) || D->evecs.prec != OVL_F64) return false;
+    for (int i = 0; i < D->evecs.nrhs; i++)
+        if (!std::isfinite(D->evals[i])) return false;
+    return true;
+}
+
+bool eig_ok(const ovl_eig_params *p)
+{
+    return p && p->nev >= 1 && p->nev <= OVL_MAX_NEV && p->extra >= 0 && p->nev + p->extra <= 2 * OVL_MAX_NEV &&
+           p->tol > 0.0 && std::isfinite(p->tol) && p->degree >= 1 && p->degree <= 200 && p->steps >= 0 &&
+           p->steps <= 4096 && (p->steps == 0 || p->steps >= p->nev + (p->extra > 0 ? p->extra : p->nev / 2 + 4)) &&
+           p->stages >= 1 && p->stages <= 64 && p->check_every >= 1;
 }
 
 bool zolo_ok(const ovl_zolo *z)
@@ -324,8 +349,15 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
     }
     if (op == OVL_OP_MSCG) {
         if (nshift < 1 || nshift > OVL_MAX_SHIFTS || (prm && !params_ok(prm))) return 0;
+        // deflation (sign_q_apply, overlap_apply): projected sources of every
+        // RHS in front of the solver's own workspace
+        size_t yb = 0;
+        if (prm && prm->deflation) {
+            if (!defl_ok(prm->deflation)) return 0;
+            yb = align256(deflation_ws_bytes(L, nrhs, prm->deflation->evecs.nrhs));
+        }
         if (prm && prm->rhs_group > 0) nrhs = std::min(nrhs, (int32_t)prm->rhs_group);   // one group
-        size_t yb = (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
+        yb += (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_LANCZOS) return yb + lanczos_sign_ws_bytes(L, nrhs);
         if (prm && prm->mode == OVL_SOLVE_MIXED)
             return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0);
@@ -350,6 +382,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->sloppy_below = 1e-5;
     p->block_f64 = 0;
     p->rhs_group = 0;
+    p->deflation = nullptr;
 }
 
 int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
@@ -477,9 +510,10 @@ int ovl_multishift_cg(const ovl_lattice *lat, const ovl_gauge *U, double m0, int
     return rc_all;
 }
 
-static int sign_or_overlap(const ovl_lattice *lat, const ovl_gauge *U, double m0, double rho, const ovl_zolo *z,
-                           const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
-                           ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream, bool overlap)
+static int sign_or_overlap_core(const ovl_lattice *lat, const ovl_gauge *U, double m0, double rho,
+                                const ovl_zolo *z, const ovl_spinor *b, ovl_spinor *out,
+                                const ovl_solver_params *prm, ovl_solver_stats *stats, void *ws, size_t ws_bytes,
+                                void *stream, bool overlap)
 {
     double t0 = now();
     clear_stats(stats);
@@ -551,6 +585,42 @@ static int sign_or_overlap(const ovl_lattice *lat, const ovl_gauge *U, double m0
     OVL_HIP(hipStreamSynchronize(S(stream)));
     if (stats) stats->seconds = now() - t0;
     return rc_all;
+}
+
+// With deflation: project the low modes out of b, run the approximation on
+// Pi b in the rest of the workspace, then add the modes back exactly
+static int sign_or_overlap(const ovl_lattice *lat, const ovl_gauge *U, double m0, double rho, const ovl_zolo *z,
+                           const ovl_spinor *b, ovl_spinor *out, const ovl_solver_params *prm,
+                           ovl_solver_stats *stats, void *ws, size_t ws_bytes, void *stream, bool overlap)
+{
+    const ovl_deflation *D = prm ? prm->deflation : nullptr;
+    if (!D) return sign_or_overlap_core(lat, U, m0, rho, z, b, out, prm, stats, ws, ws_bytes, stream, overlap);
+    const double t0 = now();
+    clear_stats(stats);
+    if (!lat_ok(lat) || !spinor_ok(b) || !spinor_ok(out) || !params_ok(prm) || !defl_ok(D) || !zolo_ok(z) || !U ||
+        !U->f64 || !ws)
+        return OVL_ERR_INVALID;
+    if (b->prec != OVL_F64 || out->prec != OVL_F64 || b->nrhs != out->nrhs || b->d == out->d) return OVL_ERR_INVALID;
+    if (D->evecs.d == b->d || D->evecs.d == out->d) return OVL_ERR_INVALID;
+    const int R = b->nrhs;
+    if (ws_bytes < ovl_workspace_bytes(lat, OVL_OP_MSCG, OVL_F64, R, z->npoles, prm)) return OVL_ERR_WORKSPACE;
+    const Lat L = make_lat(lat);
+    const size_t db = align256(deflation_ws_bytes(L, R, D->evecs.nrhs));
+    std::vector<std::complex<double>> cr;
+    Fld proj{ws, nullptr, P_F64, R};
+    int e = deflate_project(L, D, fld(b), proj, cr, (char *)ws, S(stream));
+    if (e) return e;
+    ovl_solver_params p2 = *prm;
+    p2.deflation = nullptr;
+    ovl_spinor pb{proj.d, nullptr, OVL_F64, R};
+    const int rc = sign_or_overlap_core(lat, U, m0, rho, z, &pb, out, &p2, stats, (char *)ws + db, ws_bytes - db,
+                                        stream, overlap);
+    if (rc < 0) return rc;
+    e = deflate_restore(L, D, cr, rho, overlap, fld(out), (char *)ws, S(stream));
+    if (e) return e;
+    OVL_HIP(hipStreamSynchronize(S(stream)));
+    if (stats) stats->seconds = now() - t0;
+    return rc;
 }
 
 int ovl_sign_q_apply(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_zolo *z, const ovl_spinor *b,
@@ -644,6 +714,41 @@ int ovl_wilson_solve(const ovl_lattice *lat, const ovl_gauge *U, double m0, cons
         stats->seconds = now() - t0;
     }
     return rc;
+}
+
+void ovl_default_eig_params(ovl_eig_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->nev = 16;
+    p->extra = 0;
+    p->tol = 1e-10;
+    p->degree = 40;
+    p->steps = 0;
+    p->stages = 8;
+    p->check_every = 10;
+}
+
+size_t ovl_low_modes_workspace_bytes(const ovl_lattice *lat, const ovl_eig_params *prm)
+{
+    if (!lat_ok(lat) || !eig_ok(prm)) return 0;
+    return low_modes_ws_bytes(make_lat(lat), prm);
+}
+
+int ovl_low_modes(const ovl_lattice *lat, const ovl_gauge *U, double m0, const ovl_spinor *start,
+                  const ovl_eig_params *prm, ovl_spinor *evecs, double *evals, double *residuals,
+                  ovl_eig_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (!lat_ok(lat) || !eig_ok(prm) || !U || !U->f64 || !ws || !evals || !residuals || !std::isfinite(m0))
+        return OVL_ERR_INVALID;
+    if (!spinor_ok(start) || start->prec != OVL_F64 || start->nrhs != 1) return OVL_ERR_INVALID;
+    if (!spinor_ok(evecs, OVL_MAX_NEV) || evecs->prec != OVL_F64 || evecs->nrhs != prm->nev ||
+        evecs->d == start->d)
+        return OVL_ERR_INVALID;
+    if (ws_bytes < ovl_low_modes_workspace_bytes(lat, prm)) return OVL_ERR_WORKSPACE;
+    return low_modes(make_lat(lat), U->f64, m0, fld(start), prm, fld(evecs), evals, residuals, stats, (char *)ws,
+                     ws_bytes, S(stream));
 }
 
 const char *ovl_status_string(int s)

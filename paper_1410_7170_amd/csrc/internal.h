@@ -78,6 +78,13 @@ hipError_t launch_reduce(const double *partials, int nq, int nrhs, int nblk, dou
 hipError_t launch_convert(const Lat &L, Fld src, Fld dst, hipStream_t st);
 hipError_t launch_axpby(const Lat &L, double a, Fld x, double b, Fld y, hipStream_t st);
 hipError_t launch_zero(const Lat &L, Fld f, hipStream_t st);
+// FP64 field-set kernels (outer.hip), grids of site_blocks(L) blocks:
+// partials[2][nv][nblk] of <V_f, w> for the nv fields V_f (grid.y = nv);
+// w += sgn sum_f (coef[f] + i coef[nv+f]) V_f (coef on the device);
+// out = Gamma_5 in per field (grid.y = fields; in place allowed)
+__global__ void k_mdot(Geom g, int nb, int nv, const double2 *V, const double2 *w, double *partials);
+__global__ void k_mcaxpy(Geom g, int nb, int nv, const double *coef, double sgn, const double2 *V, double2 *w);
+__global__ void k_gamma5(Geom g, int nb, const double2 *in, double2 *out);
 
 int elems_per_field(int prec, int Vh);   // flat vector elements of one RHS
 int site_blocks(const Lat &L);           // blocks of a flat elementwise launch over one field

@@ -10,13 +10,17 @@
 namespace ovl {
 
 // d[0..n-1] diagonal, e[0..n-2] off-diagonal (destroyed).  On return d holds
-// the eigenvalues and Z (n x n, row-major, Z[i*n + j] = component i of
-// eigenvector j) the orthonormal eigenvectors.  Returns false if an
-// eigenvalue fails to converge in 60 sweeps.
-inline bool tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, std::vector<double> &Z)
+// the eigenvalues and Z (nrow x n, row-major, Z[r*n + j] = component row0 + r
+// of eigenvector j) the requested rows of the orthonormal eigenvectors: all
+// of them by default, or e.g. only the last (nrow 1, row0 n-1), which costs
+// O(n^2) instead of O(n^3).  Returns false if an eigenvalue fails to
+// converge in 60 sweeps.
+inline bool tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, std::vector<double> &Z, int nrow = -1,
+                        int row0 = 0)
 {
-    Z.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; i++) Z[(size_t)i * n + i] = 1.0;
+    if (nrow < 0) nrow = n, row0 = 0;
+    Z.assign((size_t)nrow * n, 0.0);
+    for (int r = 0; r < nrow; r++) Z[(size_t)r * n + row0 + r] = 1.0;
     if (n == 1) return true;
     e.resize(n);
     e[n - 1] = 0.0;
@@ -56,7 +60,7 @@ inline bool tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, st
                 d[i + 1] = g + p;
                 g = c * r - b;
                 // the rotation acts on eigenvector columns i and i+1
-                for (int k = 0; k < n; k++) {
+                for (int k = 0; k < nrow; k++) {
                     const double zi = Z[(size_t)k * n + i], zi1 = Z[(size_t)k * n + i + 1];
                     Z[(size_t)k * n + i + 1] = s * zi + c * zi1;
                     Z[(size_t)k * n + i] = c * zi - s * zi1;

@@ -20,6 +20,7 @@ def lib(tmp_path_factory):
     P = ctypes.c_void_p
     lib.tri_eig.argtypes = [ctypes.c_int, P, P, P, P]
     lib.tri_sign_e1.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P]
+    lib.herm_eig.argtypes = [ctypes.c_int, P, P, P]
     return lib
 
 
@@ -56,3 +57,31 @@ def test_tridiag_sign_e1_matches_lapack(lib):
     th, Z = np.linalg.eigh(T)
     ref = 2.5 * (Z @ (np.sign(th) * Z[0]))
     assert np.allclose(c, ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,seed,degenerate", [(1, 0, False), (2, 1, False), (7, 2, False), (40, 3, False),
+                                               (40, 4, True), (128, 5, False)])
+def test_hermitian_jacobi_matches_lapack(lib, n, seed, degenerate):
+    """The Rayleigh-Ritz step's Hermitian Jacobi solver: eigenvalues as LAPACK,
+    A V = V diag(w) and V unitary, also with a spectrum of +-lambda pairs
+    (the degeneracy of Q^2 that the step resolves)."""
+    rng = np.random.default_rng(seed)
+    if degenerate:
+        Qm, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+        lam = np.repeat(rng.uniform(0.5, 2.0, n // 2), 2) * np.tile([1.0, -1.0], n // 2)
+        lam[:4] = [0.7, 0.7, -0.7, 1e-3]
+        A = (Qm * lam) @ Qm.conj().T
+    else:
+        X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        A = X + X.conj().T
+    A = 0.5 * (A + A.conj().T)
+    a = np.ascontiguousarray(A).view(np.float64).copy()
+    w = np.empty(n)
+    v = np.empty(2 * n * n)
+    assert lib.herm_eig(n, ptr(a), ptr(w), ptr(v)) == 0
+    V = v.view(np.complex128).reshape(n, n)
+    ref = np.linalg.eigvalsh(A)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.allclose(np.sort(w), ref, atol=1e-12 * scale)
+    assert np.abs(A @ V - V * w).max() < 1e-11 * scale
+    assert np.abs(V.conj().T @ V - np.eye(n)).max() < 1e-12

@@ -473,3 +473,62 @@ def test_lanczos_sign_converges_to_exact_sign(lat44, U44, dense44):
     # a 2x2 diagonal check: sign of diag(3, -2) applied to (1, 1)
     x, n = krylov.lanczos_sign(lambda v: np.array([3.0, -2.0]) * v, np.array([1.0 + 0j, 1.0]), 5)
     assert n == 2 and np.allclose(x, [1.0, -1.0], atol=1e-14)
+
+
+# ---------------------------------------------------------------- deflation (Section 5.2)
+@pytest.fixture(scope="module")
+def modes44(lat44, U44):
+    from oracle import deflation
+    return deflation.low_modes_dense(lat44, U44, M0, 16)
+
+
+def test_low_modes_dense_are_the_smallest_eigenpairs(lat44, U44, dense44, modes44):
+    """The k = 16 pairs are eigenpairs of the stencil's Q (residual through
+    oracle.q), orthonormal, and carry the 16 smallest moduli of the spectrum;
+    the smallest modulus squared is the oracle Lanczos's lowest Ritz value of
+    Q^2 (an independent routine)."""
+    lam, xi, wsorted = modes44
+    assert np.allclose(np.abs(lam), np.sort(np.abs(dense44["w"]))[:16], rtol=0, atol=1e-12)
+    assert np.all(np.diff(np.abs(lam)) >= -1e-14)
+    G = np.array([[np.vdot(a, b) for b in xi] for a in xi])
+    assert np.abs(G - np.eye(16)).max() < 1e-12
+    for l, x in zip(lam, xi):
+        assert np.linalg.norm(oracle.q(lat44, U44, M0, x) - l * x) < 1e-11
+    v0 = synth.gaussian_spinor(lat44.V, 101)[0]
+    t0, _ = oracle.lanczos_q2(lat44, U44, M0, v0, 300)
+    assert abs(np.sqrt(t0) - abs(lam[0])) < 1e-6 * abs(lam[0])
+
+
+def test_deflated_sign_with_exact_sign_is_exact(lat44, U44, dense44, modes44):
+    """With the exact sign(Q) for the remainder, the deflation formula gives
+    sign(Q) chi itself: sign(Q) xi_i = sign(lambda_i) xi_i, so any dropped or
+    doubled term (no projector, wrong sign of a mode, xi^H chi vs chi^H xi)
+    shows.  D_ov with the deflated sign is the dense overlap matrix."""
+    from oracle import deflation
+    lam, xi, _ = modes44
+    S = dense44["S"]
+    exact_sign = lambda v: (S @ v.reshape(-1)).reshape(v.shape)
+    chi = synth.gaussian_spinor(lat44.V, 211)[0]
+    got = deflation.deflated_sign(exact_sign, xi, lam, chi)
+    assert rel(got, exact_sign(chi)) < 1e-13
+    Dov = RHO * (np.eye(3072) + dense44["G5"] @ S)
+    got = deflation.deflated_overlap(exact_sign, xi, lam, chi, RHO)
+    assert rel(got, (Dov @ chi.reshape(-1)).reshape(chi.shape)) < 1e-13
+
+
+def test_deflated_zolotarev_meets_the_deflated_bound(lat44, U44, dense44, modes44):
+    """Zolotarev + multishift CG built on [|lambda_17|, lambda_max] only: with
+    the 16 modes deflated the sign(Q) chi error stays within the rational
+    bound delta of that interval; without deflation the same approximation
+    misses the low modes by far more."""
+    from oracle import deflation
+    lam, xi, wsorted = modes44
+    lo, hi = 0.999 * abs(wsorted[16]), 1.001 * abs(wsorted[-1])
+    s, wt, delta = oracle.zolotarev(lo, hi, 8)
+    apply = lambda v: oracle.sign_q(lat44, U44, M0, s, wt, v, 1e-13, 5000)[0]
+    chi = synth.gaussian_spinor(lat44.V, 212)[0]
+    exact = (dense44["S"] @ chi.reshape(-1)).reshape(chi.shape)
+    err_defl = rel(deflation.deflated_sign(apply, xi, lam, chi), exact)
+    err_plain = rel(apply(chi), exact)
+    assert err_defl <= 1.05 * delta + 1e-12
+    assert err_plain > 10 * err_defl

@@ -322,38 +322,41 @@ OVL_API int ovl_spectral_bounds(const ovl_lattice *lat, const ovl_gauge *U, doub
 
 /* Low modes of Q (for ovl_deflation): the nev eigenpairs of
  * Q = Gamma_5 D_W(m0) smallest in |lambda|, in FP64.
- * Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice) on a
- * Chebyshev polynomial p(Q^2) of the given degree that is bounded by 1 on
- * [theta_cut, theta_max] and grows steeply below theta_cut, so that the
- * lowest eigenvalues of Q^2 become the best-separated largest ones of p.  A
- * first plain Lanczos run on Q^2 (40 steps) gives theta_max and a first
- * theta_cut; every check_every steps the nev + extra Ritz vectors of p with the
- * largest |p| are resolved into eigenvectors of Q by Rayleigh-Ritz with Q on
- * their span (Q^2's eigenvalues pair up as lambda^2 ~ (-lambda')^2, which
- * only Q separates; H = Y^H Q Y diagonalised on the host by Hermitian Jacobi),
- * and the nev with the smallest |Q x| are tested against tol.  After `steps`
- * steps a stage restarts from the sum of the current vectors with theta_cut
- * lowered to the (nev+extra)-th Rayleigh-Ritz value of Q^2 on their span (an
- * upper bound of that eigenvalue), at most `stages` times.  evecs: FP64,
- * nrhs = nev fields, written; evals[nev] (ascending |lambda|) and
- * residuals[nev] = |Q xi_i - lambda_i xi_i| (|xi_i| = 1) written on the host.
- * Returns OVL_OK when every residual is <= tol, OVL_NOT_CONVERGED when the
- * stages ran out first (the best pairs are still returned), or an error.
- * The start vector's random numbers are the caller's.  Synchronises the
- * stream. */
+ * A Lanczos run on Q^2 (`steps` steps, full reorthogonalisation by classical
+ * Gram-Schmidt twice) from the FP64 device spinor `start` gives the top of the
+ * spectrum theta_max and a block of nev + extra Ritz vectors.  Then
+ * Chebyshev-filtered subspace iteration: the block is multiplied by
+ * T_degree(a Q^2 + b), which is bounded by 1 on [theta_cut, theta_max] and
+ * grows steeply below theta_cut, orthonormalised, and resolved into
+ * eigenvectors of Q by Rayleigh-Ritz with Q on its span (Q^2 pairs
+ * lambda^2 ~ (-lambda')^2, which only Q separates; H = Y^H Q Y diagonalised on
+ * the host by Hermitian Jacobi).  The nev pairs with the smallest |Q x| are
+ * tested against tol; theta_cut moves down to the block's largest Rayleigh-Ritz
+ * value of Q^2 (an upper bound of that eigenvalue) times 1.05, at most
+ * `stages` iterations; each iteration's degree is capped so that the filter's
+ * gain at the lowest Rayleigh-Ritz value stays below 1e5, which keeps the
+ * block's weaker directions above the rounding of its dominant ones.  The
+ * filter runs on the whole block per stencil launch
+ * (nrhs = nev + extra).  evecs: FP64, nrhs = nev fields, written; evals[nev]
+ * (ascending |lambda|) and residuals[nev] = |Q xi_i - lambda_i xi_i|
+ * (|xi_i| = 1) written on the host.  Returns OVL_OK when every residual is
+ * <= tol, OVL_NOT_CONVERGED when the iterations ran out first (the best pairs
+ * are still returned), or an error.  The start vector's random numbers are the
+ * caller's.  Synchronises the stream. */
 typedef struct {
     int32_t nev;             /* number of low modes, 1..OVL_MAX_NEV (16) */
-    int32_t extra;           /* additional Rayleigh-Ritz vectors (0: nev/2 + 4) */
+    int32_t extra;           /* block size beyond nev (0: nev/2 + 4) */
     double tol;              /* residual target |Q xi - lambda xi| (1e-10) */
-    int32_t degree;          /* Chebyshev degree of the filter, 1..200 (40) */
-    int32_t steps;           /* Lanczos steps per stage (0: 2 (nev + extra) + 8) */
-    int32_t stages;          /* cap on filtered Lanczos stages, 1..64 (8) */
-    int32_t check_every;     /* steps between Rayleigh-Ritz tests (10) */
+    int32_t degree;          /* Chebyshev degree of the filter, 1..200 (60) */
+    int32_t steps;           /* steps of the seeding Lanczos run, >= nev + extra
+                                (0: max(40, nev + extra + 8)) */
+    int32_t stages;          /* cap on filtered subspace iterations, 1..200 (40) */
+    int32_t check_every;     /* reserved (0) */
 } ovl_eig_params;
 
 typedef struct {
-    int32_t steps;           /* filtered Lanczos steps over all stages */
-    int32_t stages;          /* stages run */
+    int32_t steps;           /* steps of the seeding Lanczos run */
+    int32_t stages;          /* filtered subspace iterations run */
     int64_t q2_applies;      /* applications of Q^2 (two stencils each) */
     int32_t converged;       /* 1 if every residual met tol */
     int32_t reserved;
@@ -363,6 +366,7 @@ typedef struct {
                                 not a bound (|evals[nev-1]| is a safe lower
                                 edge for the deflated Zolotarev interval) */
     double theta_cut;        /* the filter's final lower edge */
+    double mean_degree;      /* mean filter degree over the iterations */
     double seconds;
 } ovl_eig_stats;
 

@@ -75,7 +75,7 @@ class ovl_eig_params(ctypes.Structure):
 class ovl_eig_stats(ctypes.Structure):
     _fields_ = [("steps", c_i32), ("stages", c_i32), ("q2_applies", ctypes.c_int64), ("converged", c_i32),
                 ("reserved", c_i32), ("max_residual", c_dbl), ("lambda_next", c_dbl), ("theta_cut", c_dbl),
-                ("seconds", c_dbl)]
+                ("mean_degree", c_dbl), ("seconds", c_dbl)]
 
 
 class ovl_solver_stats(ctypes.Structure):

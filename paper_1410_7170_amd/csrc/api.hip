@@ -118,7 +118,7 @@ bool eig_ok(const ovl_eig_params *p)
     return p && p->nev >= 1 && p->nev <= OVL_MAX_NEV && p->extra >= 0 && p->nev + p->extra <= 2 * OVL_MAX_NEV &&
            p->tol > 0.0 && std::isfinite(p->tol) && p->degree >= 1 && p->degree <= 200 && p->steps >= 0 &&
            p->steps <= 4096 && (p->steps == 0 || p->steps >= p->nev + (p->extra > 0 ? p->extra : p->nev / 2 + 4)) &&
-           p->stages >= 1 && p->stages <= 64 && p->check_every >= 1;
+           p->stages >= 1 && p->stages <= 200 && p->check_every >= 0;
 }
 
 bool zolo_ok(const ovl_zolo *z)
@@ -723,10 +723,10 @@ void ovl_default_eig_params(ovl_eig_params *p)
     p->nev = 16;
     p->extra = 0;
     p->tol = 1e-10;
-    p->degree = 40;
+    p->degree = 60;
     p->steps = 0;
-    p->stages = 8;
-    p->check_every = 10;
+    p->stages = 40;
+    p->check_every = 0;
 }
 
 size_t ovl_low_modes_workspace_bytes(const ovl_lattice *lat, const ovl_eig_params *prm)

@@ -7,22 +7,20 @@
 // approximation, whose lower spectral bound rises from |lambda_1| to the
 // smallest |lambda| outside the deflated set.
 //
-// The eigenpairs come from ovl_low_modes: Lanczos with full
-// reorthogonalisation on a Chebyshev filter p(Q^2) that maps the lowest
-// eigenvalues of Q^2 to the largest, best-separated eigenvalues of p (plain
-// Lanczos on Q^2 converges slowly there: the low end is dense and, through
-// the near pairing lambda ~ -lambda', nearly degenerate in Q^2), then
-// Rayleigh-Ritz with Q itself on the span of the leading Ritz vectors, which
-// separates the +-lambda pairs.  A stage that has not converged restarts from
-// the sum of its vectors with the filter's lower edge moved down to an upper
-// bound of the (nev+extra)-th eigenvalue of Q^2.  Memory: steps + 1 basis
-// fields plus 3 (nev + extra) + 5 work fields, FP64.
+// The eigenpairs come from ovl_low_modes: a Lanczos run on Q^2 seeds a block
+// of nev + extra vectors and the interval of a Chebyshev filter p(Q^2) that
+// stays within [-1, 1] above a lower edge theta_cut and grows steeply below
+// it; then subspace iteration with that filter (X <- p(Q^2) X, orthonormalised)
+// and Rayleigh-Ritz with Q itself on span X, which separates the +-lambda
+// pairs that are nearly degenerate in Q^2.  Plain Lanczos on Q^2 converges
+// slowly here: its low end is dense.  The edge moves down every iteration to
+// an upper bound of the block's last eigenvalue of Q^2.  Memory: steps + 1
+// basis fields plus 5 (nev + extra) + 1 work fields, FP64.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
-#include <functional>
 #include <numeric>
 #include <vector>
 
@@ -123,7 +121,7 @@ bool tridiag_sorted(int n, const std::vector<double> &alpha, const std::vector<d
 namespace {
 
 struct EigDims {
-    int k, kp, m;   // wanted, Rayleigh-Ritz space, Lanczos steps per stage
+    int k, kp, m;   // wanted, block size, steps of the seeding Lanczos run
 };
 
 EigDims eig_dims(const ovl_eig_params *p)
@@ -131,8 +129,7 @@ EigDims eig_dims(const ovl_eig_params *p)
     EigDims d;
     d.k = p->nev;
     d.kp = p->nev + (p->extra > 0 ? p->extra : p->nev / 2 + 4);
-    d.m = p->steps > 0 ? p->steps : 2 * d.kp + 8;
-    d.m = std::max(d.m, std::max(d.kp, 40));
+    d.m = p->steps > 0 ? p->steps : std::max(40, d.kp + 8);
     return d;
 }
 
@@ -144,16 +141,20 @@ size_t low_modes_ws_bytes(const Lat &L, const ovl_eig_params *p)
     WsCarve c{nullptr, 0, 0};
     const size_t F = field_bytes(P_F64, L.V);
     const int nv = std::max(d.m + 1, 2 * d.kp);
-    c.take(F * (d.m + 1));                                   // Lanczos basis
-    c.take(F * 2 * d.kp);                                    // Y, then Q Y
-    c.take(F * d.kp);                                        // X = Y C
-    c.take(F * 5);                                           // w, Q v, Chebyshev recurrence (3)
+    c.take(F * (d.m + 1));                                   // Lanczos basis of the seeding run
+    c.take(F * 2 * d.kp);                                    // Y, then Q Y (Chebyshev: y_j and (Q^2+s) y_j)
+    c.take(F * d.kp);                                        // X
+    c.take(F * d.kp);                                        // Q y inside (Q^2 + s) y
+    c.take(F);                                               // w
     c.take(sizeof(double) * 2 * nv * site_blocks(L));        // partials
     c.take(sizeof(double) * 2 * nv);                         // reduced sums / coefficients
     return c.off + 256;
 }
 
-// Chebyshev-filtered Lanczos for the low modes of Q; see include/ovl.h
+// Low modes of Q: a Lanczos run on Q^2 seeds a block of kp = nev + extra
+// vectors and the filter interval; then Chebyshev-filtered subspace
+// iteration: X <- T_deg(a Q^2 + b) X, orthonormalised, Rayleigh-Ritz with Q;
+// see include/ovl.h
 int low_modes(const Lat &L, const void *U64, double m0, Fld start, const ovl_eig_params *p, Fld evecs, double *evals,
               double *resid, ovl_eig_stats *S, char *ws, size_t ws_bytes, hipStream_t st)
 {
@@ -167,233 +168,183 @@ int low_modes(const Lat &L, const void *U64, double m0, Fld start, const ovl_eig
     Fld YQ{c.take(F * 2 * kp), nullptr, P_F64, 2 * kp};   // Y_0..Y_kp-1, then Q Y_0..
     Fld Y = sub(YQ, L.V, 0, kp), QY = sub(YQ, L.V, kp, kp);
     Fld X{c.take(F * kp), nullptr, P_F64, kp};
+    Fld T{c.take(F * kp), nullptr, P_F64, kp};
     Fld w{c.take(F), nullptr, P_F64, 1};
-    Fld t{c.take(F), nullptr, P_F64, 1};
-    Fld cb[3];
-    for (auto &f : cb) f = Fld{c.take(F), nullptr, P_F64, 1};
     double *partials = (double *)c.take(sizeof(double) * 2 * nv * site_blocks(L));
     double *coef = (double *)c.take(sizeof(double) * 2 * nv);
     if (c.off > ws_bytes) return OVL_ERR_WORKSPACE;
     int64_t q2n = 0;
     int e;
 
-    // out = (Q^2 + s) in: the second stencil adds s * in in its epilogue
+    // out = (Q^2 + s) in for a field set: the second stencil adds s * in in
+    // its epilogue
     auto q2s = [&](Fld in, Fld out, double s) -> hipError_t {
+        Fld t = sub(T, L.V, 0, in.nrhs);
         hipError_t h = q_apply(L, U64, m0, in, t, st);
         if (h != hipSuccess) return h;
         WArgs a{};
         a.U = U64;
         a.diag = m0 + 4.0;
-        a.nrhs = 1;
+        a.nrhs = in.nrhs;
         a.in = t.d;
         a.out = out.d;
         a.p = in.d;
         a.shift = s;
-        q2n++;
+        q2n += in.nrhs;
         return launch_wilson(L, P_F64, W_SHIFT, true, a, st);
     };
-    // the operator of the Lanczos recursion: Q^2 (deg 0) or the Chebyshev
-    // polynomial T_deg(a Q^2 + b), a = 2/(tmax - tcut), b = -(tmax + tcut)/(tmax - tcut)
-    int deg = 0;
-    double ca = 0.0, cbb = 0.0;
-    auto op = [&](Fld in, Fld out) -> int {
-        if (deg == 0) {
-            OVL_HIP(q2s(in, out, 0.0));
-            return OVL_OK;
-        }
-        // y0 = in, y1 = (a Q^2 + b) in, y_{j+1} = 2 (a Q^2 + b) y_j - y_{j-1}
-        Fld y0 = cb[0], y1 = cb[1], tmp = cb[2];
-        OVL_HIP(hipMemcpyAsync(y0.d, in.d, F, hipMemcpyDeviceToDevice, st));
-        OVL_HIP(q2s(in, tmp, cbb / ca));
-        OVL_HIP(launch_axpby(L, ca, tmp, 0.0, y1, st));
-        for (int j = 2; j <= deg; j++) {
-            OVL_HIP(q2s(y1, tmp, cbb / ca));
-            OVL_HIP(launch_axpby(L, 2.0 * ca, tmp, -1.0, y0, st));   // y0 <- y_{j}
-            std::swap(y0, y1);
-        }
-        OVL_HIP(hipMemcpyAsync(out.d, y1.d, F, hipMemcpyDeviceToDevice, st));
-        return OVL_OK;
-    };
 
-    // one Lanczos run with full reorthogonalisation from the unit vector V_0;
-    // `check(n, b)` after every step may stop it (returns > 0), < 0 is an error
-    std::vector<double> alpha, beta;
-    std::vector<cd> h(m + 1);
-    auto lanczos = [&](int steps, const std::function<int(int, double)> &check) -> int {
-        alpha.clear();
-        beta.clear();
-        for (int j = 0; j < steps; j++) {
-            int r = op(field(V, L, j), w);
-            if (r) return r;
-            double a = 0.0;
-            for (int pass = 0; pass < 2; pass++) {
-                r = mdot(L, V, j + 1, w, partials, coef, h.data(), st);
-                if (r) return r;
-                k_mcaxpy<<<site_blocks(L), kBlock, 0, st>>>(L.g, L.nb, j + 1, coef, -1.0, (const double2 *)V.d,
-                                                            (double2 *)w.d);
-                OVL_HIP(hipGetLastError());
-                a += h[j].real();
-            }
-            double b;
-            r = field_norms(L, w, partials, coef, &b, st);
-            if (r) return r;
-            if (!std::isfinite(a) || !std::isfinite(b)) return OVL_ERR_NONFINITE;
-            alpha.push_back(a);
-            const int n = j + 1;
-            r = check(n, b);
-            if (r) return r;
-            // an invariant subspace ends the recursion
-            if (b <= 1e-14 * std::max(1.0, std::fabs(a)) || n == steps) break;
-            beta.push_back(b);
-            OVL_HIP(launch_axpby(L, 1.0 / b, w, 0.0, field(V, L, j + 1), st));
-        }
-        return 0;
-    };
-
+    // ---- seeding run: Lanczos on Q^2 with full reorthogonalisation
     double bn;
     e = field_norms(L, start, partials, coef, &bn, st);
     if (e) return e;
     if (!(bn > 0.0) || !std::isfinite(bn)) return bn == 0.0 ? OVL_ERR_INVALID : OVL_ERR_NONFINITE;
     OVL_HIP(launch_axpby(L, 1.0 / bn, start, 0.0, field(V, L, 0), st));
-
-    // stage 0: plain Lanczos on Q^2 for the filter's interval
-    const int m0s = std::min(m, 40);
-    e = lanczos(m0s, [](int, double) { return 0; });
-    if (e < 0) return e;
-    const int n0 = (int)alpha.size();
-    std::vector<double> theta, Z;
-    if (!tridiag_sorted(n0, alpha, beta, theta, Z, true)) return OVL_ERR_NONFINITE;
-    // the largest Ritz value converges from below within a few steps; 1% above
-    // it bounds the spectrum (an eigenvalue just outside is only mildly amplified)
-    const double tmax = 1.01 * theta[n0 - 1] + 1e-12;
-    double tcut = theta[std::min(kp, n0 - 1)];
-    if (!(tcut < tmax)) tcut = 0.5 * tmax;
-    int total_steps = n0, stages = 0;
-    bool ok = false;
-    std::vector<double> lam, sig, rn(kp);
-    std::vector<cd> H((size_t)kp * kp), H2((size_t)kp * kp), Cm, C2, col(2 * kp);
-    std::vector<int> order;
-    int nsel = 0;   // Rayleigh-Ritz pairs available in X (sorted by |Q x|)
-
-    // Rayleigh-Ritz on the kp Ritz vectors of p with the largest |p|: X, lam,
-    // residuals rn, the Q^2 values sig; converged when the k smallest |Q x|
-    // meet tol
-    auto rayleigh_ritz = [&](int n) -> int {
-        std::vector<double> th, Zf;
-        if (!tridiag_sorted(n, alpha, beta, th, Zf)) return OVL_ERR_NONFINITE;
-        std::vector<int> ix(n);
-        std::iota(ix.begin(), ix.end(), 0);
-        std::sort(ix.begin(), ix.end(), [&](int a, int b) { return std::fabs(th[a]) > std::fabs(th[b]); });
-        const int q = std::min(kp, n);
-        std::vector<cd> cz(n);
-        for (int i = 0; i < q; i++) {
-            for (int j = 0; j < n; j++) cz[j] = Zf[(size_t)j * n + ix[i]];
-            OVL_HIP(launch_zero(L, field(Y, L, i), st));
-            int r = mcaxpy(L, V, n, cz.data(), field(Y, L, i), coef, st);
-            if (r) return r;
+    std::vector<double> alpha, beta;
+    std::vector<cd> h(nv);
+    int n0 = 0;
+    for (int j = 0; j < m; j++) {
+        OVL_HIP(q2s(field(V, L, j), w, 0.0));
+        double a = 0.0;
+        for (int pass = 0; pass < 2; pass++) {
+            e = mdot(L, V, j + 1, w, partials, coef, h.data(), st);
+            if (e) return e;
+            k_mcaxpy<<<site_blocks(L), kBlock, 0, st>>>(L.g, L.nb, j + 1, coef, -1.0, (const double2 *)V.d,
+                                                        (double2 *)w.d);
+            OVL_HIP(hipGetLastError());
+            a += h[j].real();
         }
-        Fld Yq = sub(Y, L.V, 0, q), QYq = sub(QY, L.V, 0, q);
+        double b;
+        e = field_norms(L, w, partials, coef, &b, st);
+        if (e) return e;
+        if (!std::isfinite(a) || !std::isfinite(b)) return OVL_ERR_NONFINITE;
+        alpha.push_back(a);
+        n0 = j + 1;
+        if (b <= 1e-14 * std::max(1.0, std::fabs(a)) || n0 == m) break;   // invariant subspace or done
+        beta.push_back(b);
+        OVL_HIP(launch_axpby(L, 1.0 / b, w, 0.0, field(V, L, j + 1), st));
+    }
+    if (n0 < k) return OVL_ERR_INVALID;   // the Krylov space is smaller than nev
+    const int q = std::min(kp, n0);       // block size
+    std::vector<double> theta, Z;
+    if (!tridiag_sorted(n0, alpha, beta, theta, Z)) return OVL_ERR_NONFINITE;
+    // filter interval: the largest Ritz value converges from below within a
+    // few steps (1% above it bounds the spectrum; an eigenvalue just outside
+    // is only mildly amplified); the q-th smallest Ritz value is >= theta_q
+    // (interlacing), so the first edge keeps the q lowest modes amplified
+    const double tmax = 1.01 * theta[n0 - 1] + 1e-12;
+    double tcut = theta[std::min(q, n0 - 1)];
+    if (!(tcut < tmax)) tcut = 0.5 * tmax;
+    // the block starts as the q lowest Ritz vectors of Q^2
+    {
+        std::vector<cd> cz(n0);
+        for (int i = 0; i < q; i++) {
+            for (int j = 0; j < n0; j++) cz[j] = Z[(size_t)j * n0 + i];
+            OVL_HIP(launch_zero(L, field(X, L, i), st));
+            e = mcaxpy(L, V, n0, cz.data(), field(X, L, i), coef, st);
+            if (e) return e;
+        }
+    }
+    const Fld Xq = sub(X, L.V, 0, q), Yq = sub(Y, L.V, 0, q), QYq = sub(QY, L.V, 0, q);
+
+    double tlow = theta[0];   // >= theta_1 (interlacing)
+    int64_t degs = 0;
+    std::vector<double> lam, sig, rn(q);
+    std::vector<cd> H, H2, Cm, C2, col(2 * kp), cc(2 * kp);
+    std::vector<int> order(q);
+    bool ok = false;
+    int iters = 0;
+    for (int it = 0; it < p->stages && !ok; it++) {
+        iters++;
+        // Y = T_deg(a Q^2 + b) X by the three-term recurrence, y_0 = X,
+        // y_1 = (a Q^2 + b) X, y_{j+1} = 2 (a Q^2 + b) y_j - y_{j-1}, in the
+        // buffers X and Y (the Q Y half holds (Q^2 + b/a) y_j)
+        const double ca = 2.0 / (tmax - tcut), cbb = -(tmax + tcut) / (tmax - tcut);
+        // degree: at most p->degree, and low enough that the filter's gain at
+        // the lowest eigenvalue estimate stays below 1e5 (T_d(x) =
+        // cosh(d acosh|x|)); a larger spread would leave the block's weaker
+        // directions below the rounding of its dominant ones
+        const double xlow = std::fabs(ca * tlow + cbb);
+        int deg = p->degree;
+        if (xlow > 1.0) deg = std::max(1, std::min(deg, (int)std::ceil(std::acosh(1e5) / std::acosh(xlow))));
+        Fld y0 = Xq, y1 = Yq;
+        OVL_HIP(q2s(y0, QYq, cbb / ca));
+        OVL_HIP(launch_axpby(L, ca, QYq, 0.0, y1, st));
+        for (int j = 2; j <= deg; j++) {
+            OVL_HIP(q2s(y1, QYq, cbb / ca));
+            OVL_HIP(launch_axpby(L, 2.0 * ca, QYq, -1.0, y0, st));
+            std::swap(y0, y1);
+        }
+        if (y1.d != Yq.d) OVL_HIP(hipMemcpyAsync(Yq.d, y1.d, F * q, hipMemcpyDeviceToDevice, st));
+        // orthonormalise the block (classical Gram-Schmidt, twice)
+        for (int i = 0; i < q; i++) {
+            Fld yi = field(Y, L, i);
+            for (int pass = 0; pass < 2 && i > 0; pass++) {
+                e = mdot(L, Y, i, yi, partials, coef, h.data(), st);
+                if (e) return e;
+                k_mcaxpy<<<site_blocks(L), kBlock, 0, st>>>(L.g, L.nb, i, coef, -1.0, (const double2 *)Y.d,
+                                                            (double2 *)yi.d);
+                OVL_HIP(hipGetLastError());
+            }
+            double nn;
+            e = field_norms(L, yi, partials, coef, &nn, st);
+            if (e) return e;
+            if (!(nn > 0.0) || !std::isfinite(nn)) return OVL_ERR_NONFINITE;
+            OVL_HIP(launch_axpby(L, 1.0 / nn, yi, 0.0, yi, st));
+        }
+        // Rayleigh-Ritz with Q (H) and Q^2 (H2 = (QY)^H QY) on span Y
         OVL_HIP(q_apply(L, U64, m0, Yq, QYq, st));
         H.assign((size_t)q * q, 0.0);
         H2.assign((size_t)q * q, 0.0);
         for (int b = 0; b < q; b++) {
-            int r = mdot(L, Yq, q, field(QY, L, b), partials, coef, col.data(), st);
-            if (r) return r;
+            e = mdot(L, Yq, q, field(QY, L, b), partials, coef, col.data(), st);
+            if (e) return e;
             for (int a = 0; a < q; a++) H[(size_t)a * q + b] = col[a];
-            r = mdot(L, QYq, q, field(QY, L, b), partials, coef, col.data(), st);
-            if (r) return r;
+            e = mdot(L, QYq, q, field(QY, L, b), partials, coef, col.data(), st);
+            if (e) return e;
             for (int a = 0; a < q; a++) H2[(size_t)a * q + b] = col[a];
         }
         for (auto *M : {&H, &H2})
             for (int a = 0; a < q; a++)
                 for (int b = a; b < q; b++) {
-                    const cd s = 0.5 * ((*M)[(size_t)a * q + b] + std::conj((*M)[(size_t)b * q + a]));
-                    (*M)[(size_t)a * q + b] = s;
-                    (*M)[(size_t)b * q + a] = std::conj(s);
+                    const cd sv = 0.5 * ((*M)[(size_t)a * q + b] + std::conj((*M)[(size_t)b * q + a]));
+                    (*M)[(size_t)a * q + b] = sv;
+                    (*M)[(size_t)b * q + a] = std::conj(sv);
                 }
         if (!herm_jacobi(q, H, lam, Cm) || !herm_jacobi(q, H2, sig, C2)) return OVL_ERR_NONFINITE;
         std::sort(sig.begin(), sig.end());
-        // residual of pair i: R_i = sum_a C_ai (Q Y_a - lam_i Y_a), into X_i
-        // for its norm, then X_i = sum_a C_ai Y_a
+        // residual of pair i: R_i = sum_a C_ai (Q Y_a - lam_i Y_a) into X_i for
+        // its norm, then X_i = sum_a C_ai Y_a
         for (int i = 0; i < q; i++) {
+            std::fill(cc.begin(), cc.end(), cd(0.0));
             for (int a = 0; a < q; a++) {
-                col[a] = -lam[i] * Cm[(size_t)a * q + i];
-                col[q + a] = Cm[(size_t)a * q + i];
+                cc[a] = -lam[i] * Cm[(size_t)a * q + i];
+                cc[kp + a] = Cm[(size_t)a * q + i];
             }
-            Fld xi = field(X, L, i);
-            OVL_HIP(launch_zero(L, xi, st));
-            // Y and Q Y are one contiguous set of 2 kp fields; only the first q
-            // of each are used
-            std::vector<cd> cc(2 * kp, cd(0.0));
-            for (int a = 0; a < q; a++) {
-                cc[a] = col[a];
-                cc[kp + a] = col[q + a];
-            }
-            int r = mcaxpy(L, YQ, 2 * kp, cc.data(), xi, coef, st);
-            if (r) return r;
+            OVL_HIP(launch_zero(L, field(X, L, i), st));
+            e = mcaxpy(L, YQ, 2 * kp, cc.data(), field(X, L, i), coef, st);
+            if (e) return e;
         }
-        e = field_norms(L, sub(X, L.V, 0, q), partials, coef, rn.data(), st);
+        e = field_norms(L, Xq, partials, coef, rn.data(), st);
         if (e) return e;
         for (int i = 0; i < q; i++) {
             for (int a = 0; a < q; a++) col[a] = Cm[(size_t)a * q + i];
-            Fld xi = field(X, L, i);
-            OVL_HIP(launch_zero(L, xi, st));
-            int r = mcaxpy(L, Yq, q, col.data(), xi, coef, st);
-            if (r) return r;
+            OVL_HIP(launch_zero(L, field(X, L, i), st));
+            e = mcaxpy(L, Yq, q, col.data(), field(X, L, i), coef, st);
+            if (e) return e;
         }
-        order.resize(q);
         std::iota(order.begin(), order.end(), 0);
         std::sort(order.begin(), order.end(), [&](int a, int b) {
             return lam[a] * lam[a] + rn[a] * rn[a] < lam[b] * lam[b] + rn[b] * rn[b];
         });
-        nsel = q;
-        if (q < k) return 0;
         double mx = 0.0;
         for (int i = 0; i < k; i++) mx = std::max(mx, rn[order[i]]);
-        return mx <= p->tol ? 1 : 0;
-    };
-
-    for (int sgi = 0; sgi < p->stages && !ok; sgi++) {
-        stages++;
-        deg = p->degree;
-        ca = 2.0 / (tmax - tcut);
-        cbb = -(tmax + tcut) / (tmax - tcut);
-        int conv = 0;
-        e = lanczos(m, [&](int n, double) -> int {
-            total_steps++;
-            if (n < kp || (n % p->check_every != 0 && n != m)) return 0;
-            const int r = rayleigh_ritz(n);
-            if (r < 0) return r;
-            conv = r;
-            return r;
-        });
-        if (e < 0) return e;
-        if (conv == 1) {
-            ok = true;
-            break;
-        }
-        if (nsel == 0) {
-            const int r = rayleigh_ritz((int)alpha.size());
-            if (r < 0) return r;
-            if (r == 1) {
-                ok = true;
-                break;
-            }
-        }
-        // restart: lower the edge to the kp-th Rayleigh-Ritz value of Q^2 on
-        // span Y (an upper bound of theta_kp), start from the sum of the pairs
-        if ((int)sig.size() >= kp) tcut = std::min(tcut, 1.05 * sig[kp - 1]);
-        OVL_HIP(launch_zero(L, field(V, L, 0), st));
-        std::vector<cd> ones(nsel, cd(1.0));
-        e = mcaxpy(L, X, nsel, ones.data(), field(V, L, 0), coef, st);
-        if (e) return e;
-        double nn;
-        e = field_norms(L, field(V, L, 0), partials, coef, &nn, st);
-        if (e) return e;
-        if (!(nn > 0.0)) return OVL_ERR_NONFINITE;
-        OVL_HIP(launch_axpby(L, 1.0 / nn, field(V, L, 0), 0.0, field(V, L, 0), st));
+        ok = mx <= p->tol;
+        // the q-th Rayleigh-Ritz value of Q^2 bounds theta_q from above
+        tcut = std::min(tcut, 1.05 * sig[q - 1]);
+        tlow = sig[0];
+        degs += deg;
     }
-    if (nsel < k) return OVL_ERR_INVALID;   // the Krylov space is smaller than nev
 
     // the k pairs with the smallest |Q x|, ascending |lambda|, to evecs
     std::vector<int> best(order.begin(), order.begin() + k);
@@ -403,7 +354,7 @@ int low_modes(const Lat &L, const void *U64, double m0, Fld start, const ovl_eig
         evals[i] = lam[best[i]];
     }
     // exact residuals |Q xi - lambda xi| / |xi|
-    Fld R = sub(X, L.V, 0, k);
+    Fld R = sub(Y, L.V, 0, k);
     OVL_HIP(q_apply(L, U64, m0, evecs, R, st));
     for (int i = 0; i < k; i++) OVL_HIP(launch_axpby(L, -evals[i], field(evecs, L, i), 1.0, field(R, L, i), st));
     std::vector<double> rr(k), xn(k);
@@ -420,18 +371,19 @@ int low_modes(const Lat &L, const void *U64, double m0, Fld start, const ovl_eig
         ok = ok && resid[i] <= p->tol;
     }
     if (S) {
-        S->steps = total_steps;
-        S->stages = stages;
+        S->steps = n0;
+        S->stages = iters;
         S->q2_applies = q2n;
         S->converged = ok ? 1 : 0;
         S->max_residual = mx;
         double nxt = 0.0;
-        for (int i = k; i < nsel; i++) {
+        for (int i = k; i < q; i++) {
             const double v = std::fabs(lam[order[i]]);
             if (nxt == 0.0 || v < nxt) nxt = v;
         }
         S->lambda_next = nxt;
         S->theta_cut = tcut;
+        S->mean_degree = iters > 0 ? (double)degs / iters : 0.0;
         S->seconds = now_s() - t0;
     }
     return ok ? OVL_OK : OVL_NOT_CONVERGED;

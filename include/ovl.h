@@ -215,6 +215,13 @@ typedef struct {
                                 modes of Q (NULL: none, the default).  The
                                 Zolotarev interval of the call should then
                                 start at the smallest |lambda| not deflated */
+    int32_t sloppy_f16;      /* mixed: 1 rounds the FP32 phase's Krylov vectors
+                                (residual ring, p0 and Q p0) through FP16
+                                storage with per-site scales after every update,
+                                as FP16S storage of them would; a measurement
+                                mode for that format's residual floor and
+                                iteration count (the extra conversions make it
+                                slower, not faster).  0 (default): FP32 */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */
@@ -492,7 +499,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
  * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 1e-5,
- * block_f64 0, rhs_group 0, deflation NULL. */
+ * block_f64 0, rhs_group 0, deflation NULL, sloppy_f16 0. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 /* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on

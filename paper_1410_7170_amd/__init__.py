@@ -64,7 +64,7 @@ class ovl_solver_params(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("maxiter", c_i32), ("mode", c_i32), ("reliable_delta", c_dbl),
                 ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32), ("profile", c_i32),
                 ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32), ("rhs_group", c_i32),
-                ("deflation", ctypes.POINTER(ovl_deflation))]
+                ("deflation", ctypes.POINTER(ovl_deflation)), ("sloppy_f16", c_i32)]
 
 
 class ovl_eig_params(ctypes.Structure):

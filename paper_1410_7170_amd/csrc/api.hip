@@ -21,7 +21,7 @@ hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld 
                           bool accumulate = false);
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase);
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase, bool f16_store);
 size_t tune_ws_bytes(const Lat &L, int nrhs);
 int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes, hipStream_t st,
                      int32_t *tried, float *times_us, int32_t max_tried);
@@ -102,7 +102,7 @@ bool params_ok(const ovl_solver_params *p)
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED || p->mode == OVL_SOLVE_LANCZOS) &&
            p->reliable_delta > 0.0 &&
            p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
-           p->sloppy_below < 1.0 && p->rhs_group >= 0;
+           p->sloppy_below < 1.0 && p->rhs_group >= 0 && (p->sloppy_f16 == 0 || p->sloppy_f16 == 1);
 }
 
 bool defl_ok(const ovl_deflation *D)
@@ -360,7 +360,8 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         yb += (field_bytes(P_F64, L.V) * nrhs + 255) & ~(size_t)255;
         if (prm && prm->mode == OVL_SOLVE_LANCZOS) return yb + lanczos_sign_ws_bytes(L, nrhs);
         if (prm && prm->mode == OVL_SOLVE_MIXED)
-            return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0);
+            return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0,
+                                       prm->sloppy_f16 != 0);
         if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64);
         return yb + mscg_ws_bytes(L, nrhs, nshift);
     }
@@ -383,6 +384,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->block_f64 = 0;
     p->rhs_group = 0;
     p->deflation = nullptr;
+    p->sloppy_f16 = 0;
 }
 
 int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,

@@ -541,19 +541,30 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     for (int q = 0; q < R; q++) it_left = std::min<long>(it_left, prm->maxiter - it0[q]);
     while (k < it_left && !done && !switched) {
         int batch = (int)std::min<long>(m, it_left - k);
+        // FP16 storage of the Krylov vectors (measurement mode): each new
+        // vector is rounded through the FP16S set and back after its kernel
+        const bool f16 = PS == P_F32 && o.f16.d;
+        auto round16 = [&](void *d) -> hipError_t {
+            const Fld f{d, nullptr, P_F32, R};
+            hipError_t h = launch_convert(L, f, o.f16, st);
+            return h == hipSuccess ? launch_convert(L, o.f16, f, st) : h;
+        };
         for (int q = 0; q < batch; q++, k++) {
             int e0 = prof.mark();
             OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
+            if (f16) OVL_HIP(round16(t.d));
             int e1 = prof.mark();
             k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
             int e2 = prof.mark();
             B.rin = slot(k);
             B.out = slot(k + 1);
             OVL_HIP(launch_wilson(L, PS, W_RUPDATE, true, B, st));
+            if (f16) OVL_HIP(round16(slot(k + 1)));
             int e3 = prof.mark();
             k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk, npart, sw2);
             int e4 = prof.mark();
             k_base_p<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), p0.d);
+            if (f16) OVL_HIP(round16(p0.d));
             int e5 = prof.mark();
             OVL_HIP(hipGetLastError());
             prof.span(e0, e1, OVL_K_STENCIL);

@@ -53,10 +53,14 @@ static size_t region_b_bytes(const Lat &L, int nrhs, int nshift, int m)
     return std::max(std::max(a, b), F);
 }
 
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase)
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase, bool f16_store)
 {
     const size_t F = field_bytes(P_F64, L.V);
     WsCarve c{nullptr, 0, 0};
+    if (f16_store) {
+        c.take(field_bytes(P_F16S, L.V) * nrhs);      // FP16 storage of the sloppy vectors
+        c.take(scale_bytes(L.V) * nrhs);
+    }
     const int nbat = refine_batch(nrhs);
     if (!f64_phase) c.take(F * nrhs * nshift);        // x_j (no FP64 phase to lend its p_j)
     c.take(F * nbat);                                 // refinement batch right-hand sides
@@ -112,8 +116,16 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     const size_t F = field_bytes(P_F64, L.V);
     const bool f64_phase = prm->sloppy_below > 0.0;
     if (!weights) return OVL_ERR_INVALID;
-    if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, m64, f64_phase)) return OVL_ERR_WORKSPACE;
+    const bool f16 = prm->sloppy_f16 != 0;
+    if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, m64, f64_phase, f16)) return OVL_ERR_WORKSPACE;
     WsCarve c{ws, 0, ws_bytes};
+    Fld F16{};
+    if (f16) {
+        F16.d = c.take(field_bytes(P_F16S, L.V) * R);
+        F16.sc = (float *)c.take(scale_bytes(L.V) * R);
+        F16.prec = P_F16S;
+        F16.nrhs = R;
+    }
     const int NB = refine_batch(R);
     // the increments dx_j (field j*R + q): their own fields without an FP64
     // phase, else that phase's p_j (set after it)
@@ -150,6 +162,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     o.m = m;
     o.keep_x = true;
     o.reliable = true;
+    o.f16 = F16;   // the bulk only: the refinement keeps FP32 storage
     int rc;
     bool switched = false;
     Fld r0 = b;                                                    // residual at the hand-over

@@ -91,6 +91,9 @@ struct BlkOpts {
     // precision to continue (0: run to convergence).
     double switch_rel = 0.0;
     const struct MsScratch *resume = nullptr;   // continue the recurrences of a switched solve
+    // FP32 solves: round r (ring), p0 and t = Q p0 through this FP16S field set
+    // (nrhs fields with scales) after every update, as FP16S storage would
+    Fld f16{};
 };
 
 // Return code of a blocked solve that stopped at switch_rel (internal).

@@ -194,3 +194,32 @@ def test_mixed_zero_rhs_in_batch(ovl):
     assert not np.any(got[1]) and not np.any(ref[1])
     assert (np.array(st["true_residual"][0]) <= 1e-10).all()
     close(got[0], ref[0], dims, 1e-9)
+
+
+@pytest.mark.parametrize("sloppy_below", [1e-5, 1e-8])
+def test_mixed_fp16_storage_mode(ovl, sloppy_below):
+    """sloppy_f16 rounds the FP32 phase's Krylov vectors through FP16 storage
+    with per-site scales.  With refinement every shift still meets 1e-10 and
+    D_ov matches the oracle; without it the verified residuals report the
+    format's floor, which stays above the FP32 bulk's when the hand-over is
+    early."""
+    dims = (8, 8, 8, 8)
+    note(f"mixed fp16 storage sloppy_below={sloppy_below}")
+    U, lat, olat, G, (s, w), (os_, ow) = setup(ovl, dims, 311)
+    b = synth.gaussian_spinor(lat.V, 312)[0]
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    O = ovl.Spinor(lat, 0)
+    prm = ovl.default_params(tol=1e-10, maxiter=5000, mode=ovl.SOLVE_MIXED, sloppy_below=sloppy_below, sloppy_f16=1)
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, prm)
+    tr = np.array(st["true_residual"][0])
+    note(f"  refined: max residual {tr.max():.2e}, {st['refine_iterations']} refinement iterations")
+    assert (tr > 0).all() and (tr <= 1e-10).all(), tr
+    ref, _, _ = oracle.overlap(olat, U, RHO, os_, ow, b, 1e-13, 5000)
+    close(O.to_canonical().cpu().numpy()[0], ref, dims, 1e-8)
+    prm.refine = 0
+    st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, prm, allow_not_converged=True)
+    floor = max(st["true_residual"][0])
+    note(f"  floor without refinement: {floor:.2e}")
+    assert floor > 0 and np.isfinite(floor)
+    if sloppy_below >= 1e-5:
+        assert floor > 1e-10

@@ -314,6 +314,26 @@ def test_autotune_keeps_results(ovl, dims, nrhs):
             check(prec, got[r], oracle.dw(olat, U, M0, psi[r]), psi[r], dims)
 
 
+def test_autotune_cache_round_trip(ovl, tmp_path):
+    """The cached autotuner times once, writes its choice as a JSON line and
+    returns it unchanged on the next call for the same lattice and RHS count
+    without timing; another RHS count is tuned anew."""
+    dims = (16, 8, 8, 8)
+    note("autotune cache")
+    lat, olat, U, G = setup(ovl, dims, seed=33, n_stout=1)
+    cache = str(tmp_path / "tune.json")
+    first = ovl.autotune_stencil(lat, G, 3, cache=cache)
+    assert first["timings"] != "cache" and len(first["timings"]) > 3
+    lat2 = ovl.Lattice(dims)
+    again = ovl.autotune_stencil(lat2, G, 3, cache=cache)
+    assert again["timings"] == "cache"
+    for k in ("tile_t", "stream_t", "stream_t64", "rhs_tile", "mfma"):
+        assert again[k] == first[k]
+    other = ovl.autotune_stencil(ovl.Lattice(dims), G, 1, cache=cache)
+    assert other["timings"] != "cache"
+    assert len(open(cache).read().splitlines()) == 2
+
+
 # LDS-staged streaming form: blocks of whole x3 rows of consecutive x2 at one
 # x1 (256 % L3 == 0, L2*L3 % 256 == 0) and launches of at most 512 blocks
 # the last three have x3 extents (24, 48) whose rows tile 192-site blocks, not 256

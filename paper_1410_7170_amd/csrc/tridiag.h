@@ -15,8 +15,15 @@ namespace ovl {
 // of them by default, or e.g. only the last (nrow 1, row0 n-1), which costs
 // O(n^2) instead of O(n^3).  Returns false if an eigenvalue fails to
 // converge in 60 sweeps.
+// One plane rotation of the eigenvector accumulation: columns i, i+1 of Z
+// become (c z_i - s z_{i+1}, s z_i + c z_{i+1}).
+struct PlaneRot {
+    int i;
+    double c, s;
+};
+
 inline bool tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, std::vector<double> &Z, int nrow = -1,
-                        int row0 = 0)
+                        int row0 = 0, std::vector<PlaneRot> *rots = nullptr)
 {
     if (nrow < 0) nrow = n, row0 = 0;
     Z.assign((size_t)nrow * n, 0.0);
@@ -60,6 +67,7 @@ inline bool tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, st
                 d[i + 1] = g + p;
                 g = c * r - b;
                 // the rotation acts on eigenvector columns i and i+1
+                if (rots) rots->push_back({i, c, s});
                 for (int k = 0; k < nrow; k++) {
                     const double zi = Z[(size_t)k * n + i], zi1 = Z[(size_t)k * n + i + 1];
                     Z[(size_t)k * n + i + 1] = s * zi + c * zi1;
@@ -77,16 +85,24 @@ inline bool tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, st
 
 // c = |b| sign(T) e_1 for the Lanczos matrix T (diagonal a, off-diagonal
 // bt): the coefficients of the Lanczos approximation of sign(A) b in the
-// Lanczos basis.  A zero Ritz value counts as +1.  Returns false if the
+// Lanczos basis.  With T = Z diag(theta) Z^T, c = |b| Z (sign(theta) .* Z^T e_1):
+// the first row of Z is accumulated alongside the QL sweeps (Z^T e_1), and Z
+// times the weighted vector is formed by applying the logged rotations
+// (Z = G_1 G_2 ... G_N) in reverse order, so the cost is O(n^2), not the O(n^3)
+// of forming Z.  A zero Ritz value counts as +1.  Returns false if the
 // eigen-decomposition fails.
 inline bool tridiag_sign_e1(int n, const double *a, const double *bt, double bnorm, std::vector<double> &c)
 {
-    std::vector<double> d(a, a + n), e(bt, bt + (n > 1 ? n - 1 : 0)), Z;
-    if (!tridiag_eig(n, d, e, Z)) return false;
+    std::vector<double> d(a, a + n), e(bt, bt + (n > 1 ? n - 1 : 0)), z0;
+    std::vector<PlaneRot> rots;
+    if (!tridiag_eig(n, d, e, z0, 1, 0, &rots)) return false;
     c.assign(n, 0.0);
-    for (int j = 0; j < n; j++) {
-        const double w = (d[j] >= 0.0 ? 1.0 : -1.0) * Z[j] * bnorm;   // sign(theta_j) z_j(0) |b|
-        for (int i = 0; i < n; i++) c[i] += w * Z[(size_t)i * n + j];
+    for (int j = 0; j < n; j++) c[j] = (d[j] >= 0.0 ? 1.0 : -1.0) * z0[j] * bnorm;   // sign(theta_j) z_j(0) |b|
+    for (size_t r = rots.size(); r-- > 0;) {
+        const PlaneRot &g = rots[r];
+        const double x = c[g.i], y = c[g.i + 1];
+        c[g.i] = g.c * x + g.s * y;
+        c[g.i + 1] = -g.s * x + g.c * y;
     }
     return true;
 }

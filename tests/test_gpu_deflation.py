@@ -179,3 +179,25 @@ def test_low_modes_rejects_bad_arguments(ovl, w44):
     start.data.zero_()
     with pytest.raises(ovl.OvlError):
         ovl.low_modes(lat, w44["G"], M0, start, nev=4)
+
+
+def test_outer_solve_with_deflated_inner_applies(ovl, w44):
+    """The outer FGMRES with its D_ov applications deflated (16 modes, poles on
+    the deflated interval) reaches the same solution as without deflation."""
+    lat, dims = w44["lat"], w44["dims"]
+    ws = w44["wsorted"]
+    eta = synth.gaussian_spinor(lat.V, 321)
+    E = ovl.Spinor.from_canonical(lat, dev(eta), 0)
+    sols = []
+    for defl in (w44["D"], None):
+        lo = abs(w44["D"].evals[-1]) if defl is not None else 0.999 * abs(ws[0])
+        s, wt, _ = ovl.zolotarev(lo, 1.001 * abs(ws[-1]), 16)
+        P = ovl.Spinor(lat, 0)
+        prm = ovl.default_outer_params(tol=1e-9, inner=dict(deflation=defl) if defl is not None else {})
+        st = ovl.overlap_solve(lat, w44["G"], RHO, s, wt, E, P, prm)
+        note(f"  deflated={defl is not None}: {st['iterations']} steps, {st['mscg_iterations']} multishift "
+             f"iterations, residual {st['residual']:.2e}")
+        assert st["residual"] <= 1e-9
+        sols.append(P.to_canonical().cpu().numpy()[0])
+    ratio, r2 = field_check(sols[0], sols[1], dims, 1e-7)
+    assert ratio <= 1.0

@@ -46,9 +46,11 @@ def test_tridiag_eig_matches_lapack(lib, n, seed):
     assert np.allclose(Z.T @ Z, np.eye(n), atol=1e-12)
 
 
-def test_tridiag_sign_e1_matches_lapack(lib):
-    rng = np.random.default_rng(9)
-    n = 120
+@pytest.mark.parametrize("n,seed", [(1, 8), (2, 10), (120, 9), (700, 11)])
+def test_tridiag_sign_e1_matches_lapack(lib, n, seed):
+    """sign(T) e_1 from the first eigenvector row and the logged rotations
+    (O(n^2)) equals Z sign(theta) Z^T e_1 from LAPACK."""
+    rng = np.random.default_rng(seed)
     a = rng.standard_normal(n)
     b = np.abs(rng.standard_normal(n - 1)) + 0.1
     c = np.empty(n)

@@ -8,7 +8,8 @@
 //           c_k = |b| sign(T_k) e_1 from an eigen-decomposition of T_k and an
 //           RHS stops once |c_k - c_{k-kCheck}| <= tol |b|;
 //   pass 2: the same recurrence regenerates v_1..v_m from the stored
-//           coefficients, accumulating y = sum_k c_k v_k.
+//           coefficients (one fused update-and-scale kernel per step),
+//           accumulating y = sum_k c_k v_k.
 // Four FP64 fields per RHS, twice the stencils of one pass.  Each RHS of a
 // batch has its own coefficients; the passes run in step for all of them.
 #include <cmath>
@@ -31,8 +32,10 @@ struct LzCoef {
 };
 
 // w = t - a_k v_k - b_{k-1} v_{k-1} into v_prev's field, partial |w|^2 per
-// RHS; in pass 2 (c != null) also y += c_k v_k.  a_k comes from the reduced
-// dot ar (pass 1) or the stored coefficients (pass 2).
+// RHS; in pass 2 (c != null) also y += c_k v_k, and w is stored already
+// divided by the known b_k (the next basis vector; no separate scaling
+// pass).  a_k comes from the reduced dot ar (pass 1) or the stored
+// coefficients (pass 2).
 __global__ __launch_bounds__(kBlock) void k_lz_update(Geom g, int nb, int nrhs, const double2 *t, const double2 *vk,
                                                        double2 *vprev, const LzCoef *cf, int k, const double *ar,
                                                        const double *c, double2 *y, double *partials)
@@ -49,11 +52,14 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(Geom g, int nb, int nrhs, 
         spinor_ref<P_F64>(vk, nullptr, g.S, r).load(p, i, v);
         const auto VP = spinor_ref<P_F64>(vprev, nullptr, g.S, r);
         VP.load(p, i, u);
+        const double bk = c ? cf->b[k][r] : 1.0;
+        const double inv = bk > 0.0 ? 1.0 / bk : 0.0;
 #pragma unroll
         for (int q = 0; q < 12; q++) {
             cplx<double> &w = tv[q / 3][q % 3];
             w = fmac(fmac(w, -a, v[q / 3][q % 3]), -bprev, u[q / 3][q % 3]);
             n2 += norm2(w);
+            if (c) w = inv * w;
         }
         VP.store(p, i, tv);
         if (c) {
@@ -70,24 +76,21 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(Geom g, int nb, int nrhs, 
     if (threadIdx.x == 0 && partials) partials[(size_t)r * gridDim.x + bl] = s;
 }
 
-// pass 1: a[k] from the reduced dot (real part), b[k] = |w| from the reduced
-// norm; an RHS whose new vector vanishes (an invariant subspace) keeps b = 0
-__global__ void k_lz_store(LzCoef *cf, int k, const double *dot, const double *nrm2, int nrhs)
-{
-    const int r = threadIdx.x;
-    if (r < nrhs) {
-        cf->a[k][r] = dot[r];
-        cf->b[k][r] = sqrt(fmax(nrm2[r], 0.0));
-    }
-}
-
-// v_next = w / b_k (0 when b_k is 0) written over w's field
-__global__ __launch_bounds__(kBlock) void k_lz_scale(Geom g, int nb, double2 *w, const LzCoef *cf, int k)
+// pass 1: v_next = w / b_k (0 when b_k is 0) written over w's field, with
+// b_k = |w| from the reduced norm; the first block also records a[k] (the
+// reduced dot, real part) and b[k].  An RHS whose new vector vanishes (an
+// invariant subspace) keeps b = 0.
+__global__ __launch_bounds__(kBlock) void k_lz_scale(Geom g, int nb, double2 *w, LzCoef *cf, int k,
+                                                      const double *dot, const double *nrm2)
 {
     const int r = blockIdx.y, bl = blockIdx.x;
     const int p = bl / nb, i = (bl % nb) * kBlock + threadIdx.x;
+    const double bk = sqrt(fmax(nrm2[r], 0.0));
+    if (bl == 0 && threadIdx.x == 0) {
+        cf->a[k][r] = dot[r];
+        cf->b[k][r] = bk;
+    }
     if (i >= g.Vh) return;
-    const double bk = cf->b[k][r];
     const double inv = bk > 0.0 ? 1.0 / bk : 0.0;
     const auto W = spinor_ref<P_F64>(w, nullptr, g.S, r);
     cplx<double> v[4][3];
@@ -172,8 +175,7 @@ int lanczos_sign(const Lat &L, const void *U64, double m0, Fld b, Fld y, double 
                                              (double2 *)vprev.d, cf, k, red, nullptr, nullptr, partials);
         OVL_HIP(hipGetLastError());
         OVL_HIP(launch_reduce(partials, 1, R, nblk, red + NR, st));
-        k_lz_store<<<1, 64, 0, st>>>(cf, k, red, red + NR, R);
-        k_lz_scale<<<grid, kBlock, 0, st>>>(L.g, L.nb, (double2 *)vprev.d, cf, k);
+        k_lz_scale<<<grid, kBlock, 0, st>>>(L.g, L.nb, (double2 *)vprev.d, cf, k, red, red + NR);
         OVL_HIP(hipGetLastError());
         std::swap(vprev, vk);
         k++;
@@ -247,10 +249,6 @@ int lanczos_sign(const Lat &L, const void *U64, double m0, Fld b, Fld y, double 
         k_lz_update<<<grid, kBlock, 0, st>>>(L.g, L.nb, R, (const double2 *)t.d, (const double2 *)vk.d,
                                              (double2 *)vprev.d, cf, j, nullptr, cw, (double2 *)y.d, nullptr);
         OVL_HIP(hipGetLastError());
-        if (j + 1 < kmx) {
-            k_lz_scale<<<grid, kBlock, 0, st>>>(L.g, L.nb, (double2 *)vprev.d, cf, j);
-            OVL_HIP(hipGetLastError());
-        }
         std::swap(vprev, vk);
     }
     OVL_HIP(hipStreamSynchronize(st));

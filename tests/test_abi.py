@@ -181,3 +181,96 @@ def test_zolotarev_rejects(ovl):
     for args in [(0.0, 1.0, 4), (1.0, 0.5, 4), (0.1, 1.0, 0), (0.1, 1.0, 33), (0.1, float("inf"), 4)]:
         with pytest.raises(ovl.OvlError):
             ovl.zolotarev(*args)
+
+
+def test_deflation_rejected_before_launch(ovl):
+    """ovl_deflation: FP64 eigenvectors, 1..OVL_MAX_NEV of them, finite
+    eigenvalues, no aliasing with the call's fields; its bytes count in the
+    workspace."""
+    lat = ovl.Lattice((4, 4, 4, 4))
+    lib = ovl._lib
+    b = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 1)
+    o = ovl.ovl_spinor(ctypes.c_void_p(1 << 20), None, ovl.F64, 1)
+    gf = ovl.ovl_gauge(ctypes.c_void_p(8192), None, None)
+    s = (ctypes.c_double * 2)(0.1, 0.2)
+    w = (ctypes.c_double * 2)(1.0, 1.0)
+    z = ovl.ovl_zolo(2, s, w)
+    st = ovl.ovl_solver_stats()
+    ev = (ctypes.c_double * 4)(0.1, -0.2, 0.3, -0.4)
+    bad_ev = (ctypes.c_double * 4)(0.1, float("nan"), 0.3, -0.4)
+    cases = [ovl.ovl_deflation(ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F32, 4), ev),
+             ovl.ovl_deflation(ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F64, 0), ev),
+             ovl.ovl_deflation(ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F64, 257), ev),
+             ovl.ovl_deflation(ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F64, 4), bad_ev),
+             ovl.ovl_deflation(ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F64, 4), None),
+             ovl.ovl_deflation(ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 4), ev)]   # aliases b
+    for d in cases:
+        p = ovl.default_params()
+        p.deflation = ctypes.pointer(d)
+        for fn in (lib.ovl_overlap_apply, lib.ovl_sign_q_apply):
+            rc = fn(lat.ref, ctypes.byref(gf), 1.6 if fn is lib.ovl_overlap_apply else -1.6, ctypes.byref(z),
+                    ctypes.byref(b), ctypes.byref(o), ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(1 << 26),
+                    1 << 30, None)
+            assert rc == ovl.ERR_INVALID
+    good = ovl.ovl_deflation(ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F64, 4), ev)
+    p = ovl.default_params()
+    base = lib.ovl_workspace_bytes(lat.ref, ovl.OP_MSCG, ovl.F64, 1, 2, ctypes.byref(p))
+    p.deflation = ctypes.pointer(good)
+    need = lib.ovl_workspace_bytes(lat.ref, ovl.OP_MSCG, ovl.F64, 1, 2, ctypes.byref(p))
+    assert need >= base + lat.spinor_bytes(ovl.F64)
+    rc = lib.ovl_overlap_apply(lat.ref, ctypes.byref(gf), 1.6, ctypes.byref(z), ctypes.byref(b), ctypes.byref(o),
+                               ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(1 << 26), need - 1, None)
+    assert rc == ovl.ERR_WORKSPACE
+
+
+def test_low_modes_rejected_before_launch(ovl):
+    lat = ovl.Lattice((4, 4, 4, 4))
+    lib = ovl._lib
+    gf = ovl.ovl_gauge(ctypes.c_void_p(8192), None, None)
+    start = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 1)
+    ev = (ctypes.c_double * 8)()
+    res = (ctypes.c_double * 8)()
+    st = ovl.ovl_eig_stats()
+    ws = ctypes.c_void_p(1 << 26)
+
+    def call(p, evecs, start=start, g=gf, nbytes=1 << 40):
+        return lib.ovl_low_modes(lat.ref, ctypes.byref(g), -1.6, ctypes.byref(start), ctypes.byref(p),
+                                 ctypes.byref(evecs), ev, res, ctypes.byref(st), ws, nbytes, None)
+
+    ok = ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F64, 8)
+    for field, value in (("nev", 0), ("nev", 300), ("degree", 0), ("degree", 201), ("stages", 0), ("steps", 5),
+                         ("tol", 0.0), ("extra", -1)):
+        p = ovl.ovl_eig_params()
+        lib.ovl_default_eig_params(ctypes.byref(p))
+        p.nev = 8
+        setattr(p, field, value)
+        assert lib.ovl_low_modes_workspace_bytes(lat.ref, ctypes.byref(p)) == 0, field
+        assert call(p, ok) == ovl.ERR_INVALID, field
+    p = ovl.ovl_eig_params()
+    lib.ovl_default_eig_params(ctypes.byref(p))
+    p.nev = 8
+    need = lib.ovl_low_modes_workspace_bytes(lat.ref, ctypes.byref(p))
+    assert need > 40 * lat.spinor_bytes(ovl.F64)
+    # evecs count, precision and aliasing; start count; missing FP64 links; workspace
+    assert call(p, ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F64, 7)) == ovl.ERR_INVALID
+    assert call(p, ovl.ovl_spinor(ctypes.c_void_p(1 << 24), None, ovl.F32, 8)) == ovl.ERR_INVALID
+    assert call(p, ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 8)) == ovl.ERR_INVALID
+    assert call(p, ok, start=ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 2)) == ovl.ERR_INVALID
+    assert call(p, ok, g=ovl.ovl_gauge(None, ctypes.c_void_p(8192), None)) == ovl.ERR_INVALID
+    assert call(p, ok, nbytes=need - 1) == ovl.ERR_WORKSPACE
+
+
+def test_new_descriptor_fields_validated(ovl):
+    """rhs_tile in {1, 2, 4, 8}, mfma in {0, 1}, sloppy_f16 in {0, 1}."""
+    lat = ovl.Lattice((4, 4, 4, 4))
+    lib = ovl._lib
+    gf = ovl.ovl_gauge(ctypes.c_void_p(8192), ctypes.c_void_p(8192), None)
+    i = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F32, 2)
+    o = ovl.ovl_spinor(ctypes.c_void_p(1 << 20), None, ovl.F32, 2)
+    for field, value in (("rhs_tile", 3), ("rhs_tile", 16), ("mfma", 2), ("mfma", -1)):
+        l2 = ovl.Lattice((4, 4, 4, 4))
+        setattr(l2.c, field, value)
+        assert lib.ovl_wilson_apply(l2.ref, ctypes.byref(gf), -1.6, ctypes.byref(i), ctypes.byref(o), None) \
+            == ovl.ERR_INVALID, field
+    p = ovl.default_params(mode=ovl.SOLVE_MIXED, sloppy_f16=2)
+    assert lib.ovl_workspace_bytes(lat.ref, ovl.OP_MSCG, ovl.F64, 1, 2, ctypes.byref(p)) == 0

@@ -518,10 +518,13 @@ def outer_line(ovl, torch, lat, G, shifts, weights, E):
     """D_ov psi = eta (eq. (linsys)) by FGMRES(100) to 1e-8: with the relaxed
     sign accuracy of Table (allparms1) and without it, and with the Wilson
     preconditioner D_W(m0^prec)^{-1} (eps_prec 0.1) at a few masses m0^prec
-    (the paper scans m0^prec, Fig. (prec_eff_m0w))."""
+    (the paper scans m0^prec, Fig. (prec_eff_m0w)), solved in the even-odd
+    form and, at one mass, through the full-lattice normal equations."""
     psi = ovl.Spinor(lat, ovl.F64)
     runs = []
     cases = [dict(relax=1), dict(relax=0)] + [dict(relax=1, precondition=1, prec_m0=m) for m in (-0.1, 0.0, 0.1)]
+    # the same preconditioner solved through the normal equations of the full lattice
+    cases.append(dict(relax=1, precondition=1, prec_m0=0.0, prec_even_odd=0))
     for kw in cases:
         prm = ovl.default_outer_params(tol=1e-8, **kw)
         torch.cuda.synchronize()

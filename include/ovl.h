@@ -222,6 +222,14 @@ typedef struct {
                                 mode for that format's residual floor and
                                 iteration count (the extra conversions make it
                                 slower, not faster).  0 (default): FP32 */
+    int32_t even_odd;        /* ovl_wilson_solve only: 1 solves the even-odd
+                                reduced system (Schur complement on the even
+                                sites) by an FP32 CGLS inside FP64 defect
+                                correction and stops on the true residual
+                                |b - D_W x| <= tol |b|; maxiter caps its CGLS
+                                iterations.  0 (default): CG on the normal
+                                equations of the full lattice, as described
+                                at ovl_wilson_solve */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */
@@ -437,6 +445,11 @@ typedef struct {
                                 on its normal equations (1e-1) */
     int32_t prec_maxiter;    /* cap on each preconditioner solve's CG iterations (200) */
     int32_t prec_block;      /* block length of that CG, 1..OVL_MAX_BLOCK (16) */
+    int32_t prec_even_odd;   /* 1: the preconditioner solves are ovl_wilson_solve's
+                                even-odd form, prec_tol then bounding the true
+                                residual |v - D_W z| / |v| of each (the paper's
+                                eps_prec) and prec_maxiter its CGLS iterations;
+                                0: the normal-equations CG (1) */
 } ovl_outer_params;
 
 typedef struct {
@@ -470,12 +483,17 @@ OVL_API int ovl_overlap_solve(const ovl_lattice *lat, const ovl_gauge *U, double
                               const ovl_spinor *eta, ovl_spinor *psi, const ovl_outer_params *prm,
                               ovl_outer_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
-/* x = D_W(m0)^{-1} b (eq. (Wilson-Dirac)) for each RHS, through the normal
- * equations D_W^H D_W x = D_W^H b with D_W^H = Gamma_5 D_W Gamma_5
- * (eq. (gamma_5_symmetry)): an FP32 CG (block length prm->block, 0 meaning 16)
- * with FP64 residual replacement, to prm->tol relative residual of the normal
- * equations or prm->maxiter iterations.  b, x: FP64 spinors, equal nrhs,
- * distinct.  stats (optional): iterations[q] and true_residual[q][0] =
+/* x = D_W(m0)^{-1} b (eq. (Wilson-Dirac)) for each RHS, the Wilson solve of
+ * the outer iteration's preconditioner (Section 5.1).  prm->even_odd = 0:
+ * through the normal equations D_W^H D_W x = D_W^H b with D_W^H = Gamma_5 D_W
+ * Gamma_5 (eq. (gamma_5_symmetry)): an FP32 CG (block length prm->block, 0
+ * meaning 16) with FP64 residual replacement, to prm->tol relative residual of
+ * the normal equations or prm->maxiter iterations.  prm->even_odd = 1: the
+ * even-site Schur complement system M x_e = b_e + H_eo b_o / (2(m0+4)),
+ * M = (m0+4) - H_eo H_oe / (4(m0+4)), by an FP32 CGLS inside FP64 defect
+ * correction, then x_o = (b_o + H_oe x_e / 2) / (m0+4); it stops when the true
+ * residual |b - D_W x| <= prm->tol |b| or after prm->maxiter CGLS iterations
+ * (m0 = -4 is rejected).  b, x: FP64 spinors, equal nrhs, distinct.  stats (optional): iterations[q] and true_residual[q][0] =
  * |b - D_W x| / |b| in FP64.  ws: ovl_workspace_bytes(lat, OVL_OP_WILSON_SOLVE,
  * OVL_F64, nrhs, 0, prm) bytes.  Returns OVL_OK, OVL_NOT_CONVERGED or an
  * error.  Synchronises the stream. */
@@ -499,7 +517,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
  * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 1e-5,
- * block_f64 0, rhs_group 0, deflation NULL, sloppy_f16 0. */
+ * block_f64 0, rhs_group 0, deflation NULL, sloppy_f16 0, even_odd 0. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 /* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on

@@ -64,7 +64,8 @@ class ovl_solver_params(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("maxiter", c_i32), ("mode", c_i32), ("reliable_delta", c_dbl),
                 ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32), ("profile", c_i32),
                 ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32), ("rhs_group", c_i32),
-                ("deflation", ctypes.POINTER(ovl_deflation)), ("sloppy_f16", c_i32)]
+                ("deflation", ctypes.POINTER(ovl_deflation)), ("sloppy_f16", c_i32),
+                ("even_odd", c_i32)]
 
 
 class ovl_eig_params(ctypes.Structure):
@@ -103,7 +104,7 @@ class ovl_outer_params(ctypes.Structure):
     _fields_ = [("tol", c_dbl), ("restart", c_i32), ("maxiter", c_i32), ("relax", c_i32),
                 ("relax_factor", c_dbl), ("sign_tol_max", c_dbl), ("inner", ovl_solver_params),
                 ("precondition", c_i32), ("prec_m0", c_dbl), ("prec_tol", c_dbl), ("prec_maxiter", c_i32),
-                ("prec_block", c_i32)]
+                ("prec_block", c_i32), ("prec_even_odd", c_i32)]
 
 
 class ovl_outer_stats(ctypes.Structure):

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libovl.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "wilson.hip", "wilson_mfma.hip", "solver.hip", "blocked.hip", "mixed.hip", "tune.hip", "outer.hip", "lanczos_sign.hip", "deflation.hip", "api.hip", "noalloc.hip", "zolotarev.cpp"]
+SOURCES = ["kernels.hip", "wilson.hip", "wilson_mfma.hip", "solver.hip", "blocked.hip", "mixed.hip", "tune.hip", "outer.hip", "wilson_eo.hip", "lanczos_sign.hip", "deflation.hip", "api.hip", "noalloc.hip", "zolotarev.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

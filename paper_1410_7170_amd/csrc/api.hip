@@ -102,7 +102,8 @@ bool params_ok(const ovl_solver_params *p)
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED || p->mode == OVL_SOLVE_LANCZOS) &&
            p->reliable_delta > 0.0 &&
            p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
-           p->sloppy_below < 1.0 && p->rhs_group >= 0 && (p->sloppy_f16 == 0 || p->sloppy_f16 == 1);
+           p->sloppy_below < 1.0 && p->rhs_group >= 0 && (p->sloppy_f16 == 0 || p->sloppy_f16 == 1) &&
+           (p->even_odd == 0 || p->even_odd == 1);
 }
 
 bool defl_ok(const ovl_deflation *D)
@@ -343,6 +344,8 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
     if (op == OVL_OP_LANCZOS) return lanczos_ws_bytes(L);
     if (op == OVL_OP_TUNE) return tune_ws_bytes(L, nrhs);
     if (op == OVL_OP_WILSON_SOLVE) {
+        if (prm && !params_ok(prm)) return 0;
+        if (prm && prm->even_odd) return wilson_solve_eo_ws_bytes(L);
         const int m = prm && prm->block > 0 ? prm->block : 16;
         if (m > OVL_MAX_BLOCK) return 0;
         return wilson_solve_ws_bytes(L, nrhs, m);
@@ -385,6 +388,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->rhs_group = 0;
     p->deflation = nullptr;
     p->sloppy_f16 = 0;
+    p->even_odd = 0;
 }
 
 int ovl_autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int32_t nrhs, void *ws, size_t ws_bytes,
@@ -657,6 +661,7 @@ void ovl_default_outer_params(ovl_outer_params *p)
     p->prec_tol = 1e-1;
     p->prec_maxiter = 200;
     p->prec_block = 16;
+    p->prec_even_odd = 1;
 }
 
 static bool outer_ok(const ovl_outer_params *p)
@@ -665,7 +670,8 @@ static bool outer_ok(const ovl_outer_params *p)
            p->maxiter >= 1 && (p->relax == 0 || p->relax == 1) && p->relax_factor > 0.0 && p->relax_factor <= 1.0 &&
            p->sign_tol_max > 0.0 && p->sign_tol_max < 1.0 && params_ok(&p->inner) &&
            (p->precondition == 0 || p->precondition == 1) && std::isfinite(p->prec_m0) && p->prec_tol > 0.0 &&
-           p->prec_tol < 1.0 && p->prec_maxiter >= 1 && p->prec_block >= 1 && p->prec_block <= OVL_MAX_BLOCK;
+           p->prec_tol < 1.0 && p->prec_maxiter >= 1 && p->prec_block >= 1 && p->prec_block <= OVL_MAX_BLOCK &&
+           (p->prec_even_odd == 0 || p->prec_even_odd == 1);
 }
 
 size_t ovl_overlap_solve_workspace_bytes(const ovl_lattice *lat, int32_t npoles, const ovl_outer_params *prm)
@@ -706,8 +712,10 @@ int ovl_wilson_solve(const ovl_lattice *lat, const ovl_gauge *U, double m0, cons
     const Lat L = make_lat(lat);
     double tr[NR];
     int it[NR] = {0};
-    int rc = wilson_solve(L, U, m0, fld(b), fld(x), prm->tol, prm->maxiter, prm->block > 0 ? prm->block : 16, tr, it,
-                          (char *)ws, ws_bytes, S(stream));
+    int rc = prm->even_odd ? wilson_solve_eo(L, U, m0, fld(b), fld(x), prm->tol, prm->maxiter, tr, it, (char *)ws,
+                                             ws_bytes, S(stream))
+                           : wilson_solve(L, U, m0, fld(b), fld(x), prm->tol, prm->maxiter,
+                                          prm->block > 0 ? prm->block : 16, tr, it, (char *)ws, ws_bytes, S(stream));
     if (rc >= 0 && stats) {
         for (int q = 0; q < b->nrhs; q++) {
             stats->iterations[q] = it[q];

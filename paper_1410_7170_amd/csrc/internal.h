@@ -102,4 +102,10 @@ StencilShape stencil_shape(const Lat &L, int prec, int nrhs);
 // consumer may sum only these (the same sum bit for bit).
 int stencil_partials(const Lat &L, int prec, int nrhs);
 
+// Even-odd reduced Wilson solve (wilson_eo.hip): D_W(m0) x = b per RHS, to
+// |b - D_W x| <= tol |b| (true_res) or maxiter CGLS iterations (iters).
+size_t wilson_solve_eo_ws_bytes(const Lat &L);
+int wilson_solve_eo(const Lat &L, const ovl_gauge *U, double m0, Fld b, Fld x, double tol, int maxiter,
+                    double *true_res, int *iters, char *ws, size_t ws_bytes, hipStream_t st);
+
 }  // namespace ovl

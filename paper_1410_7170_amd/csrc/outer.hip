@@ -10,7 +10,7 @@
 // Optionally each step is right-preconditioned by D_W(m0^prec)^{-1} applied to
 // a relative accuracy eps_prec (Section 3: D_W(m0^prec) shares its
 // eigenvectors with D_N for normal D_W, and eq. (default_m) gives the paper's
-// default m0^prec), computed by ovl_wilson_solve's method.
+// default m0^prec), computed by one of ovl_wilson_solve's two methods.
 // Orthogonalisation: classical Gram-Schmidt applied twice, each pass one
 // batched dot kernel and one batched update kernel; the Hessenberg least-squares
 // problem is solved on the host with complex Givens rotations.
@@ -204,7 +204,8 @@ size_t outer_ws_bytes(const Lat &L, int npoles, const ovl_outer_params *p, const
     c.take(sizeof(double) * 2 * (m + 1));                 // reductions
     c.take(sizeof(double) * 2 * (m + 1));                 // coefficients
     size_t inner = ovl_workspace_bytes(lat, OVL_OP_MSCG, OVL_F64, 1, npoles, &p->inner);
-    if (p->precondition) inner = std::max(inner, wilson_solve_ws_bytes(L, 1, p->prec_block));
+    if (p->precondition)
+        inner = std::max(inner, p->prec_even_odd ? wilson_solve_eo_ws_bytes(L) : wilson_solve_ws_bytes(L, 1, p->prec_block));
     c.take(inner);
     return c.off + 256;
 }
@@ -285,8 +286,11 @@ int overlap_solve(const ovl_lattice *lat, const ovl_gauge *U, double rho, const 
             if (prm->precondition) {
                 double tr;
                 int it = 0;
-                e = wilson_solve(L, U, prm->prec_m0, field(V, j), zj, prm->prec_tol, prm->prec_maxiter,
-                                 prm->prec_block, &tr, &it, iws, iws_bytes, st);
+                e = prm->prec_even_odd
+                        ? wilson_solve_eo(L, U, prm->prec_m0, field(V, j), zj, prm->prec_tol, prm->prec_maxiter, &tr,
+                                          &it, iws, iws_bytes, st)
+                        : wilson_solve(L, U, prm->prec_m0, field(V, j), zj, prm->prec_tol, prm->prec_maxiter,
+                                       prm->prec_block, &tr, &it, iws, iws_bytes, st);
                 if (e < 0) return e;
                 S.prec_iterations += it;
             }

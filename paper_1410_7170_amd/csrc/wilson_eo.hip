@@ -1,0 +1,534 @@
+// Even-odd reduced Wilson solve, the Wilson-Dirac solve that right-
+// preconditions the outer iteration (Section 5.1: D_W(m0^prec)^{-1} applied to
+// a relative residual eps_prec; any efficient Wilson solver may serve).
+//
+// With the sites split by parity (even: x0+x1+x2+x3 even), D_W of eq.
+// (Wilson-Dirac) is the block matrix
+//     D_W = [ A         -H_eo / 2 ]     A = m0 + 4 (a multiple of the identity),
+//           [ -H_oe / 2  A        ]     H the hopping sum of the equation,
+// and eliminating the odd sites leaves the even-site system
+//     M x_e = c,   M = A - H_eo H_oe / (4A),   c = b_e + H_eo b_o / (2A),
+// after which x_o = (b_o + H_oe x_e / 2) / A.  The odd rows of D_W x - b then
+// vanish and its even rows are M x_e - c, so |b - D_W x| = |c - M x_e|.
+// eq. (gamma_5_symmetry) maps H_eo to H_oe^H under Gamma_5, hence
+// M^H = Gamma_5 M Gamma_5.
+//
+// M x_e = c is solved by defect correction.  An FP64 outer loop keeps x_e and
+// the true residual c - M x_e; each of its steps reduces that residual with an
+// FP32 CGLS (CG on M^H M in the form that updates the residual of M itself, so
+// its recursive residual is the reduced system's) and adds the correction to
+// x_e in FP64.  Every field lives in the library's even-odd layout; only the
+// even half of the Krylov vectors carries data, and the odd half of each
+// vector that M is applied to holds the intermediate H_oe v_e / (2A).
+#include <cmath>
+#include <vector>
+
+#include "mscg.h"
+
+namespace ovl {
+
+namespace {
+
+struct EoArgs {
+    Geom g;
+    const void *in;     // hop source, read at parity 1 - p
+    const void *d;      // diagonal source, read at parity p (unused when cd == 0)
+    void *out;          // written at parity p
+    const void *U;
+    double cd, ch;      // out = cd d + ch (Gamma_5) H in
+    double *partials;   // NORM: |out|^2 per block
+    const int *done;    // exit at once when *done (may be null)
+    int p;
+};
+
+// Scalar state of one CGLS run, on the device.
+struct EoState {
+    double gamma;     // |M^H s|^2
+    double alpha, beta;
+    double target2;   // stop when |s|^2 <= target2
+    double ss;        // |s|^2 of the last iteration
+    int done;
+    int iter;
+};
+
+template <typename T>
+__device__ __forceinline__ void neg_upper(cplx<T> s[4][3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        s[0][c] = {-s[0][c].x, -s[0][c].y};
+        s[1][c] = {-s[1][c].x, -s[1][c].y};
+    }
+}
+
+// Both hops in direction MU of the site (p, i) at x, from the parity 1 - p
+// values of in (Gamma_5 applied to each when G5H).
+template <int PREC, int MU, bool G5H>
+__device__ __forceinline__ void eo_hops(const Geom &g, const SpinorRef<PREC> &in, const GaugeRef<PREC> &U, int p,
+                                        int i, const int x[4], cplx<typename Real<PREC>::T> acc[4][3])
+{
+    using T = typename Real<PREC>::T;
+    cplx<T> s[4][3], u[3][3];
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    T ph = (T)1;
+    y[MU] = x[MU] + 1;
+    if (y[MU] == g.L[MU]) { y[MU] = 0; ph = (T)g.bc[MU]; }
+    int j = cb_index(g, y);
+    in.load(1 - p, j, s);
+    if (G5H) neg_upper(s);
+    U.load(p, MU, i, u);
+    hop<T, MU, true>(acc, s, u, ph);
+    ph = (T)1;
+    y[MU] = x[MU] - 1;
+    if (y[MU] < 0) { y[MU] = g.L[MU] - 1; ph = (T)g.bc[MU]; }
+    j = cb_index(g, y);
+    in.load(1 - p, j, s);
+    if (G5H) neg_upper(s);
+    U.load(1 - p, MU, j, u);
+    hop<T, MU, false>(acc, s, u, ph);
+}
+
+// out_p = cd d_p + ch (Gamma_5 if G5O) H_{p,1-p} (Gamma_5 if G5H) in_{1-p}, one
+// thread per site of parity p.
+template <int PREC, bool G5H, bool G5O, bool NORM>
+__global__ __launch_bounds__(kBlock) void k_eo_hop(EoArgs a)
+{
+    using T = typename Real<PREC>::T;
+    __shared__ double lds[8];
+    if (a.done && *a.done) return;
+    const Geom &g = a.g;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int jl = b * kBlock + threadIdx.x;
+    double q = 0.0;
+    if (jl < g.Vh) {
+        int x[4];
+        tiled_coords(g, a.p, jl, x);
+        const int i = cb_index(g, x);
+        const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, nullptr, g.S, 0);
+        const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.S};
+        cplx<T> acc[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[s][c] = {(T)0, (T)0};
+        eo_hops<PREC, 0, G5H>(g, in, U, a.p, i, x, acc);
+        eo_hops<PREC, 1, G5H>(g, in, U, a.p, i, x, acc);
+        eo_hops<PREC, 2, G5H>(g, in, U, a.p, i, x, acc);
+        eo_hops<PREC, 3, G5H>(g, in, U, a.p, i, x, acc);
+        if (G5O) neg_upper(acc);
+        const T ch = (T)a.ch, cd = (T)a.cd;
+        cplx<T> o[4][3];
+        if (a.cd != 0.0) {
+            spinor_ref<PREC>(a.d, nullptr, g.S, 0).load(a.p, i, o);
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    o[s][c] = {fma(ch, acc[s][c].x, cd * o[s][c].x), fma(ch, acc[s][c].y, cd * o[s][c].y)};
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) o[s][c] = {ch * acc[s][c].x, ch * acc[s][c].y};
+        }
+        spinor_ref<PREC>(a.out, nullptr, g.S, 0).store(a.p, i, o);
+        if (NORM) {
+            T n = 0;
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) n += norm2(o[s][c]);
+            q = (double)n;
+        }
+    }
+    if (NORM) {
+        const double t = block_sum(q, lds);
+        if (threadIdx.x == 0) a.partials[blockIdx.x] = t;
+    }
+}
+
+// Even-half vector kernels, one thread per complex component pair of the
+// even parity (flat over the 12 (FP64) or 6 (FP32) component arrays of
+// parity 0, each of stride S, Vh live entries).
+template <int PREC>
+struct Flat;
+template <>
+struct Flat<P_F64> {
+    using E = double2;
+    static constexpr int NC = 12;
+};
+template <>
+struct Flat<P_F32> {
+    using E = float4;
+    static constexpr int NC = 6;
+};
+
+template <typename E>
+__device__ __forceinline__ double sq(const E &v);
+template <>
+__device__ __forceinline__ double sq<double2>(const double2 &v) { return v.x * v.x + v.y * v.y; }
+template <>
+__device__ __forceinline__ double sq<float4>(const float4 &v)
+{
+    return (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+}
+
+// element k of parity 0, k in [0, NC * Vh): component array k / Vh, site k % Vh
+// (a field is [parity][component][S])
+__device__ __forceinline__ size_t even_elem(int k, int Vh, int S) { return (size_t)(k / Vh) * S + k % Vh; }
+
+// Every even-half kernel covers the NC * Vh elements with one thread each and
+// reduces, when asked, |result|^2 into partials[blockIdx.x].
+template <typename E>
+__device__ __forceinline__ void flat_partial(double v, double *partials, double *lds)
+{
+    const double t = block_sum(v, lds);
+    if (threadIdx.x == 0 && partials) partials[blockIdx.x] = t;
+}
+
+// out = a x + b y (y not read when b == 0); partial |out|^2
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_eo_lin(int Vh, int S, double a, const void *x, double b, const void *y,
+                                                    void *out, double *partials)
+{
+    using E = typename Flat<PREC>::E;
+    __shared__ double lds[8];
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    double n = 0.0;
+    if (k < Flat<PREC>::NC * Vh) {
+        const size_t e = even_elem(k, Vh, S);
+        E v = ((const E *)x)[e];
+        if constexpr (PREC == P_F64) {
+            v.x *= a;
+            v.y *= a;
+            if (b != 0.0) {
+                const E w = ((const E *)y)[e];
+                v.x = fma(b, w.x, v.x);
+                v.y = fma(b, w.y, v.y);
+            }
+        } else {
+            const float af = (float)a, bf = (float)b;
+            v.x *= af; v.y *= af; v.z *= af; v.w *= af;
+            if (b != 0.0) {
+                const E w = ((const E *)y)[e];
+                v.x = fmaf(bf, w.x, v.x); v.y = fmaf(bf, w.y, v.y);
+                v.z = fmaf(bf, w.z, v.z); v.w = fmaf(bf, w.w, v.w);
+            }
+        }
+        ((E *)out)[e] = v;
+        n = sq(v);
+    }
+    flat_partial<E>(n, partials, lds);
+}
+
+// FP64 even half -> FP32 even half, partial |src|^2 (FP64); zero: dst = 0
+__global__ __launch_bounds__(kBlock) void k_eo_round(int Vh, int S, const double2 *src, float4 *dst, double *partials)
+{
+    __shared__ double lds[8];
+    const int k = blockIdx.x * kBlock + threadIdx.x;   // FP32 element: two FP64 elements
+    double n = 0.0;
+    if (k < 6 * Vh) {
+        const int c = k / Vh, i = k % Vh;
+        const double2 a = src[(size_t)(2 * c) * S + i], b = src[(size_t)(2 * c + 1) * S + i];
+        dst[(size_t)c * S + i] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        n = a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y;
+    }
+    flat_partial<double2>(n, partials, lds);
+}
+
+// x (FP64 even half) += e (FP32 even half); first: x = e
+__global__ __launch_bounds__(kBlock) void k_eo_accum(int Vh, int S, const float4 *e, double2 *x, int first)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= 6 * Vh) return;
+    const int c = k / Vh, i = k % Vh;
+    const float4 v = e[(size_t)c * S + i];
+    double2 &a = x[(size_t)(2 * c) * S + i];
+    double2 &b = x[(size_t)(2 * c + 1) * S + i];
+    if (first) {
+        a = make_double2((double)v.x, (double)v.y);
+        b = make_double2((double)v.z, (double)v.w);
+    } else {
+        a.x += (double)v.x;
+        a.y += (double)v.y;
+        b.x += (double)v.z;
+        b.y += (double)v.w;
+    }
+}
+
+// fixed-order sum of n partials by one block (thread t sums t, t + 256, ...
+// in order, then the block's fixed shuffle order)
+__device__ __forceinline__ double sum_partials(const double *p, int n, double *lds)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += kBlock) v += p[k];
+    return block_sum(v, lds);
+}
+
+// CGLS start: s = r (already in place), z = M^H s with gamma = |z|^2 from its
+// partials, |s|^2 from the rounding's partials; target2 = (delta |s|)^2
+__global__ __launch_bounds__(kBlock) void k_eo_start(EoState *st, const double *pz, int nz, const double *ps, int ns,
+                                                      double delta)
+{
+    __shared__ double lds[8];
+    const double zz = sum_partials(pz, nz, lds);
+    const double ss = sum_partials(ps, ns, lds);
+    if (threadIdx.x == 0) {
+        st->gamma = zz;
+        st->ss = ss;
+        st->target2 = delta * delta * ss;
+        st->iter = 0;
+        st->alpha = st->beta = 0.0;
+        st->done = !(zz > 0.0) || !(ss > st->target2);
+    }
+}
+
+// alpha = gamma / |q|^2
+__global__ __launch_bounds__(kBlock) void k_eo_alpha(EoState *st, const double *pq, int n)
+{
+    __shared__ double lds[8];
+    if (st->done) return;
+    const double qq = sum_partials(pq, n, lds);
+    if (threadIdx.x == 0) {
+        if (qq > 0.0 && std::isfinite(qq)) {
+            st->alpha = st->gamma / qq;
+        } else {
+            st->alpha = 0.0;
+            st->done = 2;
+        }
+    }
+}
+
+// e += alpha p, s -= alpha q (FP32 even halves); partial |s|^2
+__global__ __launch_bounds__(kBlock) void k_eo_update(int Vh, int S, const EoState *st, const float4 *p,
+                                                       const float4 *q, float4 *e, float4 *s, double *partials)
+{
+    __shared__ double lds[8];
+    if (st->done) return;
+    const float al = (float)st->alpha;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    double n = 0.0;
+    if (k < 6 * Vh) {
+        const size_t x = even_elem(k, Vh, S);
+        const float4 pv = p[x], qv = q[x];
+        float4 ev = e[x], sv = s[x];
+        ev.x = fmaf(al, pv.x, ev.x); ev.y = fmaf(al, pv.y, ev.y);
+        ev.z = fmaf(al, pv.z, ev.z); ev.w = fmaf(al, pv.w, ev.w);
+        sv.x = fmaf(-al, qv.x, sv.x); sv.y = fmaf(-al, qv.y, sv.y);
+        sv.z = fmaf(-al, qv.z, sv.z); sv.w = fmaf(-al, qv.w, sv.w);
+        e[x] = ev;
+        s[x] = sv;
+        n = sq(sv);
+    }
+    flat_partial<float4>(n, partials, lds);
+}
+
+// beta = |z|^2 / gamma, gamma = |z|^2; stop on |s|^2 <= target2
+__global__ __launch_bounds__(kBlock) void k_eo_beta(EoState *st, const double *pz, int nz, const double *ps, int ns)
+{
+    __shared__ double lds[8];
+    if (st->done) return;
+    const double zz = sum_partials(pz, nz, lds);
+    const double ss = sum_partials(ps, ns, lds);
+    if (threadIdx.x == 0) {
+        st->iter += 1;
+        st->ss = ss;
+        if (!std::isfinite(zz) || !std::isfinite(ss)) {
+            st->done = 3;
+        } else if (ss <= st->target2 || !(zz > 0.0)) {
+            st->done = 1;
+        } else {
+            st->beta = zz / st->gamma;
+            st->gamma = zz;
+        }
+    }
+}
+
+// p = z + beta p (FP32 even halves)
+__global__ __launch_bounds__(kBlock) void k_eo_dir(int Vh, int S, const EoState *st, const float4 *z, float4 *p)
+{
+    if (st->done) return;
+    const float be = (float)st->beta;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= 6 * Vh) return;
+    const size_t x = even_elem(k, Vh, S);
+    const float4 zv = z[x];
+    float4 pv = p[x];
+    pv.x = fmaf(be, pv.x, zv.x); pv.y = fmaf(be, pv.y, zv.y);
+    pv.z = fmaf(be, pv.z, zv.z); pv.w = fmaf(be, pv.w, zv.w);
+    p[x] = pv;
+}
+
+template <int PREC, bool G5H, bool G5O, bool NORM>
+hipError_t eo_hop(const Lat &L, int p, const void *in, const void *d, void *out, const void *U, double cd, double ch,
+                  double *partials, const int *done, hipStream_t st)
+{
+    EoArgs a{};
+    a.g = L.g;
+    a.in = in;
+    a.d = d;
+    a.out = out;
+    a.U = U;
+    a.cd = cd;
+    a.ch = ch;
+    a.partials = partials;
+    a.done = done;
+    a.p = p;
+    k_eo_hop<PREC, G5H, G5O, NORM><<<(L.Vh + kBlock - 1) / kBlock, kBlock, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// Blocks of the flat even-half launches (FP64 and FP32 alike cover 6 * Vh
+// FP32-sized or 12 * Vh FP64 elements; the partial-sum buffers hold the larger).
+inline int flat_blocks(const Lat &L, int nc) { return (nc * L.Vh + kBlock - 1) / kBlock; }
+
+}  // namespace
+
+size_t wilson_solve_eo_ws_bytes(const Lat &L)
+{
+    WsCarve c{nullptr, 0, 0};
+    const size_t F64 = field_bytes(P_F64, L.V), F32 = field_bytes(P_F32, L.V);
+    c.take(F64 * 2);                                      // c, r
+    c.take(F32 * 5);                                      // s, e, p, q, z
+    c.take(sizeof(double) * 2 * flat_blocks(L, 12));      // partials
+    c.take(sizeof(EoState));
+    c.take(sizeof(double) * 2 * site_blocks(L));          // full-field norms
+    c.take(sizeof(double) * 2);
+    return c.off + 256;
+}
+
+// D_W(m0) x = b for each RHS of b (FP64), x FP64 and distinct from b; stops
+// when |b - D_W x| <= tol |b| or after maxiter CGLS iterations (iters[q]).
+// true_res[q] is |c - M x_e| / |b| from the last FP64 residual, which is
+// |b - D_W x| / |b| up to FP64 rounding since x_o is formed from x_e exactly
+// as the reduction prescribes.  Returns OVL_OK, OVL_NOT_CONVERGED or an error.
+int wilson_solve_eo(const Lat &L, const ovl_gauge *U, double m0, Fld b, Fld x, double tol, int maxiter,
+                    double *true_res, int *iters, char *ws, size_t ws_bytes, hipStream_t st)
+{
+    if (!U->f64 || !U->f32 || b.nrhs > NR || b.nrhs != x.nrhs) return OVL_ERR_INVALID;
+    if (ws_bytes < wilson_solve_eo_ws_bytes(L)) return OVL_ERR_WORKSPACE;
+    const double A = m0 + 4.0;
+    if (!(std::fabs(A) > 0.0)) return OVL_ERR_INVALID;
+    WsCarve cv{ws, 0, ws_bytes};
+    const size_t F64 = field_bytes(P_F64, L.V), F32 = field_bytes(P_F32, L.V);
+    char *C = (char *)cv.take(F64), *R = (char *)cv.take(F64);
+    char *Sf = (char *)cv.take(F32), *Ef = (char *)cv.take(F32), *Pf = (char *)cv.take(F32),
+         *Qf = (char *)cv.take(F32), *Zf = (char *)cv.take(F32);
+    const int nf64 = flat_blocks(L, 12), nf32 = flat_blocks(L, 6), nh = (L.Vh + kBlock - 1) / kBlock;
+    double *p0 = (double *)cv.take(sizeof(double) * 2 * nf64);
+    double *p1 = p0 + nf64;
+    EoState *es = (EoState *)cv.take(sizeof(EoState));
+    double *fpart = (double *)cv.take(sizeof(double) * 2 * site_blocks(L));
+    double *fred = (double *)cv.take(sizeof(double) * 2);
+    const int Vh = L.Vh, S = L.g.S;
+    const int *done = &es->done;
+    const double ih = 0.5 / A;   // 1 / (2A)
+    int rc = OVL_OK;
+
+    auto host_sum = [&](const double *parts, int n, double *out) -> int {
+        OVL_HIP(launch_reduce(parts, 1, 1, n, fred, st));
+        OVL_HIP(hipMemcpyAsync(out, fred, sizeof(double), hipMemcpyDeviceToHost, st));
+        OVL_HIP(hipStreamSynchronize(st));
+        return OVL_OK;
+    };
+
+    for (int q = 0; q < b.nrhs; q++) {
+        const Fld bq = sub(b, L.V, q, 1), xq = sub(x, L.V, q, 1);
+        iters[q] = 0;
+        // |b|^2 over both parities and |c|^2, c = b_e + H_eo b_o / (2A), in one
+        // round trip; the first residual (x_e = 0) is c itself
+        OVL_HIP(launch_norm2(L, bq, fpart, st));
+        OVL_HIP(launch_reduce(fpart, 1, 1, site_blocks(L), fred, st));
+        OVL_HIP((eo_hop<P_F64, false, false, true>(L, 0, bq.d, bq.d, C, U->f64, 1.0, ih, p0, nullptr, st)));
+        OVL_HIP(launch_reduce(p0, 1, 1, nh, fred + 1, st));
+        double hb[2];
+        OVL_HIP(hipMemcpyAsync(hb, fred, sizeof hb, hipMemcpyDeviceToHost, st));
+        OVL_HIP(hipStreamSynchronize(st));
+        const double bn = std::sqrt(hb[0]);
+        double rr = hb[1];
+        const char *Rcur = C;
+        int e = OVL_OK, status = OVL_OK;
+        bool stalled = false;
+        int outer = 0;
+        for (;; outer++) {
+            const double rn = std::sqrt(rr);
+            if (!std::isfinite(rn)) return OVL_ERR_NONFINITE;
+            if (rn <= tol * bn) break;
+            if (iters[q] >= maxiter || outer >= 64 || stalled) {
+                status = OVL_NOT_CONVERGED;
+                break;
+            }
+            // FP32 CGLS on M e = r to |s| <= delta |r|: FP32 reaches about
+            // 1e-5 of its start, so the outer loop asks for no more per step
+            const double delta = std::min(0.5, std::max(0.8 * tol * bn / rn, 1e-5));
+            k_eo_round<<<nf32, kBlock, 0, st>>>(Vh, S, (const double2 *)Rcur, (float4 *)Sf, p1);
+            OVL_HIP(hipGetLastError());
+            k_eo_lin<P_F32><<<nf32, kBlock, 0, st>>>(Vh, S, 0.0, Sf, 0.0, nullptr, Ef, nullptr);
+            OVL_HIP(hipGetLastError());
+            // z = M^H s = A s - (1/2) Gamma_5 H_eo [H_oe Gamma_5 s / (2A)], the
+            // bracket in the odd half of s
+            OVL_HIP((eo_hop<P_F32, true, false, false>(L, 1, Sf, nullptr, Sf, U->f32, 0.0, ih, nullptr, nullptr, st)));
+            OVL_HIP((eo_hop<P_F32, false, true, true>(L, 0, Sf, Sf, Zf, U->f32, A, -0.5, p0, nullptr, st)));
+            k_eo_start<<<1, kBlock, 0, st>>>(es, p0, nh, p1, nf32, delta);
+            OVL_HIP(hipGetLastError());
+            k_eo_lin<P_F32><<<nf32, kBlock, 0, st>>>(Vh, S, 1.0, Zf, 0.0, nullptr, Pf, nullptr);
+            OVL_HIP(hipGetLastError());
+            int chunk = std::min(4, maxiter - iters[q]);
+            for (;;) {
+                for (int k = 0; k < chunk; k++) {
+                    // q = M p = A p - (1/2) H_eo [H_oe p / (2A)], the bracket in p's odd half
+                    OVL_HIP((eo_hop<P_F32, false, false, false>(L, 1, Pf, nullptr, Pf, U->f32, 0.0, ih, nullptr,
+                                                                 done, st)));
+                    OVL_HIP((eo_hop<P_F32, false, false, true>(L, 0, Pf, Pf, Qf, U->f32, A, -0.5, p0, done, st)));
+                    k_eo_alpha<<<1, kBlock, 0, st>>>(es, p0, nh);
+                    OVL_HIP(hipGetLastError());
+                    k_eo_update<<<nf32, kBlock, 0, st>>>(Vh, S, es, (const float4 *)Pf, (const float4 *)Qf,
+                                                        (float4 *)Ef, (float4 *)Sf, p1);
+                    OVL_HIP(hipGetLastError());
+                    OVL_HIP((eo_hop<P_F32, true, false, false>(L, 1, Sf, nullptr, Sf, U->f32, 0.0, ih, nullptr,
+                                                                done, st)));
+                    OVL_HIP((eo_hop<P_F32, false, true, true>(L, 0, Sf, Sf, Zf, U->f32, A, -0.5, p0, done, st)));
+                    k_eo_beta<<<1, kBlock, 0, st>>>(es, p0, nh, p1, nf32);
+                    OVL_HIP(hipGetLastError());
+                    k_eo_dir<<<nf32, kBlock, 0, st>>>(Vh, S, es, (const float4 *)Zf, (float4 *)Pf);
+                    OVL_HIP(hipGetLastError());
+                }
+                EoState h;
+                OVL_HIP(hipMemcpyAsync(&h, es, sizeof h, hipMemcpyDeviceToHost, st));
+                OVL_HIP(hipStreamSynchronize(st));
+                if (h.done == 3) return OVL_ERR_NONFINITE;
+                if (h.done || iters[q] + h.iter >= maxiter) {
+                    iters[q] += h.iter;
+                    // no step taken (M p = 0, or a residual below FP32's range)
+                    if (h.iter == 0) stalled = true;
+                    break;
+                }
+                chunk = std::min(2 * chunk, std::min(16, maxiter - iters[q] - h.iter));
+            }
+            // x_e += e; r = c - M x_e in FP64, the bracket H_oe x_e / (2A) in x's odd half
+            k_eo_accum<<<nf32, kBlock, 0, st>>>(Vh, S, (const float4 *)Ef, (double2 *)xq.d, outer == 0);
+            OVL_HIP(hipGetLastError());
+            OVL_HIP((eo_hop<P_F64, false, false, false>(L, 1, xq.d, nullptr, xq.d, U->f64, 0.0, ih, nullptr,
+                                                         nullptr, st)));
+            OVL_HIP((eo_hop<P_F64, false, false, false>(L, 0, xq.d, xq.d, R, U->f64, A, -0.5, nullptr, nullptr,
+                                                         st)));
+            k_eo_lin<P_F64><<<nf64, kBlock, 0, st>>>(Vh, S, -1.0, R, 1.0, C, R, p0);
+            OVL_HIP(hipGetLastError());
+            Rcur = R;
+            if ((e = host_sum(p0, nf64, &rr))) return e;
+        }
+        if (outer == 0) {   // no correction made: x_e = 0
+            k_eo_lin<P_F64><<<nf64, kBlock, 0, st>>>(Vh, S, 0.0, C, 0.0, nullptr, xq.d, nullptr);
+            OVL_HIP(hipGetLastError());
+        }
+        // x_o = (b_o + H_oe x_e / 2) / A
+        OVL_HIP((eo_hop<P_F64, false, false, false>(L, 1, xq.d, bq.d, xq.d, U->f64, 1.0 / A, ih, nullptr, nullptr,
+                                                     st)));
+        if (status != OVL_OK) rc = status;
+        true_res[q] = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+        if (!std::isfinite(true_res[q])) return OVL_ERR_NONFINITE;
+    }
+    return rc;
+}
+
+}  // namespace ovl

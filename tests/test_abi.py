@@ -274,3 +274,29 @@ def test_new_descriptor_fields_validated(ovl):
             == ovl.ERR_INVALID, field
     p = ovl.default_params(mode=ovl.SOLVE_MIXED, sloppy_f16=2)
     assert lib.ovl_workspace_bytes(lat.ref, ovl.OP_MSCG, ovl.F64, 1, 2, ctypes.byref(p)) == 0
+
+
+def test_even_odd_wilson_solve_fields(ovl):
+    """even_odd in {0, 1} (default 0) for ovl_wilson_solve, with its own
+    workspace size; prec_even_odd in {0, 1} (default 1) for the outer solve.
+    Both are checked before any device work."""
+    lat = ovl.Lattice((4, 4, 4, 8))
+    lib = ovl._lib
+    assert ovl.default_params().even_odd == 0 and ovl.default_outer_params().prec_even_odd == 1
+    ws = [lib.ovl_workspace_bytes(lat.ref, ovl.OP_WILSON_SOLVE, ovl.F64, 1, 0,
+                                  ctypes.byref(ovl.default_params(even_odd=eo))) for eo in (0, 1)]
+    assert ws[0] > 0 and ws[1] > 0 and ws[0] != ws[1]
+    gf = ovl.ovl_gauge(ctypes.c_void_p(8192), ctypes.c_void_p(8192), None)
+    b = ovl.ovl_spinor(ctypes.c_void_p(4096), None, ovl.F64, 1)
+    x = ovl.ovl_spinor(ctypes.c_void_p(1 << 20), None, ovl.F64, 1)
+    st = ovl.ovl_solver_stats()
+    for eo in (2, -1):
+        p = ovl.default_params(even_odd=eo)
+        assert lib.ovl_wilson_solve(lat.ref, ctypes.byref(gf), -0.5, ctypes.byref(b), ctypes.byref(x),
+                                    ctypes.byref(p), ctypes.byref(st), ctypes.c_void_p(1 << 24), 1 << 30,
+                                    None) == ovl.ERR_INVALID
+        assert lib.ovl_workspace_bytes(lat.ref, ovl.OP_WILSON_SOLVE, ovl.F64, 1, 0, ctypes.byref(p)) == 0
+        q = ovl.default_outer_params(precondition=1, prec_m0=-0.5, prec_even_odd=eo)
+        assert lib.ovl_overlap_solve_workspace_bytes(lat.ref, 12, ctypes.byref(q)) == 0
+    q = ovl.default_outer_params(precondition=1, prec_m0=-0.5, prec_even_odd=1)
+    assert lib.ovl_overlap_solve_workspace_bytes(lat.ref, 12, ctypes.byref(q)) > 0

@@ -67,6 +67,78 @@ def test_wilson_solve_matches_oracle(ovl, m0):
         assert ratio <= 1.0
 
 
+@pytest.mark.parametrize("m0", [-0.6, 0.3, -1.2])
+def test_wilson_solve_even_odd_matches_oracle(ovl, m0):
+    """The even-odd form (Schur complement on the even sites, FP32 CGLS in
+    FP64 defect correction): x against the oracle's GMRES solution site by
+    site, the returned true residual against the oracle's D_W, and fewer
+    Krylov iterations than the normal-equations CG on the full lattice."""
+    dims = (8, 4, 4, 8)
+    note(f"wilson solve even-odd m0={m0}")
+    lat, olat = ovl.Lattice(dims), oracle.Lattice(dims)
+    U = synth.gauge(dims, 0.3, 91, n_stout=2)
+    G = ovl.Gauge(lat, dev(U))
+    b = synth.gaussian_spinor(lat.V, 92, 2)
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    X = ovl.Spinor(lat, 0, 2)
+    st = ovl.wilson_solve(lat, G, m0, B, X, ovl.default_params(tol=1e-11, maxiter=3000, even_odd=1))
+    full = ovl.wilson_solve(lat, G, m0, B, ovl.Spinor(lat, 0, 2), ovl.default_params(tol=1e-11, maxiter=3000))
+    x = X.to_canonical().cpu().numpy()
+    for r in range(2):
+        res = np.linalg.norm(b[r] - oracle.dw(olat, U, m0, x[r])) / np.linalg.norm(b[r])
+        assert abs(res - st["true_residual"][r]) <= 1e-3 * res + 1e-14, (res, st["true_residual"][r])
+        assert res <= 1e-11, res
+        ref, it, ores = krylov.gmres(lambda v: oracle.dw(olat, U, m0, v), b[r], 1e-13, restart=100)
+        ratio, r2 = field_check(x[r], ref, dims, 1e-8)
+        note(f"  rhs {r}: {st['iterations'][r]} CGLS iterations (normal equations on the full lattice: "
+             f"{full['iterations'][r]}), residual {res:.2e}, worst/bound {ratio:.3g}")
+        assert ratio <= 1.0
+        assert st["iterations"][r] < full["iterations"][r]
+
+
+def test_wilson_solve_even_odd_edge_cases(ovl):
+    """A zero RHS returns x = 0 with no iterations; a loose tolerance (the
+    preconditioner's 1e-1) stops after one defect-correction step with the
+    true residual below it; a capped run reports OVL_NOT_CONVERGED with its
+    iterations at the cap; m0 = -4 (no diagonal to divide by) is rejected."""
+    dims = (4, 4, 4, 8)
+    lat, olat = ovl.Lattice(dims), oracle.Lattice(dims)
+    U = synth.gauge(dims, 0.3, 94, n_stout=1)
+    G = ovl.Gauge(lat, dev(U))
+    b = np.concatenate([synth.gaussian_spinor(lat.V, 95, 1), np.zeros((1, lat.V, 4, 3), complex)])
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    X = ovl.Spinor(lat, 0, 2)
+    st = ovl.wilson_solve(lat, G, -0.8, B, X, ovl.default_params(tol=1e-1, even_odd=1))
+    x = X.to_canonical().cpu().numpy()
+    assert st["iterations"][1] == 0 and st["true_residual"][1] == 0.0 and not np.any(x[1])
+    res = np.linalg.norm(b[0] - oracle.dw(olat, U, -0.8, x[0])) / np.linalg.norm(b[0])
+    note(f"  tol 1e-1: {st['iterations'][0]} iterations, residual {res:.3e}")
+    assert 0 < res <= 1e-1 and abs(res - st["true_residual"][0]) <= 1e-6 * res
+    st = ovl.wilson_solve(lat, G, -0.8, B, X, ovl.default_params(tol=1e-12, maxiter=5, even_odd=1),
+                          allow_not_converged=True)
+    assert st["iterations"][0] == 5 and st["true_residual"][0] > 1e-12
+    with pytest.raises(ovl.OvlError):
+        ovl.wilson_solve(lat, G, -4.0, B, X, ovl.default_params(even_odd=1))
+
+
+@pytest.mark.parametrize("dims,m0", [((32, 16, 16, 16), -0.5), ((64, 32, 32, 32), -0.5)])
+def test_wilson_solve_even_odd_workload_sizes(ovl, dims, m0):
+    """At the workload sizes the oracle's D_W checks the true residual of the
+    even-odd solve (a property that holds at any size)."""
+    note(f"wilson solve even-odd {dims} m0={m0}")
+    lat, olat = ovl.Lattice(dims), oracle.Lattice(dims)
+    U = synth.gauge(dims, 0.3, 97, n_stout=1) if dims[0] <= 32 else synth.workload_gauge(2)
+    G = ovl.Gauge(lat, dev(U))
+    b = synth.gaussian_spinor(lat.V, 98)
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    X = ovl.Spinor(lat, 0)
+    st = ovl.wilson_solve(lat, G, m0, B, X, ovl.default_params(tol=1e-10, maxiter=5000, even_odd=1))
+    x = X.to_canonical().cpu().numpy()[0]
+    res = np.linalg.norm(b[0] - oracle.dw(olat, U, m0, x)) / np.linalg.norm(b[0])
+    note(f"  {st['iterations'][0]} CGLS iterations, {st['seconds']:.3f} s, oracle residual {res:.2e}")
+    assert res <= 1e-10 and abs(res - st["true_residual"][0]) <= 1e-3 * res
+
+
 def sigma_min_4x4(U):
     """Smallest real part of the eigenvalues of D_W(0) on 4^4 (dense)."""
     D = dense.dense_dw(oracle.Lattice((4, 4, 4, 4)), U, 0.0)
@@ -95,20 +167,21 @@ def test_overlap_solve_4x4_with_and_without_wilson_preconditioner(ovl, n_stout):
     sig = sigma_min_4x4(U)
     m0_prec = (-M0 - sig) + M0
     runs = {}
-    for prec in (0, 1):
+    for prec, eo in ((0, 1), (1, 0), (1, 1)):
         Psi = ovl.Spinor(lat, 0)
-        prm = ovl.default_outer_params(tol=tol, precondition=prec, prec_m0=m0_prec)
+        prm = ovl.default_outer_params(tol=tol, precondition=prec, prec_m0=m0_prec, prec_even_odd=eo)
         st = ovl.overlap_solve(lat, G, RHO, s, wt, E, Psi, prm)
         psi = Psi.to_canonical().cpu().numpy()[0]
         ores = np.linalg.norm(eta - oracle.overlap(olat, U, RHO, s, wt, psi, 1e-13, 5000)[0]) / np.linalg.norm(eta)
         err = rel_l2(psi, exact)
-        note(f"  precondition={prec}: {st['iterations']} steps, {st['restarts']} restarts, {st['mscg_iterations']} "
+        note(f"  precondition={prec} even_odd={eo}: {st['iterations']} steps, {st['restarts']} restarts, {st['mscg_iterations']} "
              f"MSCG iterations, {st['prec_iterations']} preconditioner iterations, residual {st['residual']:.2e} "
              f"(oracle {ores:.2e}), error {err:.2e}, cond {cond:.1f}")
         assert st["residual"] <= tol and ores <= 2 * tol, (st, ores)
         assert err <= cond * (2 * tol + 10 * delta), err
-        runs[prec] = st
-    assert runs[1]["iterations"] < runs[0]["iterations"], runs
+        runs[(prec, eo)] = st
+    assert runs[(1, 0)]["iterations"] < runs[(0, 1)]["iterations"], runs
+    assert runs[(1, 1)]["iterations"] < runs[(0, 1)]["iterations"], runs
 
 
 def test_overlap_solve_matches_oracle_gmres_and_relaxation_saves_work(ovl):

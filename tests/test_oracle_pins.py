@@ -532,3 +532,35 @@ def test_deflated_zolotarev_meets_the_deflated_bound(lat44, U44, dense44, modes4
     err_plain = rel(apply(chi), exact)
     assert err_defl <= 1.05 * delta + 1e-12
     assert err_plain > 10 * err_defl
+
+
+def test_even_odd_reduction_of_the_wilson_system(lat44, U44, dense44):
+    """The even-odd reduction behind ovl_wilson_solve's even_odd form, on the
+    dense 4^4 D_W of eq. (Wilson-Dirac): the hops join opposite parities, so
+    the parity-diagonal blocks are (m0+4) I; the solution of D_W x = b has
+    x_e solving the Schur complement system M x_e = b_e - D_eo D_oo^{-1} b_o
+    and x_o = D_oo^{-1}(b_o - D_oe x_e); Gamma_5 M Gamma_5 = M^H (the form of
+    M^H the CGLS applies); and for any x_e with that x_o the full residual
+    has the norm of the reduced one."""
+    L = lat44.dims
+    x = np.indices(L).reshape(4, -1)                   # canonical sites, x3 fastest
+    par = np.repeat(x.sum(0) % 2, 12)                  # parity of each (site, spin, colour)
+    e, o = np.flatnonzero(par == 0), np.flatnonzero(par == 1)
+    D, G5 = dense44["D"], dense44["G5"]
+    A = M0 + 4.0
+    assert np.array_equal(D[np.ix_(e, e)], A * np.eye(e.size))
+    assert np.array_equal(D[np.ix_(o, o)], A * np.eye(o.size))
+    Deo, Doe = D[np.ix_(e, o)], D[np.ix_(o, e)]
+    M = A * np.eye(e.size) - Deo @ Doe / A
+    # with D_eo = -H_eo / 2: M = A - H_eo H_oe / (4A) and c = b_e + H_eo b_o / (2A)
+    b = synth.gaussian_spinor(lat44.V, 931)[0].reshape(-1)
+    xs = np.linalg.solve(D, b)
+    c = b[e] - Deo @ b[o] / A
+    assert rel(M @ xs[e], c) < 1e-12
+    assert rel((b[o] - Doe @ xs[e]) / A, xs[o]) < 1e-12
+    G5e = G5[np.ix_(e, e)]
+    assert np.abs(G5e @ M @ G5e - M.conj().T).max() < 1e-13
+    xe = synth.gaussian_spinor(lat44.V, 932)[0].reshape(-1)[e]
+    full = np.empty_like(b)
+    full[e], full[o] = xe, (b[o] - Doe @ xe) / A
+    assert abs(np.linalg.norm(b - D @ full) - np.linalg.norm(c - M @ xe)) < 1e-12 * np.linalg.norm(b)

@@ -307,6 +307,8 @@ def main():
     best64 = min((f for f in results if f.startswith("fp64")), key=lambda f: results[f]["seconds"])
     best64_rate = nrhs / results[best64]["seconds"]
 
+    wsolve = wilson_solves(ovl, torch, lat, G, B) if not args.no_checks else None
+
     # ---- the small workload and the batched multi-RHS workload (own lattices)
     del G, B, out, start
     torch.cuda.empty_cache()
@@ -361,6 +363,7 @@ def main():
         "accuracy": checks,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "wilson_solve": wsolve,
         "small": small,
         "multi_rhs": mrhs,
         "big": big,
@@ -448,13 +451,14 @@ def small_line(args, ovl, synth, np, torch):
         if form == "mixed":
             ref_mixed = out.to_canonical()
     log(f"small {dims}: {rates}")
+    wsolve = wilson_solves(ovl, torch, lat, G, B)
     outer = None if args.no_outer else outer_line(ovl, torch, lat, G, shifts, weights, B)
     defl = None
     if args.deflate_nev > 0:
         defl = deflation_line(args, ovl, synth, torch, lat, G, B, ref_mixed, hi, delta, rates["mixed"]["applies_per_s"],
                               cfg)
     return dict(workload=f"{dims[1]}^3x{dims[0]}, {c['poles']} Zolotarev poles, tol {args.tol:g}",
-                operators=ops, overlap=rates, outer_solve=outer, deflation=defl)
+                operators=ops, overlap=rates, wilson_solve=wsolve, outer_solve=outer, deflation=defl)
 
 
 def deflation_line(args, ovl, synth, torch, lat, G, B, ref, hi, delta, rate_plain, cfg):
@@ -537,6 +541,30 @@ def outer_line(ovl, torch, lat, G, shifts, weights, E):
         log(f"outer solve {kw}: {sec:.2f}s, {st['iterations']} steps, {st['mscg_iterations']} MSCG iterations, "
             f"{st['prec_iterations']} CG iterations, residual {st['residual']:.2e}")
     return dict(tol=1e-8, restart=100, inner="mixed", runs=runs)
+
+
+def wilson_solves(ovl, torch, lat, G, B):
+    """ovl_wilson_solve in its two forms (normal equations on the full
+    lattice, even-odd reduced system) at a tight tolerance and at the
+    preconditioner's eps_prec, average of 3 solves each."""
+    X = ovl.Spinor(lat, ovl.F64)
+    runs = []
+    for m0, tol in ((-0.5, 1e-10), (0.0, 1e-1)):
+        for eo in (0, 1):
+            prm = ovl.default_params(tol=tol, maxiter=20000, even_odd=eo)
+            ws = ovl.workspace(lat, ovl.OP_WILSON_SOLVE, ovl.F64, 1, 0, prm, device="cuda")
+            ovl.wilson_solve(lat, G, m0, B, X, prm, ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                st = ovl.wilson_solve(lat, G, m0, B, X, prm, ws=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / 3 * 1e3
+            runs.append(dict(m0=m0, tol=tol, form="even_odd" if eo else "normal_equations", ms=round(ms, 3),
+                             iterations=st["iterations"][0], true_residual=st["true_residual"][0]))
+            log(f"wilson solve m0 {m0} tol {tol:g} {runs[-1]['form']}: {ms:.2f} ms, {st['iterations'][0]} it, "
+                f"true residual {st['true_residual'][0]:.2e}")
+    return runs
 
 
 def big_line(args, ovl, synth, np, torch):

@@ -68,6 +68,11 @@ def parse():
     ap.add_argument("--stencil-forms-only", action="store_true",
                     help="run only the multi-RHS stencil comparison (vector form, RHS tiles, matrix cores) "
                          "on the batched workload's lattice and print it as the JSON line (profiling runs)")
+    ap.add_argument("--outer-only", action="store_true",
+                    help="run only the outer-solve line on the small workload and print it as the JSON line "
+                         "(profiling runs)")
+    ap.add_argument("--outer-cases", default="",
+                    help="comma-separated indices of the outer-solve cases to run (default all)")
     ap.add_argument("--stencil-order", default="",
                     help="tile_t,stream_t,stream_t64[,rhs_tile] for the main workload instead of autotuning "
                          "(profiling runs pin the order the timed run chose)")
@@ -199,6 +204,12 @@ def main():
     if args.stencil_forms_only:
         print(json.dumps(dict(metric="multi-RHS stencil forms", data="synthetic",
                               stencil_forms=stencil_forms(args, ovl, synth, np, torch))))
+        return
+    if args.outer_only:
+        lat, G, shifts, weights, B = small_setup(args, ovl, synth, torch)
+        print(json.dumps(dict(metric="outer solve", data="synthetic",
+                              outer_solve=outer_line(ovl, torch, lat, G, shifts, weights, B,
+                                                     args.outer_cases))))
         return
     cfg = synth.WORKLOADS[args.workload]
     dims = cfg["dims"]
@@ -414,6 +425,22 @@ def accuracy_checks(args, ovl, torch, np, lat, B, out, got, overlap, form):
     return res
 
 
+def small_setup(args, ovl, synth, torch):
+    """Lattice, links, Zolotarev poles on the Lanczos interval and the source
+    of the small workload (16^3x32)."""
+    cfg = args.small
+    c = synth.WORKLOADS[cfg]
+    lat = ovl.Lattice(c["dims"])
+    G = ovl.Gauge(lat, torch.from_numpy(synth.workload_gauge(cfg)).cuda())
+    v0 = synth.gaussian_spinor(lat.V, synth.SEED_BASE + 10 * cfg + 3)[0]
+    lo, hi = ovl.spectral_bounds(lat, G, -RHO, 300, ovl.Spinor.from_canonical(lat, torch.from_numpy(v0).cuda(),
+                                                                                ovl.F64))
+    shifts, weights, delta = ovl.zolotarev(lo, hi, c["poles"])
+    ovl.autotune_stencil(lat, G, 1)
+    B = ovl.Spinor.from_canonical(lat, torch.from_numpy(synth.workload_sources(cfg)).cuda(), ovl.F64)
+    return lat, G, shifts, weights, B
+
+
 def small_line(args, ovl, synth, np, torch):
     """The 16^3x32 workload: wilson_apply and q2_apply bandwidth in every
     precision and the overlap apply's rate in the FP64 and mixed forms."""
@@ -518,7 +545,7 @@ def deflation_line(args, ovl, synth, torch, lat, G, B, ref, hi, delta, rate_plai
     return line
 
 
-def outer_line(ovl, torch, lat, G, shifts, weights, E):
+def outer_line(ovl, torch, lat, G, shifts, weights, E, only=""):
     """D_ov psi = eta (eq. (linsys)) by FGMRES(100) to 1e-8: with the relaxed
     sign accuracy of Table (allparms1) and without it, and with the Wilson
     preconditioner D_W(m0^prec)^{-1} (eps_prec 0.1) at a few masses m0^prec
@@ -529,6 +556,8 @@ def outer_line(ovl, torch, lat, G, shifts, weights, E):
     cases = [dict(relax=1), dict(relax=0)] + [dict(relax=1, precondition=1, prec_m0=m) for m in (-0.1, 0.0, 0.1)]
     # the same preconditioner solved through the normal equations of the full lattice
     cases.append(dict(relax=1, precondition=1, prec_m0=0.0, prec_even_odd=0))
+    if only:
+        cases = [cases[int(k)] for k in only.split(",")]
     for kw in cases:
         prm = ovl.default_outer_params(tol=1e-8, **kw)
         torch.cuda.synchronize()

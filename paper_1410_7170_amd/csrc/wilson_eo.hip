@@ -20,8 +20,8 @@
 // x_e in FP64.  Every field lives in the library's even-odd layout; only the
 // even half of the Krylov vectors carries data, and the odd half of each
 // vector that M is applied to holds the intermediate H_oe v_e / (2A).
+#include <algorithm>
 #include <cmath>
-#include <vector>
 
 #include "mscg.h"
 
@@ -179,7 +179,6 @@ __device__ __forceinline__ size_t even_elem(int k, int Vh, int S) { return (size
 
 // Every even-half kernel covers the NC * Vh elements with one thread each and
 // reduces, when asked, |result|^2 into partials[blockIdx.x].
-template <typename E>
 __device__ __forceinline__ void flat_partial(double v, double *partials, double *lds)
 {
     const double t = block_sum(v, lds);
@@ -218,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_lin(int Vh, int S, double a, cons
         ((E *)out)[e] = v;
         n = sq(v);
     }
-    flat_partial<E>(n, partials, lds);
+    flat_partial(n, partials, lds);
 }
 
 // FP64 even half -> FP32 even half, partial |src|^2 (FP64); zero: dst = 0
@@ -233,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_round(int Vh, int S, const double
         dst[(size_t)c * S + i] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
         n = a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y;
     }
-    flat_partial<double2>(n, partials, lds);
+    flat_partial(n, partials, lds);
 }
 
 // x (FP64 even half) += e (FP32 even half); first: x = e
@@ -320,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_update(int Vh, int S, const EoSta
         s[x] = sv;
         n = sq(sv);
     }
-    flat_partial<float4>(n, partials, lds);
+    flat_partial(n, partials, lds);
 }
 
 // beta = |z|^2 / gamma, gamma = |z|^2; stop on |s|^2 <= target2

@@ -307,7 +307,8 @@ class Spinor:
 
 
 class Gauge:
-    """A gauge field packed in FP64 (18 reals), FP32 and FP16 (12 reals)."""
+    """A gauge field packed in FP64, FP32 and FP16, 12 reals per link (rows 0
+    and 1; row 2 is rebuilt in the kernels)."""
 
     def __init__(self, lat: Lattice, canon: torch.Tensor, precs=(F64, F32, F16S), stream=None):
         canon = canon.contiguous()

@@ -121,7 +121,8 @@ def test_wilson_solve_even_odd_edge_cases(ovl):
     """A zero RHS returns x = 0 with no iterations; a loose tolerance (the
     preconditioner's 1e-1) stops after one defect-correction step with the
     true residual below it; a capped run reports OVL_NOT_CONVERGED with its
-    iterations at the cap; m0 = -4 (no diagonal to divide by) is rejected."""
+    iterations at the cap; m0 = -4 (no diagonal to divide by) is rejected; a
+    NaN in the source returns OVL_ERR_NONFINITE."""
     dims = (4, 4, 4, 8)
     lat, olat = ovl.Lattice(dims), oracle.Lattice(dims)
     U = synth.gauge(dims, 0.3, 94, n_stout=1)
@@ -140,6 +141,13 @@ def test_wilson_solve_even_odd_edge_cases(ovl):
     assert st["iterations"][0] == 5 and st["true_residual"][0] > 1e-12
     with pytest.raises(ovl.OvlError):
         ovl.wilson_solve(lat, G, -4.0, B, X, ovl.default_params(even_odd=1))
+    # a NaN in the source is reported, not iterated on
+    bn = b.copy()
+    bn[0, 5, 2, 1] = np.nan
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.wilson_solve(lat, G, -0.8, ovl.Spinor.from_canonical(lat, dev(bn), 0), X,
+                         ovl.default_params(even_odd=1))
+    assert e.value.status == ovl.ERR_NONFINITE
 
 
 @pytest.mark.parametrize("dims,m0", [((32, 16, 16, 16), -0.5), ((64, 32, 32, 32), -0.5)])

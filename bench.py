@@ -383,6 +383,26 @@ def main():
     print(json.dumps(line))
 
 
+def golden_errors(np, lat, got, kind):
+    """Every RHS of got (nrhs, V, 4, 3) against the oracle's D_ov at the sampled
+    sites stored in tests/golden (written from the oracle alone): the worst
+    site error over the field's rms site norm, over all RHS."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import load_golden
+    path = os.path.join(GOLDEN, f"overlap_{lat.dims[1]}x{lat.dims[2]}x{lat.dims[3]}x{lat.dims[0]}_{kind}.txt")
+    if not os.path.exists(path):
+        return None
+    gold = load_golden(path)
+    sites = gold["sites"]
+    worst, worst_rel = 0.0, 0.0
+    for q, g in enumerate(gold["rhs"]):
+        err = np.linalg.norm(got[q].reshape(-1, 12)[sites] - g["vals"], axis=-1)
+        worst = max(worst, float(err.max() / g["rms"]))
+        worst_rel = max(worst_rel, float(np.linalg.norm(err) / np.linalg.norm(g["vals"])))
+    return dict(rhs=len(gold["rhs"]), sites=len(sites), max_site_err_over_rms=worst, max_rel_l2_sampled=worst_rel,
+                oracle_tol=float(gold["meta"].get("tol", "nan")))
+
+
 def accuracy_checks(args, ovl, torch, np, lat, B, out, got, overlap, form):
     """Error of the timed form's D_ov b against the oracle's at the sampled
     sites (tests/golden, written from the oracle alone), and the
@@ -661,8 +681,10 @@ def multi_rhs_line(args, ovl, synth, np, torch):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rate = B.nrhs * args.multi_rhs_steps / el
-    got = out.to_canonical().cpu().numpy()[0]
+    got_all = out.to_canonical().cpu().numpy()
+    got = got_all[0]
     del out
+    oracle_samples = golden_errors(np, lat, got_all, "points")
     # FP64, one RHS at a time: both FP64 forms, each over two applies
     B1 = ovl.Spinor.from_canonical(lat, torch.from_numpy(b[:1]).cuda(), ovl.F64)
     out1 = ovl.Spinor(lat, ovl.F64)
@@ -688,6 +710,7 @@ def multi_rhs_line(args, ovl, synth, np, torch):
                 iterations=st["iterations"], max_true_residual=max(max(r) for r in st["true_residual"]),
                 refine_iterations=st["refine_iterations"],
                 rel_diff_rhs0_vs_fp64=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                oracle_samples=oracle_samples,
                 stencil_order={k: tune[k] for k in ("tile_t", "stream_t", "stream_t64", "rhs_tile", "mfma")},
                 autotune=tune["timings"],
                 stencil_forms=stencil_forms(args, ovl, synth, np, torch, lat, G))

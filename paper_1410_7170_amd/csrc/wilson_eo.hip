@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_lin(int Vh, int S, double a, cons
     flat_partial(n, partials, lds);
 }
 
-// FP64 even half -> FP32 even half, partial |src|^2 (FP64); zero: dst = 0
+// FP64 even half -> FP32 even half, partial |src|^2 (FP64)
 __global__ __launch_bounds__(kBlock) void k_eo_round(int Vh, int S, const double2 *src, float4 *dst, double *partials)
 {
     __shared__ double lds[8];
@@ -377,8 +377,8 @@ hipError_t eo_hop(const Lat &L, int p, const void *in, const void *d, void *out,
     return hipGetLastError();
 }
 
-// Blocks of the flat even-half launches (FP64 and FP32 alike cover 6 * Vh
-// FP32-sized or 12 * Vh FP64 elements; the partial-sum buffers hold the larger).
+// Blocks of a flat even-half launch over nc component arrays (12 for FP64
+// double2, 6 for FP32 float4 elements); partial-sum buffers hold the FP64 count.
 inline int flat_blocks(const Lat &L, int nc) { return (nc * L.Vh + kBlock - 1) / kBlock; }
 
 }  // namespace

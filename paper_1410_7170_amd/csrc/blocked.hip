@@ -512,6 +512,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     }
     k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
     OVL_HIP(hipGetLastError());
+    // an unshifted base system (every RHS's base shift exactly 0) needs no
+    // s0 p0 term in the residual update, so that stencil does not read p0
+    const int rmode = !o.rhs_shift && shifts[j0] == 0.0 ? W_RUPDATE0 : W_RUPDATE;
     ShiftWeights sw;
     for (int j = 0; j < NS; j++) sw.w[j] = (weights && j < nshift) ? weights[j] : 0.0;
 
@@ -558,7 +561,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             int e2 = prof.mark();
             B.rin = slot(k);
             B.out = slot(k + 1);
-            OVL_HIP(launch_wilson(L, PS, W_RUPDATE, true, B, st));
+            OVL_HIP(launch_wilson(L, PS, rmode, true, B, st));
             if (f16) OVL_HIP(round16(slot(k + 1)));
             int e3 = prof.mark();
             k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk, npart, sw2);
@@ -677,8 +680,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     if (stats) {
         stats->stencil_applies += 2 * (int)k + 2 * replacements;
         stats->reliable_updates += replacements;
-        // compulsory bytes: K_A 2F + links and K_B 4F + links per iteration,
-        // K_C 3F; each pass reads the block's residuals once, and a shift
+        // compulsory bytes: K_A 2F + links and K_B 4F + links per iteration
+        // (3F + links with an unshifted base, which does not read p0), K_C 3F;
+        // each pass reads the block's residuals once, and a shift
         // active up to iteration f takes part in ceil(f/m) passes, reading p_j
         // in each and writing it in all but the last (x mode also reads and
         // writes the FP64 x_j each time); y mode reads and writes y once per pass.
@@ -687,7 +691,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         const double Fs = (double)FS, F8 = (double)F;
         const double G = (double)L.V * 4 * (PS == P_F64 ? 96.0 : 48.0);
         const bool fresh = !o.resume;
-        double sten = iters_all * (6 * Fs + 2 * G);
+        double sten = iters_all * ((rmode == W_RUPDATE0 ? 5 : 6) * Fs + 2 * G);
         double upd = iters_all * 3 * Fs;
         double pass = iters_all * Fs + (o.keep_x ? 0.0 : 2.0 * passes * R * F8) + (fresh && passes ? R * Fs : 0.0);
         for (int q = 0; q < R; q++)

@@ -23,6 +23,15 @@
 // Finally y += sum_j w_j dx_j in FP64.
 // Without an FP64 phase (sloppy_below = 0) the sloppy phase starts from
 // x_j = 0 with r0 = b and zeta_j = 1.
+//
+// Base system.  When every shift is positive (and one more fits), the
+// recurrences run with an extra shift 0 of weight 0 as their base: the
+// unshifted system Q^2 x = b shares the Krylov space of all the others, so
+// every shifted iterate is the same, while its residual update needs no s0 p0
+// term and its stencil does not read p0 (one field less per iteration).  The
+// extra system is neither verified, refined nor combined, and the caller's
+// per-shift statistics exclude it.  It converges last, as the smallest shift
+// did, a small fraction of an iteration later.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -53,9 +62,14 @@ static size_t region_b_bytes(const Lat &L, int nrhs, int nshift, int m)
     return std::max(std::max(a, b), F);
 }
 
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase, bool f16_store)
+// systems the recurrences carry for nshift caller shifts (room for the extra
+// unshifted base)
+static int mixed_systems(int nshift) { return nshift < NS ? nshift + 1 : nshift; }
+
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift_caller, int m, int m64, bool f64_phase, bool f16_store)
 {
     const size_t F = field_bytes(P_F64, L.V);
+    const int nshift = mixed_systems(nshift_caller);
     WsCarve c{nullptr, 0, 0};
     if (f16_store) {
         c.take(field_bytes(P_F16S, L.V) * nrhs);      // FP16 storage of the sloppy vectors
@@ -107,17 +121,18 @@ static int residual_f64(const Lat &L, const void *U64, double m0, double s, Fld 
     return OVL_OK;
 }
 
-int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
-               Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
-               hipStream_t st)
+// The solve on nshift systems; base0: system 0 is the extra unshifted base
+// (weight 0), which is not verified, refined or combined.
+static int mixed_solve(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts,
+                       const double *weights, bool base0, Fld b, Fld y, const ovl_solver_params *prm,
+                       ovl_solver_stats *stats, char *ws, size_t ws_bytes, hipStream_t st)
 {
     const int R = b.nrhs;
     const int m = mixed_block(prm), m64 = mixed_block_f64(prm);
     const size_t F = field_bytes(P_F64, L.V);
     const bool f64_phase = prm->sloppy_below > 0.0;
-    if (!weights) return OVL_ERR_INVALID;
     const bool f16 = prm->sloppy_f16 != 0;
-    if (ws_bytes < mixed_ws_bytes(L, R, nshift, m, m64, f64_phase, f16)) return OVL_ERR_WORKSPACE;
+    const int j1 = base0 ? 1 : 0;   // first caller shift
     WsCarve c{ws, 0, ws_bytes};
     Fld F16{};
     if (f16) {
@@ -261,8 +276,9 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
     {
         // shifts frozen for every RHS in the FP64 phase need no stencils
         for (int f = nz * R; f < R * nshift; f++) res[f] = frozen_res[f];
-        if (nz > 0) {
-            int e = verify(0, nz * R);
+        for (int f = 0; f < j1 * R; f++) res[f] = 0.0;   // the extra base: not verified
+        if (nz > j1) {
+            int e = verify(j1 * R, (nz - j1) * R);
             if (e) return e;
         }
     }
@@ -275,7 +291,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
         // system (j, q) has j < nz = ncomb, so its increment field was written
         // by the first FP32 pass.
         std::vector<std::pair<int, int>> bad;   // (shift, rhs)
-        for (int j = 0; j < nshift; j++)
+        for (int j = j1; j < nshift; j++)
             for (int q = 0; q < R; q++) {
                 const size_t f = (size_t)j * R + q;
                 if (frozen_res[f] < 0.0 && res[f] > prm->tol) bad.push_back({j, q});
@@ -331,7 +347,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
         }
     }
     int status = rc == kSwitched ? OVL_OK : rc;
-    for (int j = 0; j < nshift; j++)
+    for (int j = j1; j < nshift; j++)
         for (int q = 0; q < R; q++) {
             if (stats) stats->true_residual[q][j] = res[(size_t)j * R + q];
             // a system frozen in the FP64 phase met the freeze test; its
@@ -340,8 +356,44 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
                 status = OVL_NOT_CONVERGED;
         }
     if (stats) stats->refine_iterations += refine_iters;
-    OVL_HIP(launch_combine(L, weights, ncomb, X, y, st, switched));
+    if (ncomb > j1)
+        OVL_HIP(launch_combine(L, weights + j1, ncomb - j1, sub(X, L.V, j1 * R, (ncomb - j1) * R), y, st, switched));
+    else if (!switched)
+        OVL_HIP(launch_zero(L, y, st));
     return status;
+}
+
+int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const double *shifts, const double *weights,
+               Fld b, Fld y, const ovl_solver_params *prm, ovl_solver_stats *stats, char *ws, size_t ws_bytes,
+               hipStream_t st)
+{
+    if (!weights) return OVL_ERR_INVALID;
+    if (ws_bytes < mixed_ws_bytes(L, b.nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0,
+                                  prm->sloppy_f16 != 0))
+        return OVL_ERR_WORKSPACE;
+    bool base0 = mixed_systems(nshift) > nshift;
+    for (int j = 0; j < nshift; j++) base0 = base0 && shifts[j] > 0.0;
+    if (!base0) return mixed_solve(L, U, m0, nshift, shifts, weights, false, b, y, prm, stats, ws, ws_bytes, st);
+    double sh[NS], w[NS];
+    sh[0] = 0.0;
+    w[0] = 0.0;
+    for (int j = 0; j < nshift; j++) {
+        sh[j + 1] = shifts[j];
+        w[j + 1] = weights[j];
+    }
+    const int rc = mixed_solve(L, U, m0, nshift + 1, sh, w, true, b, y, prm, stats, ws, ws_bytes, st);
+    if (stats) {
+        // the caller's shifts are systems 1..nshift
+        for (int q = 0; q < NR; q++) {
+            for (int j = 0; j < nshift; j++) {
+                stats->shift_iters[q][j] = stats->shift_iters[q][j + 1];
+                stats->true_residual[q][j] = stats->true_residual[q][j + 1];
+            }
+            stats->shift_iters[q][nshift] = 0;
+            stats->true_residual[q][nshift] = -1.0;
+        }
+    }
+    return rc;
 }
 
 }  // namespace ovl

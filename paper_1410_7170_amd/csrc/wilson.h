@@ -18,6 +18,8 @@ enum WMode {
     W_SHIFT = 2,     // out = Gamma_5 D in + shift * p
     W_RUPDATE = 3,   // r  -= alpha_r (Gamma_5 D in + shift * p); partial |r|^2
     W_RESNORM = 4,   // partial |rin - (Gamma_5 D in + shift * p)|^2, nothing stored
+    W_RUPDATE0 = 5,  // r  -= alpha_r Gamma_5 D in (an unshifted system: p is not read);
+                     // partial |r|^2
 };
 
 struct WArgs {
@@ -29,7 +31,7 @@ struct WArgs {
     const void *U;
     const void *p;          // W_SHIFT / W_RUPDATE second field
     const float *p_sc;
-    const void *rin;        // W_RUPDATE: read r from here (may equal out)
+    const void *rin;        // W_RUPDATE(0): read r from here (may equal out)
     const float *rin_sc;
     int rin_first;          // W_RESNORM: RHS r reads field (rin_first + r) % rin_count of rin
     int rin_count;
@@ -37,7 +39,7 @@ struct WArgs {
     double diag;            // m0 + 4
     double shift;
     const double *shiftv;   // per-RHS shift (device), overrides shift when set
-    const double *alpha;    // W_RUPDATE: alpha per RHS (device)
+    const double *alpha;    // W_RUPDATE(0): alpha per RHS (device)
     double *partials;       // [quantity][nrhs][nblk]
     const int *skip;        // per-RHS flag: block exits if skip[r] != 0 (may be null)
     int nblk;               // partial-sum slots per RHS and quantity (2 * blocks per parity)
@@ -316,7 +318,7 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int rb, int lo, 
 #pragma unroll
             for (int c = 0; c < 3; c++) o[s][c] = {fma(sh, pv[s][c].x, o[s][c].x), fma(sh, pv[s][c].y, o[s][c].y)};
     }
-    if (MODE == W_RUPDATE) {
+    if (MODE == W_RUPDATE || MODE == W_RUPDATE0) {
         cplx<T> rv[4][3];
         spinor_ref<PREC>(a.rin, a.rin_sc, g.S, rb).load_nt(p, i + lo, rv);
         const T al = (T)a.alpha[r];
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         const T dn2 = diag_minus_half(acc, d, (T)a.diag);
         site_out<PREC, MODE, G5>(a, r, r, 0, p, i, shift_r, rin_s, acc, dn2, q0, q1);
     }
-    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
+    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
         double t0 = block_sum(q0, lds);
         if (threadIdx.x == 0) a.partials[(size_t)r * nb + lb] = t0;
         if (MODE == W_NORM) {
@@ -589,7 +591,7 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
             __syncthreads();
         }
     }
-    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RESNORM) {
+    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
         const int nq = MODE == W_NORM ? 2 : 1;
         double t0s = block_sum_k<NT / 64>(q0, lds, kr);
         double t1s = MODE == W_NORM ? block_sum_k<NT / 64>(q1, lds + (NT / 64) * 8, kr) : 0.0;

@@ -14,6 +14,7 @@ static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, h
         case W_NORM: k_wilson_ts<PREC, W_NORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
+        case W_RUPDATE0: k_wilson_ts<PREC, W_RUPDATE0, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         default: k_wilson_ts<PREC, W_RESNORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         }
     } else {
@@ -92,6 +93,7 @@ static void wilson_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStr
         case W_NORM: k_wilson<PREC, W_NORM, true><<<grid, kBlock, 0, st>>>(a); break;
         case W_SHIFT: k_wilson<PREC, W_SHIFT, true><<<grid, kBlock, 0, st>>>(a); break;
         case W_RUPDATE: k_wilson<PREC, W_RUPDATE, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_RUPDATE0: k_wilson<PREC, W_RUPDATE0, true><<<grid, kBlock, 0, st>>>(a); break;
         default: k_wilson<PREC, W_RESNORM, true><<<grid, kBlock, 0, st>>>(a); break;
         }
     } else {

@@ -223,3 +223,31 @@ def test_mixed_fp16_storage_mode(ovl, sloppy_below):
     assert floor > 0 and np.isfinite(floor)
     if sloppy_below >= 1e-5:
         assert floor > 1e-10
+
+
+def test_mixed_unshifted_base_bookkeeping(ovl):
+    """With all shifts positive the mixed solver runs its recurrences on an
+    extra unshifted base system of weight 0 and hides it from the caller.
+    Passing that system explicitly (shift 0, weight 0, first) runs the same
+    arithmetic with nothing hidden: D_ov must agree bit for bit, the
+    iteration counts must agree, and the caller's per-shift statistics must
+    be the explicit run's entries 1..n."""
+    dims = (8, 4, 4, 8)
+    U, lat, olat, G, (s, w), (os_, ow) = setup(ovl, dims, 331)
+    s, w = np.asarray(s)[:12], np.asarray(w)[:12]
+    b = synth.gaussian_spinor(lat.V, 332, 2)
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    prm = ovl.default_params(tol=1e-10, maxiter=5000, mode=ovl.SOLVE_MIXED, block=8, sloppy_below=1e-3)
+    Oa, Ob = ovl.Spinor(lat, 0, 2), ovl.Spinor(lat, 0, 2)
+    sa = ovl.overlap_apply(lat, G, RHO, s, w, B, Oa, prm)
+    sb = ovl.overlap_apply(lat, G, RHO, np.concatenate([[0.0], s]), np.concatenate([[0.0], w]), B, Ob, prm)
+    ga, gb = Oa.to_canonical().cpu().numpy(), Ob.to_canonical().cpu().numpy()
+    assert np.array_equal(ga, gb)
+    assert sa["iterations"] == sb["iterations"]
+    for q in range(2):
+        ta, tb = np.array(sa["true_residual"][q]), np.array(sb["true_residual"][q])
+        assert ta.shape == (12,) and tb.shape == (13,)
+        assert np.allclose(ta, tb[1:], rtol=1e-9, atol=0.0), (ta, tb)
+        assert (ta > 0).all() and (ta <= 1e-10).all()
+        assert list(sa["shift_iters"][q]) == list(sb["shift_iters"][q][1:])
+    note(f"  iterations {sa['iterations']}, max shifted residual {max(map(max, sa['true_residual'])):.2e}")

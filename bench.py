@@ -155,6 +155,12 @@ def operator_bandwidth(ovl, torch, lat, G, b, q2=False):
 
 
 def params_for(ovl, form, tol, profile=False):
+    # an optional ":f<k>" suffix sets the mixed form's FP64-phase block length
+    if ":f" in form:
+        form, m = form.split(":f", 1)
+        prm = params_for(ovl, form, tol, profile)
+        prm.block_f64 = int(m)
+        return prm
     # an optional ":m<k>" suffix sets the block length of the blocked forms
     if ":m" in form:
         form, m = form.split(":m", 1)

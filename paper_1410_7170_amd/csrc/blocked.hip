@@ -515,6 +515,15 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     // an unshifted base system (every RHS's base shift exactly 0) needs no
     // s0 p0 term in the residual update, so that stencil does not read p0
     const int rmode = !o.rhs_shift && shifts[j0] == 0.0 ? W_RUPDATE0 : W_RUPDATE;
+    // With that base in FP64, p0 is read by nothing but the next t = Q p0, so
+    // t follows its own recurrence t_k = Q r_k + beta_{k-1} t_{k-1} (Q is
+    // linear) from the stored residual, in place, and p0 is never formed: the
+    // base system's own shift vector p_j0, which the block passes keep and
+    // which equals p0 (zeta = 1, the same alpha and beta), serves whoever needs
+    // p0 afterwards (the hand-over to the FP32 phase).  The recurrence adds
+    // FP64 rounding at each step, of the order of the iteration count times
+    // eps relative to t.
+    const bool trec = PS == P_F64 && rmode == W_RUPDATE0;
     ShiftWeights sw;
     for (int j = 0; j < NS; j++) sw.w[j] = (weights && j < nshift) ? weights[j] : 0.0;
 
@@ -554,7 +563,20 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         };
         for (int q = 0; q < batch; q++, k++) {
             int e0 = prof.mark();
-            OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
+            if (trec && k > 0) {
+                // t = Q r_k + beta t (in place; beta of the previous iteration)
+                WArgs At = A;
+                At.in = slot(k);
+                At.p = t.d;
+                At.shiftv = S->beta;
+                OVL_HIP(launch_wilson(L, PS, W_SNORM, true, At, st));
+            } else if (trec) {
+                WArgs At = A;   // t_0 = Q r_0 (p0 = r0 at the start)
+                At.in = slot(0);
+                OVL_HIP(launch_wilson(L, PS, W_NORM, true, At, st));
+            } else {
+                OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
+            }
             if (f16) OVL_HIP(round16(t.d));
             int e1 = prof.mark();
             k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
@@ -566,7 +588,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             int e3 = prof.mark();
             k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk, npart, sw2);
             int e4 = prof.mark();
-            k_base_p<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), p0.d);
+            if (!trec) k_base_p<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), p0.d);
             if (f16) OVL_HIP(round16(p0.d));
             int e5 = prof.mark();
             OVL_HIP(hipGetLastError());
@@ -673,7 +695,8 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         }
         scr->S = S;
         scr->r = Fld{slot(k), nullptr, PS, R};
-        scr->p0 = p0;
+        // with the t recurrence p0 was never formed: p_j0 equals it
+        scr->p0 = trec ? sub(pj, L.V, j0 * R, R) : p0;
         scr->pj = pj;
         scr->j0 = j0;
     }
@@ -691,8 +714,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         const double Fs = (double)FS, F8 = (double)F;
         const double G = (double)L.V * 4 * (PS == P_F64 ? 96.0 : 48.0);
         const bool fresh = !o.resume;
-        double sten = iters_all * ((rmode == W_RUPDATE0 ? 5 : 6) * Fs + 2 * G);
-        double upd = iters_all * 3 * Fs;
+        // (with the t recurrence: K_A 3F + links, K_B 3F + links, no K_C)
+        double sten = iters_all * ((rmode == W_RUPDATE0 && !trec ? 5 : 6) * Fs + 2 * G);
+        double upd = trec ? 0.0 : iters_all * 3 * Fs;
         double pass = iters_all * Fs + (o.keep_x ? 0.0 : 2.0 * passes * R * F8) + (fresh && passes ? R * Fs : 0.0);
         for (int q = 0; q < R; q++)
             for (int j = 0; j < nshift; j++) {

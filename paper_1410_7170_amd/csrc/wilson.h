@@ -20,6 +20,7 @@ enum WMode {
     W_RESNORM = 4,   // partial |rin - (Gamma_5 D in + shift * p)|^2, nothing stored
     W_RUPDATE0 = 5,  // r  -= alpha_r Gamma_5 D in (an unshifted system: p is not read);
                      // partial |r|^2
+    W_SNORM = 6,     // out = Gamma_5 D in + shift * p; partials |out|^2, |in(x)|^2
 };
 
 struct WArgs {
@@ -290,7 +291,7 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int rb, int lo, 
                                          typename Real<PREC>::T dn2, double &q0, double &q1, bool live = true)
 {
     using T = typename Real<PREC>::T;
-    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
+    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM || MODE == W_SNORM;
     const Geom &g = a.g;
     const int ist = live ? i : g.Vh;   // store index
     if (G5) {
@@ -317,6 +318,15 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int rb, int lo, 
         for (int s = 0; s < 4; s++)
 #pragma unroll
             for (int c = 0; c < 3; c++) o[s][c] = {fma(sh, pv[s][c].x, o[s][c].x), fma(sh, pv[s][c].y, o[s][c].y)};
+    }
+    if (MODE == W_SNORM) {
+        T n0 = 0;
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) n0 += norm2(o[s][c]);
+        q0 += live ? (double)n0 : 0.0;
+        q1 += live ? (double)dn2 : 0.0;
     }
     if (MODE == W_RUPDATE || MODE == W_RUPDATE0) {
         cplx<T> rv[4][3];
@@ -382,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
     const int nb = gridDim.x / a.nrhs;   // site blocks (both parities)
     if (a.skip && a.skip[r]) return;
     // the epilogue's shift, read once up front (a uniform scalar)
-    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
+    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM || MODE == W_SNORM;
     const double shift_r = kShift ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
     // the residual norm's scale of rin, likewise read once up front (a load
     // left inside the epilogue behind the null test made the compiler keep far
@@ -413,10 +423,10 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
         const T dn2 = diag_minus_half(acc, d, (T)a.diag);
         site_out<PREC, MODE, G5>(a, r, r, 0, p, i, shift_r, rin_s, acc, dn2, q0, q1);
     }
-    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
+    if (MODE == W_NORM || MODE == W_SNORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
         double t0 = block_sum(q0, lds);
         if (threadIdx.x == 0) a.partials[(size_t)r * nb + lb] = t0;
-        if (MODE == W_NORM) {
+        if (MODE == W_NORM || MODE == W_SNORM) {
             double t1 = block_sum(q1, lds + 4);
             if (threadIdx.x == 0) a.partials[(size_t)(a.nrhs + r) * nb + lb] = t1;
         }
@@ -501,7 +511,7 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
     } else if (!__syncthreads_or(live)) {
         return;   // every RHS of the tile is finished (block-uniform)
     }
-    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM;
+    constexpr bool kShift = MODE == W_SHIFT || MODE == W_RUPDATE || MODE == W_RESNORM || MODE == W_SNORM;
     const double shift_r = kShift ? (a.shiftv ? a.shiftv[r] : a.shift) : 0.0;
     // the residual norm's scale of rin, likewise read once up front (a load
     // left inside the epilogue behind the null test made the compiler keep far
@@ -591,10 +601,10 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
             __syncthreads();
         }
     }
-    if (MODE == W_NORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
-        const int nq = MODE == W_NORM ? 2 : 1;
+    if (MODE == W_NORM || MODE == W_SNORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
+        constexpr int nq = MODE == W_NORM || MODE == W_SNORM ? 2 : 1;
         double t0s = block_sum_k<NT / 64>(q0, lds, kr);
-        double t1s = MODE == W_NORM ? block_sum_k<NT / 64>(q1, lds + (NT / 64) * 8, kr) : 0.0;
+        double t1s = nq == 2 ? block_sum_k<NT / 64>(q1, lds + (NT / 64) * 8, kr) : 0.0;
         // thread q of the first K holds RHS rt*K + q's sums; the zeroed slots
         // of the tile's RHS are spread over the block's threads
         __shared__ double sums[2][8];

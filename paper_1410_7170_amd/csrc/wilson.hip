@@ -15,6 +15,7 @@ static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, h
         case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         case W_RUPDATE0: k_wilson_ts<PREC, W_RUPDATE0, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
+        case W_SNORM: k_wilson_ts<PREC, W_SNORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         default: k_wilson_ts<PREC, W_RESNORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
         }
     } else {
@@ -94,6 +95,7 @@ static void wilson_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStr
         case W_SHIFT: k_wilson<PREC, W_SHIFT, true><<<grid, kBlock, 0, st>>>(a); break;
         case W_RUPDATE: k_wilson<PREC, W_RUPDATE, true><<<grid, kBlock, 0, st>>>(a); break;
         case W_RUPDATE0: k_wilson<PREC, W_RUPDATE0, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_SNORM: k_wilson<PREC, W_SNORM, true><<<grid, kBlock, 0, st>>>(a); break;
         default: k_wilson<PREC, W_RESNORM, true><<<grid, kBlock, 0, st>>>(a); break;
         }
     } else {

@@ -80,7 +80,9 @@ def parse():
 
 
 # sources that define each kernel class's kernels and launches
-CLASS_SOURCES = {"wilson_stencil_q2": ("device.h", "wilson.h", "wilson.hip")}
+# (the stencils themselves, and the solvers that choose which of their modes an
+# apply launches)
+CLASS_SOURCES = {"wilson_stencil_q2": ("device.h", "wilson.h", "wilson.hip", "blocked.hip", "mixed.hip")}
 
 
 def source_hash(kernel: str = "") -> str:

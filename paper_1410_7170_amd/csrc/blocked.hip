@@ -521,9 +521,14 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     // base system's own shift vector p_j0, which the block passes keep and
     // which equals p0 (zeta = 1, the same alpha and beta), serves whoever needs
     // p0 afterwards (the hand-over to the FP32 phase).  The recurrence adds
-    // FP64 rounding at each step, of the order of the iteration count times
-    // eps relative to t.
-    const bool trec = PS == P_F64 && rmode == W_RUPDATE0;
+    // rounding at each step, of the order of the steps since t was last formed
+    // directly times eps relative to t: FP64 forms t directly once, FP32 at
+    // every block start from p_j0, which the block pass has just brought to
+    // the current iteration.
+    // (not in the FP16-storage measurement mode, whose subject is the stored p0
+    // and Q p0)
+    const bool trec = rmode == W_RUPDATE0 && (PS == P_F64 || (PS == P_F32 && !o.f16.d));
+    const Fld pj0 = sub(pj, L.V, j0 * R, R);
     ShiftWeights sw;
     for (int j = 0; j < NS; j++) sw.w[j] = (weights && j < nshift) ? weights[j] : 0.0;
 
@@ -563,7 +568,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         };
         for (int q = 0; q < batch; q++, k++) {
             int e0 = prof.mark();
-            if (trec && k > 0) {
+            if (trec && k > 0 && !(PS == P_F32 && q == 0)) {
                 // t = Q r_k + beta t (in place; beta of the previous iteration)
                 WArgs At = A;
                 At.in = slot(k);
@@ -571,8 +576,11 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
                 At.shiftv = S->beta;
                 OVL_HIP(launch_wilson(L, PS, W_SNORM, true, At, st));
             } else if (trec) {
-                WArgs At = A;   // t_0 = Q r_0 (p0 = r0 at the start)
-                At.in = slot(0);
+                // t = Q p0 directly: p0 = r0 at the start of a fresh solve, the
+                // handed-over p0 at the start of a resumed one, p_j0 at a block start
+                WArgs At = A;
+                if (k > 0) At.in = pj0.d;
+                else if (!o.resume) At.in = slot(0);
                 OVL_HIP(launch_wilson(L, PS, W_NORM, true, At, st));
             } else {
                 OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
@@ -696,7 +704,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         scr->S = S;
         scr->r = Fld{slot(k), nullptr, PS, R};
         // with the t recurrence p0 was never formed: p_j0 equals it
-        scr->p0 = trec ? sub(pj, L.V, j0 * R, R) : p0;
+        scr->p0 = trec ? pj0 : p0;
         scr->pj = pj;
         scr->j0 = j0;
     }

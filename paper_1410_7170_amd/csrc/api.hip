@@ -365,7 +365,10 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         if (prm && prm->mode == OVL_SOLVE_MIXED)
             return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0,
                                        prm->sloppy_f16 != 0);
-        if (prm && prm->block > 0) return yb + blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64);
+        if (prm && prm->block > 0)   // x mode, or y mode with the extra unshifted base
+            return yb + std::max(blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64),
+                                 blocked_ws_bytes(L, nrhs, std::min(nshift + 1, (int32_t)NS), prm->block, false,
+                                                  P_F64));
         return yb + mscg_ws_bytes(L, nrhs, nshift);
     }
     return 0;
@@ -450,8 +453,30 @@ static int solve_y(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         BlkOpts o;
         o.m = prm->block;
         o.keep_x = keep_x;
-        rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, weights, b, y, o, prm, stats, ws + yb, ws_bytes - yb, st,
-                                   scr);
+        // y mode with positive shifts: the recurrences run on an extra
+        // unshifted base of weight 0, as in the mixed solver (no p0 field, t by
+        // recurrence, the residual update without the s0 p0 term); the
+        // caller's per-shift statistics leave it out
+        bool base0 = !keep_x && nshift < NS;
+        for (int j = 0; j < nshift; j++) base0 = base0 && shifts[j] > 0.0;
+        if (base0) {
+            double sh[NS], w[NS];
+            sh[0] = w[0] = 0.0;
+            for (int j = 0; j < nshift; j++) {
+                sh[j + 1] = shifts[j];
+                w[j + 1] = weights[j];
+            }
+            rc = mscg_blocked_t<P_F64>(L, U, m0, nshift + 1, sh, w, b, y, o, prm, stats, ws + yb, ws_bytes - yb, st,
+                                       scr);
+            if (rc >= 0 && stats)
+                for (int q = 0; q < NR; q++) {
+                    for (int j = 0; j < nshift; j++) stats->shift_iters[q][j] = stats->shift_iters[q][j + 1];
+                    stats->shift_iters[q][nshift] = 0;
+                }
+        } else {
+            rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, weights, b, y, o, prm, stats, ws + yb,
+                                       ws_bytes - yb, st, scr);
+        }
     } else
         rc = mscg_f64(L, U->f64, m0, nshift, shifts, b, prm, stats, ws + yb, ws_bytes - yb, st, scr);
     if (rc < 0) return rc;

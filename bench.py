@@ -185,10 +185,13 @@ def params_for(ovl, form, tol, profile=False):
         if "@" in form:
             prm.sloppy_below = float(form.split("@", 1)[1])
         # "_f16": the FP32 phase's vectors rounded through FP16 storage (a
-        # measurement of that format's floor); "_norefine": report the
+        # measurement of that format's floor); "_s64": the FP64 phase's
+        # vectors stored in FP64 instead of 48 bits; "_norefine": report the
         # verified residuals without refining them
         if "_f16" in form:
             prm.sloppy_f16 = 1
+        if "_s64" in form:
+            prm.store48 = 0
         if "_norefine" in form:
             prm.refine = 0
         return prm

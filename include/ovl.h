@@ -28,6 +28,11 @@
  * (padding keeps the component arrays of one site off power-of-two strides):
  *   OVL_F64  spinor: complex128 per component, [rhs][parity][12][S]
  *   OVL_F32  spinor: float4 (two components), [rhs][parity][6][S]
+ *   OVL_F48  spinor: each real stored in 48 bits (a double rounded to nearest
+ *            at 36 stored mantissa bits), [rhs][parity][9][S] of 16-byte
+ *            elements: elements 0..5 the top 32 bits of components 2k, 2k+1
+ *            (re, im, re, im), elements 6..8 the low 16 bits of components
+ *            4g..4g+3 (word q: re | im << 16); its stencils use the F64 links
  *   OVL_F16S spinor: 8 halves (four components), [rhs][parity][3][S], plus
  *            one float scale per site [rhs][parity][S]: stored = value/scale,
  *            scale = largest |real or imaginary part| at that site
@@ -80,9 +85,10 @@ enum ovl_status {
     OVL_ERR_NONFINITE = -4
 };
 
-/* storage precision of a field; arithmetic is FP64 for OVL_F64 and FP32
- * (FP64 accumulation of dot products) for OVL_F32 and OVL_F16S */
-enum ovl_prec { OVL_F64 = 0, OVL_F32 = 1, OVL_F16S = 2 };
+/* storage precision of a field; arithmetic is FP64 for OVL_F64 and OVL_F48
+ * and FP32 (FP64 accumulation of dot products) for OVL_F32 and OVL_F16S.
+ * Gauge fields exist in OVL_F64, OVL_F32 and OVL_F16S (as F16 links). */
+enum ovl_prec { OVL_F64 = 0, OVL_F32 = 1, OVL_F16S = 2, OVL_F48 = 3 };
 
 /* solver precision modes */
 enum ovl_solve_mode {
@@ -230,6 +236,17 @@ typedef struct {
                                 iterations.  0 (default): CG on the normal
                                 equations of the full lattice, as described
                                 at ovl_wilson_solve */
+    int32_t store48;         /* mixed: 1 (default) stores the FP64 phase's
+                                Krylov vectors (residual ring, Q p and the
+                                shifted directions p_j) in 48 bits per real
+                                (OVL_F48: rounded to nearest at 36 stored
+                                mantissa bits, relative error <= 2^-37), with
+                                FP64 links and arithmetic; that rounding enters
+                                the residuals some 1e-11 below their size,
+                                under the 1e-10 target.  It needs the phase's
+                                unshifted base system (positive caller shifts,
+                                fewer than OVL_MAX_SHIFTS of them) and falls
+                                back to FP64 storage without it.  0: FP64 */
 } ovl_solver_params;
 
 /* kernel classes of ovl_solver_stats.kernel_* */
@@ -517,7 +534,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
  * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 1e-5,
- * block_f64 0, rhs_group 0, deflation NULL, sloppy_f16 0, even_odd 0. */
+ * block_f64 0, rhs_group 0, deflation NULL, sloppy_f16 0, even_odd 0, store48 1. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 
 /* Stencil autotuner.  Times the Wilson stencil (D_W, eq. (Wilson-Dirac)) on

@@ -29,12 +29,12 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID, ERR_WORKSPACE, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4
-F64, F32, F16S = 0, 1, 2
+F64, F32, F16S, F48 = 0, 1, 2, 3
 SOLVE_F64, SOLVE_MIXED, SOLVE_LANCZOS = 0, 1, 2
 OP_Q2, OP_LANCZOS, OP_MSCG, OP_TUNE, OP_WILSON_SOLVE = 0, 1, 2, 3, 4
 K_STENCIL, K_UPDATE, K_SCALAR, K_OTHER = 0, 1, 2, 3
 MAX_SHIFTS, MAX_RHS, MAX_BLOCK = 32, 16, 32
-PREC_NAMES = {F64: "f64", F32: "f32", F16S: "f16s"}
+PREC_NAMES = {F64: "f64", F32: "f32", F16S: "f16s", F48: "f48"}
 
 c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -65,7 +65,7 @@ class ovl_solver_params(ctypes.Structure):
                 ("check_every", c_i32), ("refine", c_i32), ("verify", c_i32), ("profile", c_i32),
                 ("block", c_i32), ("sloppy_below", c_dbl), ("block_f64", c_i32), ("rhs_group", c_i32),
                 ("deflation", ctypes.POINTER(ovl_deflation)), ("sloppy_f16", c_i32),
-                ("even_odd", c_i32)]
+                ("even_odd", c_i32), ("store48", c_i32)]
 
 
 class ovl_eig_params(ctypes.Structure):

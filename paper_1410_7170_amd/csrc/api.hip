@@ -21,7 +21,7 @@ hipError_t launch_combine(const Lat &L, const double *w, int nshift, Fld x, Fld 
                           bool accumulate = false);
 int lanczos_bounds(const Lat &L, const void *U64, double m0, int iters, Fld start, double *tmin, double *tmax,
                    char *ws, size_t ws_bytes, hipStream_t st);
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase, bool f16_store);
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift, int m, int m64, bool f64_phase, bool f16_store, bool s48);
 size_t tune_ws_bytes(const Lat &L, int nrhs);
 int autotune_stencil(ovl_lattice *lat, const ovl_gauge *U, int nrhs, char *ws, size_t ws_bytes, hipStream_t st,
                      int32_t *tried, float *times_us, int32_t max_tried);
@@ -79,7 +79,7 @@ bool lat_ok(const ovl_lattice *lat)
 bool spinor_ok(const ovl_spinor *s, int max_fields = OVL_MAX_RHS)
 {
     if (!s || !s->d) return false;
-    if (s->prec < OVL_F64 || s->prec > OVL_F16S) return false;
+    if (s->prec < OVL_F64 || s->prec > OVL_F48) return false;
     if (s->nrhs < 1 || s->nrhs > max_fields) return false;
     if (s->prec == OVL_F16S && !s->scale) return false;
     return true;
@@ -91,7 +91,7 @@ constexpr int kMaxFields = OVL_MAX_RHS * OVL_MAX_SHIFTS;
 const void *gauge_for(const ovl_gauge *U, int prec)
 {
     if (!U) return nullptr;
-    return prec == OVL_F64 ? U->f64 : prec == OVL_F32 ? U->f32 : U->f16;
+    return prec == OVL_F64 || prec == OVL_F48 ? U->f64 : prec == OVL_F32 ? U->f32 : U->f16;
 }
 
 hipStream_t S(void *s) { return (hipStream_t)s; }
@@ -102,7 +102,7 @@ bool params_ok(const ovl_solver_params *p)
            (p->mode == OVL_SOLVE_F64 || p->mode == OVL_SOLVE_MIXED || p->mode == OVL_SOLVE_LANCZOS) &&
            p->reliable_delta > 0.0 &&
            p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
-           p->sloppy_below < 1.0 && p->rhs_group >= 0 && (p->sloppy_f16 == 0 || p->sloppy_f16 == 1) &&
+           p->sloppy_below < 1.0 && p->rhs_group >= 0 && (p->sloppy_f16 == 0 || p->sloppy_f16 == 1) && (p->store48 == 0 || p->store48 == 1) &&
            (p->even_odd == 0 || p->even_odd == 1);
 }
 
@@ -256,7 +256,7 @@ int ovl_lattice_init(ovl_lattice *lat, const int32_t dims[4], const int32_t bc[4
 
 size_t ovl_spinor_bytes(const ovl_lattice *lat, int32_t prec)
 {
-    if (!lat_ok(lat) || prec < 0 || prec > 2) return 0;
+    if (!lat_ok(lat) || prec < 0 || prec > OVL_F48) return 0;
     return field_bytes(prec, lat->vol);
 }
 
@@ -337,7 +337,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
     if (!lat_ok(lat) || nrhs < 1 || nrhs > OVL_MAX_RHS) return 0;
     Lat L = make_lat(lat);
     if (op == OVL_OP_Q2) {
-        if (prec < 0 || prec > 2) return 0;
+        if (prec < 0 || prec > OVL_F48) return 0;
         size_t F = field_bytes(prec, L.V) * nrhs;
         return ((F + 255) & ~(size_t)255) + scale_bytes(L.V) * nrhs + 256;
     }
@@ -364,7 +364,7 @@ size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t prec, int
         if (prm && prm->mode == OVL_SOLVE_LANCZOS) return yb + lanczos_sign_ws_bytes(L, nrhs);
         if (prm && prm->mode == OVL_SOLVE_MIXED)
             return yb + mixed_ws_bytes(L, nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0,
-                                       prm->sloppy_f16 != 0);
+                                       prm->sloppy_f16 != 0, prm->store48 != 0);
         if (prm && prm->block > 0)   // x mode, or y mode with the extra unshifted base
             return yb + std::max(blocked_ws_bytes(L, nrhs, nshift, prm->block, true, P_F64),
                                  blocked_ws_bytes(L, nrhs, std::min(nshift + 1, (int32_t)NS), prm->block, false,
@@ -391,6 +391,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->rhs_group = 0;
     p->deflation = nullptr;
     p->sloppy_f16 = 0;
+    p->store48 = 1;
     p->even_odd = 0;
 }
 

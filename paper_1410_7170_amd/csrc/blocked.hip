@@ -13,6 +13,7 @@
 //   x_j += XP p_j + sum_i X_i r^{k0+i},   p_j = P p_j + sum_i C_i r^{k0+i}
 // (or y += sum_j w_j (...) directly), so each shifted vector is read and
 // written once per block instead of once per iteration.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -104,7 +105,12 @@ __global__ __launch_bounds__(kBlock) void k_blk_beta(MState *st, Blk *bk, const 
 
 // Element traits of the solver's vector fields: FP64 fields are arrays of
 // complex128 (12 per site and parity), FP32 fields of float4 (two complex,
-// 6 per site and parity).
+// 6 per site and parity), 48-bit fields hold two complex per element in two
+// places (the top 32 bits of each real in one 16-byte array, the low 16 bits
+// in half of another; see SpinorRef<P_F48>).  ld/st address element e of
+// site (p, i) of a field set at field offset k (in 16-byte units); W is a
+// field's size in 16-byte units per stride S, so field k of a set starts at element k*W*S; off gives the
+// offset of element e of site (p, i) within a field.
 template <int PS>
 struct El;
 template <>
@@ -112,13 +118,82 @@ struct El<P_F64> {
     using V = double2;
     static constexpr int N = 12;   // elements per site and parity
     static constexpr int C = 1;    // complex numbers per element
+    static constexpr int W = 24;
     __device__ static void get(const V &v, double *re, double *im) { re[0] = v.x; im[0] = v.y; }
     __device__ static V put(const double *re, const double *im) { return make_double2(re[0], im[0]); }
     __device__ static V fresh(const V &v) { return v; }
-    __device__ static V ldnt(const V *p)
+    using O = size_t;
+    __device__ static O off(int S, int p, int i, int e) { return (size_t)(p * N + e) * S + i; }
+    __device__ static V ld(const void *f, size_t k, O o) { return ((const V *)f)[k + o]; }
+    __device__ static void st(void *f, size_t k, O o, const V &v) { ((V *)f)[k + o] = v; }
+    __device__ static V ldnt(const void *f, size_t k, O o)
     {
-        nt_d2 t = __builtin_nontemporal_load((const nt_d2 *)p);
+        nt_d2 t = __builtin_nontemporal_load((const nt_d2 *)f + k + o);
         return make_double2(t.x, t.y);
+    }
+};
+struct V48 {
+    uint4 h;   // top 32 bits: re, im of complex 2e, then of 2e+1
+    uint2 l;   // low 16 bits: (re | im << 16) of complex 2e, 2e+1
+};
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+template <>
+struct El<P_F48> {
+    using V = V48;
+    static constexpr int N = 6;
+    static constexpr int C = 2;
+    static constexpr int W = 18;
+    __device__ static void get(const V &v, double *re, double *im)
+    {
+        re[0] = f48_value(v.h.x, v.l.x & 0xffffu);
+        im[0] = f48_value(v.h.y, v.l.x >> 16);
+        re[1] = f48_value(v.h.z, v.l.y & 0xffffu);
+        im[1] = f48_value(v.h.w, v.l.y >> 16);
+    }
+    __device__ static V put(const double *re, const double *im)
+    {
+        unsigned long long b[4] = {f48_bits(re[0]), f48_bits(im[0]), f48_bits(re[1]), f48_bits(im[1])};
+        V v;
+        v.h = make_uint4(f48_hi(b[0]), f48_hi(b[1]), f48_hi(b[2]), f48_hi(b[3]));
+        v.l = make_uint2(f48_lo(b[0]) | (f48_lo(b[1]) << 16), f48_lo(b[2]) | (f48_lo(b[3]) << 16));
+        return v;
+    }
+    // as El<P_F32>::fresh: the decoding of a value held across a loop stays
+    // inside the loop
+    __device__ static V fresh(const V &v)
+    {
+        V c = v;
+        asm volatile("" : "+v"(c.h.x), "+v"(c.h.y), "+v"(c.h.z), "+v"(c.h.w), "+v"(c.l.x), "+v"(c.l.y));
+        return c;
+    }
+    // 16-byte index of the top words, 8-byte index of the low words
+    struct O {
+        size_t h, l;
+    };
+    __device__ static O off(int S, int p, int i, int e)
+    {
+        return {(size_t)(p * 9 + e) * S + i, 2 * ((size_t)(p * 9 + 6 + e / 2) * S + i) + (e & 1)};
+    }
+    __device__ static V ld(const void *f, size_t k, O o)
+    {
+        V v;
+        v.h = ((const uint4 *)f)[k + o.h];
+        v.l = ((const uint2 *)f)[2 * k + o.l];
+        return v;
+    }
+    __device__ static void st(void *f, size_t k, O o, const V &v)
+    {
+        ((uint4 *)f)[k + o.h] = v.h;
+        ((uint2 *)f)[2 * k + o.l] = v.l;
+    }
+    __device__ static V ldnt(const void *f, size_t k, O o)
+    {
+        nt_u4 h = __builtin_nontemporal_load((const nt_u4 *)f + k + o.h);
+        nt_u2 l = __builtin_nontemporal_load((const nt_u2 *)f + 2 * k + o.l);
+        V v;
+        v.h = make_uint4(h.x, h.y, h.z, h.w);
+        v.l = make_uint2(l.x, l.y);
+        return v;
     }
 };
 template <>
@@ -126,6 +201,7 @@ struct El<P_F32> {
     using V = float4;
     static constexpr int N = 6;
     static constexpr int C = 2;
+    static constexpr int W = 12;
     __device__ static void get(const V &v, double *re, double *im)
     {
         re[0] = v.x; im[0] = v.y; re[1] = v.z; im[1] = v.w;
@@ -143,9 +219,13 @@ struct El<P_F32> {
         asm volatile("" : "+v"(c.x), "+v"(c.y), "+v"(c.z), "+v"(c.w));
         return c;
     }
-    __device__ static V ldnt(const V *p)
+    using O = size_t;
+    __device__ static O off(int S, int p, int i, int e) { return (size_t)(p * N + e) * S + i; }
+    __device__ static V ld(const void *f, size_t k, O o) { return ((const V *)f)[k + o]; }
+    __device__ static void st(void *f, size_t k, O o, const V &v) { ((V *)f)[k + o] = v; }
+    __device__ static V ldnt(const void *f, size_t k, O o)
     {
-        nt_f4 t = __builtin_nontemporal_load((const nt_f4 *)p);
+        nt_f4 t = __builtin_nontemporal_load((const nt_f4 *)f + k + o);
         return make_float4(t.x, t.y, t.z, t.w);
     }
 };
@@ -157,27 +237,25 @@ template <int PS>
 __global__ __launch_bounds__(kBlock) void k_base_p(Geom g, int nb, const MState *st, const void *rnv, void *p0v)
 {
     using E = El<PS>;
-    using V = typename E::V;
     const int r = blockIdx.y;
     if (!st->run_c[r]) return;
     const int b = blockIdx.x;
     const int p = b / nb, i = (b % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    const V *rn = (const V *)rnv;
-    V *p0 = (V *)p0v;
     const double be = st->beta[r];
-    const size_t off = (size_t)r * 2 * E::N * g.S + (size_t)p * E::N * g.S + i;
 #pragma unroll
     for (int e = 0; e < E::N; e++) {
         double ar[E::C], ai[E::C], qr[E::C], qi[E::C];
-        E::get(E::ldnt(rn + off + (size_t)e * g.S), ar, ai);
-        E::get(E::ldnt(p0 + off + (size_t)e * g.S), qr, qi);
+        const typename E::O o = E::off(g.S, p, i, e);
+        const size_t k = (size_t)r * E::W * g.S;
+        E::get(E::ldnt(rnv, k, o), ar, ai);
+        E::get(E::ldnt(p0v, k, o), qr, qi);
 #pragma unroll
         for (int c = 0; c < E::C; c++) {
             qr[c] = fma(be, qr[c], ar[c]);
             qi[c] = fma(be, qi[c], ai[c]);
         }
-        p0[off + (size_t)e * g.S] = E::put(qr, qi);
+        E::st(p0v, k, o, E::put(qr, qi));
     }
 }
 
@@ -189,16 +267,19 @@ struct RingPtrs {
 // FP64.  y mode (xf == null): y_r += sum_j w_j dx_j; x mode: x_j += dx_j.
 // first: the first pass of a fresh solve, where every p_j still equals b
 // (ring slot 0): it is read from there, and written for every shift of the
-// block.  p64in (FP32 passes): the first pass of a solve that continues FP64
-// recurrences reads the p_j from the FP64 solve's fields, rounded to FP32
-// as a conversion would round them.  xzero (x mode): the x_j of shifts
+// block.  pin (FP32 passes): the first pass of a solve that continues FP64
+// recurrences reads the p_j from the FP64 solve's fields (stored in FP64 or,
+// PIN48, in 48 bits), rounded to FP32 as a conversion would round them.  xzero (x mode): the x_j of shifts
 // j < xzero start at zero; the pass writes x_j = dx_j for the block's shifts
 // and zeros for the others below xzero (for every one of an RHS with no
 // iteration in the block).  The block's shifts all lie below xzero.
-template <int PS, int MBT>
-__global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
+// The 48-bit 16-slot build is held to three waves per SIMD (its residuals
+// take 6 registers a slot; left alone it takes 173 and two waves, 3.25 ms a
+// pass at 32^3x64 against 3.02 ms at three waves with a 28-byte spill).
+template <int PS, int MBT, bool PIN48 = false>
+__global__ __launch_bounds__(kBlock, PS == P_F48 && MBT <= 16 ? 3 : 1) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
                                                      ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs,
-                                                     int first, const double2 *p64in, int xzero)
+                                                     int first, const void *pin, int xzero)
 {
     using E = El<PS>;
     using V = typename E::V;
@@ -250,32 +331,37 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
         for (int j = 0; j < nzs; j++)
             if (!bk->inblk[r][j]) zero_x(j);
     if (n == 0) return;
-    V *pf = (V *)pfv;
-    const size_t FS = (size_t)2 * E::N * g.S;          // sloppy field, in elements
-    const size_t site = (size_t)p * E::N * g.S + i;
+    const size_t FS = (size_t)E::W * g.S;   // sloppy field, in 16-byte units
     for (int e = 0; e < E::N; e++) {
-        const size_t off = site + (size_t)e * g.S;
+        const typename E::O off = E::off(g.S, p, i, e);
         // the block's residuals stay in their storage precision in registers
-        // (4 VGPRs per slot) and are widened where they are used
+        // (4 VGPRs per slot, 6 for 48-bit fields) and are widened where they
+        // are used
         V rv[MBT];
 #pragma unroll
         for (int q = 0; q < MBT; q++)
-            if (q < T) rv[q] = ((const V *)ring.slot[q + 1])[(size_t)r * FS + off];
+            if (q < T) rv[q] = E::ld(ring.slot[q + 1], (size_t)r * FS, off);
         V pb{};
-        if (first) pb = ((const V *)ring.slot[0])[(size_t)r * FS + off];
+        if (first) pb = E::ld(ring.slot[0], (size_t)r * FS, off);
         double yre[E::C], yim[E::C];
 #pragma unroll
         for (int c = 0; c < E::C; c++) yre[c] = yim[c] = 0.0;
         // software pipeline over the shifts: the next shift's p_j (and x_j)
         // are loaded before this shift's results are stored, so a load is
         // always in flight while the previous shift computes
-        auto pptr = [&](int q) { return pf + ((size_t)sj[q] * nrhs + r) * FS + off; };
+        auto pfield = [&](int q) { return ((size_t)sj[q] * nrhs + r) * FS; };
         auto xptr = [&](int q) {
             return xf + ((size_t)sj[q] * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
         };
         auto pload = [&](int q) -> V {
-            if (PS == P_F32 && p64in) {
-                const double2 *b64 = p64in + ((size_t)sj[q] * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
+            if (PS == P_F32 && PIN48 && pin) {
+                using E48 = El<P_F48>;
+                double re[2], im[2];
+                E48::get(E48::ld(pin, ((size_t)sj[q] * nrhs + r) * E48::W * g.S, E48::off(g.S, p, i, e)), re, im);
+                return E::put(re, im);
+            }
+            if (PS == P_F32 && !PIN48 && pin) {
+                const double2 *b64 = (const double2 *)pin + ((size_t)sj[q] * nrhs + r) * F64 + site64 + (size_t)(e * E::C) * g.S;
                 double re[E::C], im[E::C];
 #pragma unroll
                 for (int c = 0; c < E::C; c++) {
@@ -285,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
                 }
                 return E::put(re, im);
             }
-            return *pptr(q);
+            return E::ld(pfv, pfield(q), off);
         };
         V pcur = first ? pb : pload(0);
         double2 xcur[E::C];
@@ -328,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
                         pni[c] = fma(cc, rim[c], pni[c]);
                     }
                 }
-            if (sact[q] || first) *pptr(q) = E::put(pnr, pni);
+            if (sact[q] || first) E::st(pfv, pfield(q), off, E::put(pnr, pni));
             if (xf) {
                 double2 *xp = xptr(q);
 #pragma unroll
@@ -356,6 +442,22 @@ __global__ __launch_bounds__(kBlock) void k_blk_pass(Geom g, int nb, const MStat
     }
 }
 
+// The block pass build for the block length (16 residuals in registers, or
+// MB) and, in FP32, for the precision of the p_j of a continued FP64 solve.
+template <int PS, typename... A>
+static void launch_blk_pass(int m, bool pin48, dim3 grid, hipStream_t st, A... a)
+{
+    if constexpr (PS == P_F32) {
+        if (pin48) {
+            if (m <= 16) k_blk_pass<PS, 16, true><<<grid, kBlock, 0, st>>>(a...);
+            else k_blk_pass<PS, MB, true><<<grid, kBlock, 0, st>>>(a...);
+            return;
+        }
+    }
+    if (m <= 16) k_blk_pass<PS, 16><<<grid, kBlock, 0, st>>>(a...);
+    else k_blk_pass<PS, MB><<<grid, kBlock, 0, st>>>(a...);
+}
+
 // ring slot 0 = b, p0 = b (precision PS), and y = 0 or x_j = 0 (FP64).  The
 // p_j (= b) are left to the first block pass, which reads b from slot 0;
 // only an RHS that is finished from the start (b = 0) gets them here.
@@ -370,10 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const MSta
     const int bl = blockIdx.x;
     const int p = bl / nb, i = (bl % nb) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    V *r0 = (V *)r0v, *p0 = (V *)p0v, *pf = (V *)pfv;
-    const size_t FS = (size_t)2 * E::N * g.S;
     const size_t F64 = (size_t)24 * g.S;
-    const size_t off = (size_t)rr * FS + (size_t)p * E::N * g.S + i;
     const size_t off64 = (size_t)rr * F64 + (size_t)p * 12 * g.S + i;
     const double2 z = make_double2(0.0, 0.0);
     for (int e = 0; e < E::N; e++) {
@@ -385,11 +484,12 @@ __global__ __launch_bounds__(kBlock) void k_blk_start(Geom g, int nb, const MSta
             im[c] = v.y;
         }
         V v = E::put(re, im);
-        const size_t o = off + (size_t)e * g.S;
-        r0[o] = v;
-        p0[o] = v;
+        const typename E::O o = E::off(g.S, p, i, e);
+        const size_t FS = (size_t)E::W * g.S;
+        E::st(r0v, rr * FS, o, v);
+        E::st(p0v, rr * FS, o, v);
         if (st->skip[rr])
-            for (int j = 0; j < nshift; j++) pf[(size_t)j * nrhs * FS + o] = v;
+            for (int j = 0; j < nshift; j++) E::st(pfv, ((size_t)j * nrhs + rr) * FS, o, v);
     }
     for (int c = 0; c < 12; c++) {
         const size_t o64 = off64 + (size_t)c * g.S;
@@ -431,12 +531,19 @@ size_t blocked_ws_bytes(const Lat &L, int nrhs, int nshift, int m, bool keep_x, 
     c.take(sizeof(Blk));
     c.take(sizeof(double) * 2 * nrhs * site_blocks(L));
     c.take(sizeof(double) * 4 * NR);
-    c.take(FS * nrhs * (m + 1));         // ring
-    c.take(FS * nrhs);                   // p0
-    c.take(FS * nrhs);                   // t
-    c.take(FS * nrhs * nshift);          // p_j
+    if (ps == P_F48) {
+        // p_j first, then the ring, p0 and t, spanning at least nrhs*nshift
+        // FP64 fields (MsScratch::xlend)
+        c.take(FS * nrhs * nshift);
+        c.take(std::max(FS * nrhs * (m + 3), F * nrhs * nshift));
+    } else {
+        c.take(FS * nrhs * (m + 1));     // ring
+        c.take(FS * nrhs);               // p0
+        c.take(FS * nrhs);               // t
+        c.take(FS * nrhs * nshift);      // p_j
+    }
     if (keep_x && !ext_x) c.take(F * nrhs * nshift);   // x_j
-    if (keep_x || ps != P_F64) {
+    if (keep_x || ps == P_F32) {
         c.take(F * nrhs);                // FP64 scratch (verification, residual replacement)
         c.take(F * nrhs);
     }
@@ -460,7 +567,11 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     const int m = o.m;
     if (m < 1 || m > MB || R > NR) return OVL_ERR_INVALID;
     if (o.reliable && !o.keep_x) return OVL_ERR_INVALID;
-    const void *Us = PS == P_F64 ? U->f64 : U->f32;
+    // 48-bit storage: y mode of a fresh solve on an unshifted base (the t
+    // recurrence; neither p0 nor the base-direction update is needed)
+    if (PS == P_F48 && (o.keep_x || o.resume || o.rhs_shift || *std::min_element(shifts, shifts + nshift) != 0.0))
+        return OVL_ERR_INVALID;
+    const void *Us = PS == P_F32 ? U->f32 : U->f64;
     if (!Us || !U->f64) return OVL_ERR_INVALID;
     WsCarve c{ws, 0, ws_bytes};
     const size_t F = field_bytes(P_F64, L.V), FS = field_bytes(PS, L.V);
@@ -468,13 +579,24 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     Blk *BK = (Blk *)c.take(sizeof(Blk));
     double *partials = (double *)c.take(sizeof(double) * 2 * R * nblk);
     double *red = (double *)c.take(sizeof(double) * 4 * NR);
-    char *ring = (char *)c.take(FS * R * (m + 1));
-    Fld p0{c.take(FS * R), nullptr, PS, R};
-    Fld t{c.take(FS * R), nullptr, PS, R};
-    Fld pj{c.take(FS * R * nshift), nullptr, PS, R * nshift};
+    char *ring;
+    Fld p0{nullptr, nullptr, PS, R}, t{nullptr, nullptr, PS, R}, pj{nullptr, nullptr, PS, R * nshift};
+    void *xlend = nullptr;
+    if (PS == P_F48) {
+        pj.d = c.take(FS * R * nshift);
+        xlend = c.take(std::max(FS * R * (m + 3), F * R * nshift));
+        ring = (char *)xlend;
+        p0.d = ring + FS * R * (m + 1);
+        t.d = ring + FS * R * (m + 2);
+    } else {
+        ring = (char *)c.take(FS * R * (m + 1));
+        p0.d = c.take(FS * R);
+        t.d = c.take(FS * R);
+        pj.d = c.take(FS * R * nshift);
+    }
     Fld xs{}, s1{}, s2{};
     if (o.keep_x) xs = {o.x_ext.d ? o.x_ext.d : c.take(F * R * nshift), nullptr, P_F64, R * nshift};
-    if (o.keep_x || PS != P_F64) {
+    if (o.keep_x || PS == P_F32) {
         s1 = {c.take(F * R), nullptr, P_F64, R};
         s2 = {c.take(F * R), nullptr, P_F64, R};
     }
@@ -492,7 +614,8 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         // continue the recurrences of a switched solve: same scalars, the
         // vectors r, p0 and p_j rounded to this precision, x_j kept
         const MsScratch &rs = *o.resume;
-        if (!o.keep_x || rs.r.nrhs != R || rs.pj.nrhs != R * nshift || rs.pj.prec != P_F64) return OVL_ERR_INVALID;
+        if (!o.keep_x || rs.r.nrhs != R || rs.pj.nrhs != R * nshift || (rs.pj.prec != P_F64 && rs.pj.prec != P_F48))
+            return OVL_ERR_INVALID;
         j0 = rs.j0;
         OVL_HIP(hipMemcpyAsync(S, rs.S, sizeof(MState), hipMemcpyDeviceToDevice, st));
         OVL_HIP(launch_convert(L, rs.r, Fld{slot(0), nullptr, PS, R}, st));
@@ -527,7 +650,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     // the current iteration.
     // (not in the FP16-storage measurement mode, whose subject is the stored p0
     // and Q p0)
-    const bool trec = rmode == W_RUPDATE0 && (PS == P_F64 || (PS == P_F32 && !o.f16.d));
+    const bool trec = rmode == W_RUPDATE0 && (PS == P_F64 || PS == P_F48 || (PS == P_F32 && !o.f16.d));
     const Fld pj0 = sub(pj, L.V, j0 * R, R);
     ShiftWeights sw;
     for (int j = 0; j < NS; j++) sw.w[j] = (weights && j < nshift) ? weights[j] : 0.0;
@@ -613,15 +736,10 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         // blocks of up to 16 take the build that holds 16 residuals in
         // registers (more waves per SIMD)
         const int first = !o.resume && passes == 0;
-        const double2 *p64in =
-            PS == P_F32 && o.resume && passes == 0 ? (const double2 *)o.resume->pj.d : nullptr;
+        const void *pin = PS == P_F32 && o.resume && passes == 0 ? o.resume->pj.d : nullptr;
+        const bool pin48 = pin && o.resume->pj.prec == P_F48;
         const int xzero = passes == 0 ? o.x_zero_shifts : 0;
-        if (m <= 16)
-            k_blk_pass<PS, 16>
-                <<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in, xzero);
-        else
-            k_blk_pass<PS, MB>
-                <<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, p64in, xzero);
+        launch_blk_pass<PS>(m, pin48, sgrid, st, L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, pin, xzero);
         int e7 = prof.mark();
         k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
         OVL_HIP(hipGetLastError());
@@ -707,6 +825,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         scr->p0 = trec ? pj0 : p0;
         scr->pj = pj;
         scr->j0 = j0;
+        scr->xlend = xlend;
     }
     if (stats) {
         stats->stencil_applies += 2 * (int)k + 2 * replacements;
@@ -720,7 +839,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         // A fresh solve's first pass reads b once per RHS in place of the p_j
         // and writes every p_j.
         const double Fs = (double)FS, F8 = (double)F;
-        const double G = (double)L.V * 4 * (PS == P_F64 ? 96.0 : 48.0);
+        const double G = (double)L.V * 4 * (PS == P_F32 ? 48.0 : 96.0);
         const bool fresh = !o.resume;
         // (with the t recurrence: K_A 3F + links, K_B 3F + links, no K_C)
         double sten = iters_all * ((rmode == W_RUPDATE0 && !trec ? 5 : 6) * Fs + 2 * G);
@@ -730,8 +849,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             for (int j = 0; j < nshift; j++) {
                 int np = (fz[q][j] + m - 1) / m;
                 double pj_io = fresh ? (np >= 2 ? 2.0 * np - 2.0 : 1.0) : 2.0 * np - 1.0;
-                // an FP32 solve's first pass reads the FP64 p_j it continues
-                const double wide = !fresh && PS == P_F32 ? F8 - Fs : 0.0;
+                // an FP32 solve's first pass reads the FP64 (or 48-bit) p_j it continues
+                const double wide =
+                    !fresh && PS == P_F32 ? (double)field_bytes(o.resume->pj.prec, L.V) - Fs : 0.0;
                 if (np > 0) pass += pj_io * Fs + wide + (o.keep_x ? 2.0 * np * F8 : 0.0);
             }
         double other = replacements * (R * (2 * 768.0 * L.V + 6 * F8) + R * Fs);
@@ -744,6 +864,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
 }
 
 template int mscg_blocked_t<P_F64>(const Lat &, const ovl_gauge *, double, int, const double *, const double *, Fld,
+                                   Fld, const BlkOpts &, const ovl_solver_params *, ovl_solver_stats *, char *, size_t,
+                                   hipStream_t, MsScratch *);
+template int mscg_blocked_t<P_F48>(const Lat &, const ovl_gauge *, double, int, const double *, const double *, Fld,
                                    Fld, const BlkOpts &, const ovl_solver_params *, ovl_solver_stats *, char *, size_t,
                                    hipStream_t, MsScratch *);
 template int mscg_blocked_t<P_F32>(const Lat &, const ovl_gauge *, double, int, const double *, const double *, Fld,

@@ -175,7 +175,10 @@ __device__ __forceinline__ void st_nt(uint4 *p, unsigned a, unsigned b, unsigned
 }
 
 // ---------------------------------------------------------------- fields
-enum { P_F64 = 0, P_F32 = 1, P_F16S = 2 };
+// P_F48: FP64 arithmetic on fields stored in 48 bits per real (a double
+// rounded to nearest at 36 stored mantissa bits, relative error <= 2^-37);
+// its gauge links are the FP64 ones.
+enum { P_F64 = 0, P_F32 = 1, P_F16S = 2, P_F48 = 3 };
 
 template <int PREC>
 struct Real {
@@ -183,6 +186,10 @@ struct Real {
 };
 template <>
 struct Real<P_F64> {
+    using T = double;
+};
+template <>
+struct Real<P_F48> {
     using T = double;
 };
 
@@ -322,10 +329,117 @@ struct SpinorRef<P_F16S> {
     }
 };
 
+// 48-bit storage of a double: the top 48 bits of its IEEE pattern after
+// rounding the dropped 16 bits to nearest (ties away from zero; a carry moves
+// into the exponent as it should).  Infinities and NaNs keep their top bits.
+__device__ __forceinline__ unsigned long long f48_bits(double x)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const bool special = (u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
+    return special ? u : u + 0x8000ull;
+}
+__device__ __forceinline__ double f48_value(unsigned hi, unsigned lo16)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | ((unsigned long long)lo16 << 16)));
+}
+__device__ __forceinline__ unsigned f48_hi(unsigned long long b) { return (unsigned)(b >> 32); }
+__device__ __forceinline__ unsigned f48_lo(unsigned long long b) { return (unsigned)(b >> 16) & 0xffffu; }
+
+// The 48-bit layout: per site and parity 9 arrays of 16-byte elements (stride
+// Vh).  Arrays 0..5 hold the top 32 bits of complex numbers 2k and 2k+1
+// (re, im, re, im); arrays 6..8 the low 16 bits of complex numbers 4g..4g+3,
+// word q = lo(re) | lo(im) << 16.  Complex number k is spin k/3, colour k%3.
+struct F48Code {
+    uint4 h[6], l[3];
+};
+__device__ __forceinline__ void f48_decode(const F48Code &c, cplx<double> s[4][3])
+{
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const uint4 &h = c.h[k / 2];
+        const uint4 &l = c.l[k / 4];
+        const unsigned hr = (k & 1) ? h.z : h.x, hi = (k & 1) ? h.w : h.y;
+        const unsigned lw = (k & 3) == 0 ? l.x : (k & 3) == 1 ? l.y : (k & 3) == 2 ? l.z : l.w;
+        s[k / 3][k % 3] = {f48_value(hr, lw & 0xffffu), f48_value(hi, lw >> 16)};
+    }
+}
+__device__ __forceinline__ void f48_encode(const cplx<double> s[4][3], F48Code &c)
+{
+    unsigned hw[24], lw[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const unsigned long long br = f48_bits(s[k / 3][k % 3].x), bi = f48_bits(s[k / 3][k % 3].y);
+        hw[2 * k] = f48_hi(br);
+        hw[2 * k + 1] = f48_hi(bi);
+        lw[k] = f48_lo(br) | (f48_lo(bi) << 16);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) c.h[k] = make_uint4(hw[4 * k], hw[4 * k + 1], hw[4 * k + 2], hw[4 * k + 3]);
+#pragma unroll
+    for (int g = 0; g < 3; g++) c.l[g] = make_uint4(lw[4 * g], lw[4 * g + 1], lw[4 * g + 2], lw[4 * g + 3]);
+}
+
+template <>
+struct SpinorRef<P_F48> {
+    uint4 *d;
+    int Vh;
+    __device__ __forceinline__ void load_raw(int p, int i, F48Code &c) const
+    {
+        const uint4 *b = d + (size_t)p * 9 * Vh + i;
+#pragma unroll
+        for (int k = 0; k < 6; k++) c.h[k] = b[(size_t)k * Vh];
+#pragma unroll
+        for (int k = 0; k < 3; k++) c.l[k] = b[(size_t)(6 + k) * Vh];
+    }
+    __device__ __forceinline__ void load(int p, int i, cplx<double> s[4][3]) const
+    {
+        F48Code c;
+        load_raw(p, i, c);
+        f48_decode(c, s);
+    }
+    __device__ __forceinline__ void load_nt(int p, int i, cplx<double> s[4][3]) const
+    {
+        const uint4 *b = d + (size_t)p * 9 * Vh + i;
+        F48Code c;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            nt_u4 v = __builtin_nontemporal_load((const nt_u4 *)&b[(size_t)k * Vh]);
+            c.h[k] = make_uint4(v.x, v.y, v.z, v.w);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            nt_u4 v = __builtin_nontemporal_load((const nt_u4 *)&b[(size_t)(6 + k) * Vh]);
+            c.l[k] = make_uint4(v.x, v.y, v.z, v.w);
+        }
+        f48_decode(c, s);
+    }
+    __device__ __forceinline__ void store(int p, int i, const cplx<double> s[4][3]) const
+    {
+        uint4 *b = d + (size_t)p * 9 * Vh + i;
+        F48Code c;
+        f48_encode(s, c);
+#pragma unroll
+        for (int k = 0; k < 6; k++) b[(size_t)k * Vh] = c.h[k];
+#pragma unroll
+        for (int k = 0; k < 3; k++) b[(size_t)(6 + k) * Vh] = c.l[k];
+    }
+    __device__ __forceinline__ void store_nt(int p, int i, const cplx<double> s[4][3]) const
+    {
+        uint4 *b = d + (size_t)p * 9 * Vh + i;
+        F48Code c;
+        f48_encode(s, c);
+#pragma unroll
+        for (int k = 0; k < 6; k++) st_nt(&b[(size_t)k * Vh], c.h[k].x, c.h[k].y, c.h[k].z, c.h[k].w);
+#pragma unroll
+        for (int k = 0; k < 3; k++) st_nt(&b[(size_t)(6 + k) * Vh], c.l[k].x, c.l[k].y, c.l[k].z, c.l[k].w);
+    }
+};
+
 // Elements (in the pointer's own unit) of one RHS in each layout, S = stride.
 __host__ __device__ inline size_t spinor_elems(int prec, int S)
 {
-    return prec == P_F64 ? (size_t)24 * S : prec == P_F32 ? (size_t)12 * S : (size_t)6 * S;
+    return prec == P_F64 ? (size_t)24 * S : prec == P_F32 ? (size_t)12 * S : prec == P_F48 ? (size_t)18 * S
+                                                                                            : (size_t)6 * S;
 }
 
 // Gauge links.  Every precision keeps rows 0 and 1 and rebuilds
@@ -403,6 +517,20 @@ struct GaugeRef<P_F32> {
         rebuild_row2(u);
     }
 };
+
+// 48-bit fields use the FP64 links.
+template <>
+struct GaugeRef<P_F48> : GaugeRef<P_F64> {
+};
+
+template <int PREC>
+__device__ __forceinline__ GaugeRef<PREC> gauge_ref(const void *U, int S)
+{
+    GaugeRef<PREC> g;
+    g.d = (decltype(g.d))U;
+    g.Vh = S;
+    return g;
+}
 
 template <>
 struct GaugeRef<P_F16S> {

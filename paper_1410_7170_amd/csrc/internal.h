@@ -27,11 +27,11 @@ int hip_fail(hipError_t e);
     } while (0)
 
 // bytes of one packed field (one RHS) of precision prec, excluding scales:
-// 2 parities x (12, 6 or 3) component arrays of 16-byte elements, padded stride
+// 2 parities x (12, 9, 6 or 3) component arrays of 16-byte elements, padded stride
 inline size_t field_bytes(int prec, int64_t V)
 {
     size_t S = (size_t)padded_stride((int)(V / 2));
-    return prec == P_F64 ? 24 * S * 16 : prec == P_F32 ? 12 * S * 16 : 6 * S * 16;
+    return prec == P_F64 ? 24 * S * 16 : prec == P_F48 ? 18 * S * 16 : prec == P_F32 ? 12 * S * 16 : 6 * S * 16;
 }
 // per-site scales of one F16S field: 2 parities x S floats
 inline size_t scale_bytes(int64_t V) { return (size_t)2 * padded_stride((int)(V / 2)) * 4; }

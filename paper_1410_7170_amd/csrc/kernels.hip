@@ -133,6 +133,8 @@ hipError_t launch_pack_spinor(const Lat &L, const void *canon, Fld out, hipStrea
     dim3 grid((unsigned)((L.V + kBlock - 1) / kBlock), out.nrhs);
     if (out.prec == P_F64)
         k_pack_spinor<P_F64><<<grid, kBlock, 0, st>>>(L.g, L.V, (const double2 *)canon, out.d, out.sc);
+    else if (out.prec == P_F48)
+        k_pack_spinor<P_F48><<<grid, kBlock, 0, st>>>(L.g, L.V, (const double2 *)canon, out.d, out.sc);
     else if (out.prec == P_F32)
         k_pack_spinor<P_F32><<<grid, kBlock, 0, st>>>(L.g, L.V, (const double2 *)canon, out.d, out.sc);
     else
@@ -145,6 +147,8 @@ hipError_t launch_unpack_spinor(const Lat &L, Fld in, void *canon, hipStream_t s
     dim3 grid((unsigned)((L.V + kBlock - 1) / kBlock), in.nrhs);
     if (in.prec == P_F64)
         k_unpack_spinor<P_F64><<<grid, kBlock, 0, st>>>(L.g, L.V, in.d, in.sc, (double2 *)canon);
+    else if (in.prec == P_F48)
+        k_unpack_spinor<P_F48><<<grid, kBlock, 0, st>>>(L.g, L.V, in.d, in.sc, (double2 *)canon);
     else if (in.prec == P_F32)
         k_unpack_spinor<P_F32><<<grid, kBlock, 0, st>>>(L.g, L.V, in.d, in.sc, (double2 *)canon);
     else
@@ -310,6 +314,7 @@ hipError_t launch_norm2(const Lat &L, Fld f, double *partials, hipStream_t st)
 {
     dim3 grid(2 * L.nb, f.nrhs);
     if (f.prec == P_F64) k_norm2<P_F64><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc, partials);
+    else if (f.prec == P_F48) k_norm2<P_F48><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc, partials);
     else if (f.prec == P_F32) k_norm2<P_F32><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc, partials);
     else k_norm2<P_F16S><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc, partials);
     return hipGetLastError();
@@ -318,7 +323,7 @@ hipError_t launch_norm2(const Lat &L, Fld f, double *partials, hipStream_t st)
 hipError_t launch_diff_norm2(const Lat &L, Fld a, Fld b, double *partials, hipStream_t st)
 {
     dim3 grid(2 * L.nb, a.nrhs);
-    if (a.prec != P_F64) return hipErrorInvalidValue;
+    if (a.prec != P_F64 || b.prec == P_F48) return hipErrorInvalidValue;
     if (b.prec == P_F64) k_diff_norm2<P_F64, P_F64><<<grid, kBlock, 0, st>>>(L.g, L.nb, a.d, a.sc, b.d, b.sc, partials);
     else if (b.prec == P_F32) k_diff_norm2<P_F64, P_F32><<<grid, kBlock, 0, st>>>(L.g, L.nb, a.d, a.sc, b.d, b.sc, partials);
     else k_diff_norm2<P_F64, P_F16S><<<grid, kBlock, 0, st>>>(L.g, L.nb, a.d, a.sc, b.d, b.sc, partials);
@@ -344,6 +349,7 @@ static hipError_t convert_to(const Lat &L, Fld s, Fld d, hipStream_t st)
 {
     dim3 grid(2 * L.nb, s.nrhs);
     if (d.prec == P_F64) k_convert<PS, P_F64><<<grid, kBlock, 0, st>>>(L.g, L.nb, s.d, s.sc, d.d, d.sc);
+    else if (d.prec == P_F48) k_convert<PS, P_F48><<<grid, kBlock, 0, st>>>(L.g, L.nb, s.d, s.sc, d.d, d.sc);
     else if (d.prec == P_F32) k_convert<PS, P_F32><<<grid, kBlock, 0, st>>>(L.g, L.nb, s.d, s.sc, d.d, d.sc);
     else k_convert<PS, P_F16S><<<grid, kBlock, 0, st>>>(L.g, L.nb, s.d, s.sc, d.d, d.sc);
     return hipGetLastError();
@@ -352,6 +358,7 @@ static hipError_t convert_to(const Lat &L, Fld s, Fld d, hipStream_t st)
 hipError_t launch_convert(const Lat &L, Fld s, Fld d, hipStream_t st)
 {
     if (s.prec == P_F64) return convert_to<P_F64>(L, s, d, st);
+    if (s.prec == P_F48) return convert_to<P_F48>(L, s, d, st);
     if (s.prec == P_F32) return convert_to<P_F32>(L, s, d, st);
     return convert_to<P_F16S>(L, s, d, st);
 }
@@ -368,6 +375,7 @@ static hipError_t axpby_to(const Lat &L, double a, Fld x, double b, Fld y, hipSt
 
 hipError_t launch_axpby(const Lat &L, double a, Fld x, double b, Fld y, hipStream_t st)
 {
+    if (x.prec == P_F48 || y.prec == P_F48) return hipErrorInvalidValue;   // not needed on 48-bit fields
     if (x.prec == P_F64) return axpby_to<P_F64>(L, a, x, b, y, st);
     if (x.prec == P_F32) return axpby_to<P_F32>(L, a, x, b, y, st);
     return axpby_to<P_F16S>(L, a, x, b, y, st);
@@ -377,6 +385,7 @@ hipError_t launch_zero(const Lat &L, Fld f, hipStream_t st)
 {
     dim3 grid(2 * L.nb, f.nrhs);
     if (f.prec == P_F64) k_zero<P_F64><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc);
+    else if (f.prec == P_F48) k_zero<P_F48><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc);
     else if (f.prec == P_F32) k_zero<P_F32><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc);
     else k_zero<P_F16S><<<grid, kBlock, 0, st>>>(L.g, L.nb, f.d, f.sc);
     return hipGetLastError();

@@ -32,6 +32,7 @@
 // extra system is neither verified, refined nor combined, and the caller's
 // per-shift statistics exclude it.  It converges last, as the smallest shift
 // did, a small fraction of an iteration later.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -66,7 +67,16 @@ static size_t region_b_bytes(const Lat &L, int nrhs, int nshift, int m)
 // unshifted base)
 static int mixed_systems(int nshift) { return nshift < NS ? nshift + 1 : nshift; }
 
-size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift_caller, int m, int m64, bool f64_phase, bool f16_store)
+// Workspace of the FP64 phase: FP64 storage, or room for either form with
+// 48-bit storage (which falls back to FP64 storage without an unshifted base)
+static size_t phase64_ws_bytes(const Lat &L, int nrhs, int nshift, int m64, bool s48)
+{
+    const size_t w = blocked_ws_bytes(L, nrhs, nshift, m64, false, P_F64);
+    return s48 ? std::max(w, blocked_ws_bytes(L, nrhs, nshift, m64, false, P_F48)) : w;
+}
+
+size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift_caller, int m, int m64, bool f64_phase, bool f16_store,
+                      bool s48)
 {
     const size_t F = field_bytes(P_F64, L.V);
     const int nshift = mixed_systems(nshift_caller);
@@ -86,7 +96,7 @@ size_t mixed_ws_bytes(const Lat &L, int nrhs, int nshift_caller, int m, int m64,
     c.take(sizeof(double) * 4 * NR);
     c.take(sizeof(double) * NR * NS);                 // shift of each (shift, RHS) field
     c.take(sizeof(double) * NR * NS);                 // zeta at the hand-over of each field
-    if (f64_phase) c.take(blocked_ws_bytes(L, nrhs, nshift, m64, false, P_F64));
+    if (f64_phase) c.take(align256(phase64_ws_bytes(L, nrhs, nshift, m64, s48)));
     c.take(region_b_bytes(L, nrhs, nshift, m));
     return c.off + 256;
 }
@@ -155,7 +165,9 @@ static int mixed_solve(const Lat &L, const ovl_gauge *U, double m0, int nshift, 
     double *fsh = (double *)c.take(sizeof(double) * NR * NS);
     double *fze = (double *)c.take(sizeof(double) * NR * NS);
     // region A (FP64 phase), then region B
-    const size_t w64 = f64_phase ? align256(blocked_ws_bytes(L, R, nshift, m64, false, P_F64)) : 0;
+    // 48-bit storage of the FP64 phase's vectors needs the unshifted base
+    const bool s48 = f64_phase && prm->store48 && *std::min_element(shifts, shifts + nshift) == 0.0;
+    const size_t w64 = f64_phase ? align256(phase64_ws_bytes(L, R, nshift, m64, prm->store48 != 0)) : 0;
     char *sws = ws + c.off;
     char *swb = sws + w64;
     const size_t swb_bytes = ws_bytes - c.off - w64;
@@ -192,7 +204,8 @@ static int mixed_solve(const Lat &L, const ovl_gauge *U, double m0, int nshift, 
         o64.m = m64;
         o64.switch_rel = prm->sloppy_below;
         MsScratch h64{};
-        rc = mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, weights, b, y, o64, prm, stats, sws, w64, st, &h64);
+        rc = s48 ? mscg_blocked_t<P_F48>(L, U, m0, nshift, shifts, weights, b, y, o64, prm, stats, sws, w64, st, &h64)
+                 : mscg_blocked_t<P_F64>(L, U, m0, nshift, shifts, weights, b, y, o64, prm, stats, sws, w64, st, &h64);
         if (rc < 0) return rc;
         if (rc != kSwitched) return rc;   // converged (or stopped) within the FP64 phase: y is complete
         switched = true;
@@ -210,13 +223,18 @@ static int mixed_solve(const Lat &L, const ovl_gauge *U, double m0, int nshift, 
             for (int q = 0; q < R; q++)
                 if (frozen_res[(size_t)j * R + q] < 0.0) nz = j + 1;
         // keep r0 outside the solver workspace, which the refinement reuses
-        OVL_HIP(hipMemcpyAsync(R0.d, h64.r.d, F * R, hipMemcpyDeviceToDevice, st));
+        if (h64.r.prec == P_F64) OVL_HIP(hipMemcpyAsync(R0.d, h64.r.d, F * R, hipMemcpyDeviceToDevice, st));
+        else OVL_HIP(launch_convert(L, h64.r, R0, st));
         r0 = R0;
         o.resume = &h64;
         o.x_zero_shifts = nz;   // the increments dx_j (j < nz) start at zero
-        // dx_j take over the FP64 p_j, which the first pass reads in place
-        if (h64.pj.prec != P_F64 || h64.pj.nrhs != R * nshift) return OVL_ERR_INVALID;
-        X.d = h64.pj.d;
+        // dx_j take over the FP64 p_j, which the first pass reads in place;
+        // with 48-bit storage they go over the phase's dead ring, p0 and t
+        // (xlend), and the first pass reads the 48-bit p_j from their fields
+        if (h64.pj.nrhs != R * nshift) return OVL_ERR_INVALID;
+        if (h64.pj.prec == P_F64) X.d = h64.pj.d;
+        else if (h64.pj.prec == P_F48 && h64.xlend) X.d = h64.xlend;
+        else return OVL_ERR_INVALID;
         o.x_ext = X;
         // the base system's true residual during the sloppy phase is r0 - (Q^2 + s0) dx_0
         rc = mscg_blocked_t<P_F32>(L, U, m0, nshift, shifts, nullptr, r0, Fld{}, o, prm, stats, swb, swb_bytes, st,
@@ -369,7 +387,7 @@ int mscg_mixed(const Lat &L, const ovl_gauge *U, double m0, int nshift, const do
 {
     if (!weights) return OVL_ERR_INVALID;
     if (ws_bytes < mixed_ws_bytes(L, b.nrhs, nshift, mixed_block(prm), mixed_block_f64(prm), prm->sloppy_below > 0.0,
-                                  prm->sloppy_f16 != 0))
+                                  prm->sloppy_f16 != 0, prm->store48 != 0))
         return OVL_ERR_WORKSPACE;
     bool base0 = mixed_systems(nshift) > nshift;
     for (int j = 0; j < nshift; j++) base0 = base0 && shifts[j] > 0.0;

@@ -111,6 +111,9 @@ struct MsScratch {
     MState *S = nullptr;
     Fld r{}, p0{}, pj{};
     int j0 = 0;
+    // a switched y-mode solve with 48-bit storage: room for nrhs*nshift FP64
+    // fields over its dead ring, p0 and t, where a solve continuing it keeps x_j
+    void *xlend = nullptr;
 };
 
 // alpha and the shifted zeta_j', alpha_j (one block per RHS); defined in solver.hip

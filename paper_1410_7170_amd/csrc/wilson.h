@@ -65,6 +65,12 @@ __device__ __forceinline__ SpinorRef<P_F32> spinor_ref<P_F32>(const void *base, 
 }
 
 template <>
+__device__ __forceinline__ SpinorRef<P_F48> spinor_ref<P_F48>(const void *base, const float *, int S, int r)
+{
+    return {(uint4 *)base + (size_t)r * 18 * S, S};
+}
+
+template <>
 __device__ __forceinline__ SpinorRef<P_F16S> spinor_ref<P_F16S>(const void *base, const float *sc, int S, int r)
 {
     return {(uint4 *)base + (size_t)r * 6 * S, (float *)sc + (size_t)r * 2 * S, S};
@@ -206,6 +212,38 @@ struct LdsPsi<P_F64, NT> {
     }
 };
 
+// 48-bit fields keep their encoding in LDS (36 KB per 256 sites): the
+// streaming kernel stores the words it loaded for the next slice's centres
+// (store_raw), so a slice costs no encode.
+template <int NT>
+struct LdsPsi<P_F48, NT> {
+    using E = uint4;
+    static constexpr int NC = 9;
+    E (*d)[NT];
+    __device__ __forceinline__ void store(int l, const cplx<double> s[4][3]) const
+    {
+        F48Code c;
+        f48_encode(s, c);
+        store_raw(l, c);
+    }
+    __device__ __forceinline__ void store_raw(int l, const F48Code &c) const
+    {
+#pragma unroll
+        for (int k = 0; k < 6; k++) d[k][l] = c.h[k];
+#pragma unroll
+        for (int k = 0; k < 3; k++) d[6 + k][l] = c.l[k];
+    }
+    __device__ __forceinline__ void load(int l, cplx<double> s[4][3]) const
+    {
+        F48Code c;
+#pragma unroll
+        for (int k = 0; k < 6; k++) c.h[k] = d[k][l];
+#pragma unroll
+        for (int k = 0; k < 3; k++) c.l[k] = d[6 + k][l];
+        f48_decode(c, s);
+    }
+};
+
 // Neighbour spinor from the slice's LDS copy (local index ln) when inside,
 // else from memory (parity pn, index jn): one generic-pointer load path for
 // both, so the compiler need not carry both versions.  The LDS and memory
@@ -228,6 +266,13 @@ __device__ __forceinline__ void load_either(const LdsPsi<PREC, NT> &lp, const Sp
         if constexpr (PREC == P_F64) {
 #pragma unroll
             for (int k = 0; k < 12; k++) s[k / 3][k % 3] = {v[k].x, v[k].y};
+        } else if constexpr (PREC == P_F48) {
+            F48Code c;
+#pragma unroll
+            for (int k = 0; k < 6; k++) c.h[k] = v[k];
+#pragma unroll
+            for (int k = 0; k < 3; k++) c.l[k] = v[6 + k];
+            f48_decode(c, s);
         } else {
 #pragma unroll
             for (int k = 0; k < 6; k++) {
@@ -403,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
     const Geom &g = a.g;
     const bool valid = jl < g.Vh;
     const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.S, r);
-    const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.S};
+    const GaugeRef<PREC> U = gauge_ref<PREC>(a.U, g.S);
     double q0 = 0.0, q1 = 0.0;
     if (valid) {
         int x[4];
@@ -526,14 +571,14 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
     x[3] = sidx % L3;
     x[2] = (sidx / L3) % L2;
     x[1] = sidx / (L3 * L2);
-    const int Ts = PREC == P_F64 && g.Ts64 > 0 ? g.Ts64 : g.Ts;
+    const int Ts = (PREC == P_F64 || PREC == P_F48) && g.Ts64 > 0 ? g.Ts64 : g.Ts;
     const int t0 = tc * Ts;
     // tiles: field pointers at the tile's first RHS (uniform), the lane's RHS
     // as an element offset of the site index (32-bit, in vector registers)
     const int rb = TILED ? rt * K : r;
     const int lo = TILED ? (r - rb) * (int)spinor_elems(PREC, g.S) : 0;
     const SpinorRef<PREC> in = spinor_ref<PREC>(a.in, a.in_sc, g.S, rb);
-    const GaugeRef<PREC> U{(decltype(GaugeRef<PREC>::d))a.U, g.S};
+    const GaugeRef<PREC> U = gauge_ref<PREC>(a.U, g.S);
     const int sp = x[1] + x[2] + x[3];   // parity of the spatial part
     cplx<T> cen[4][3], w[2][3];   // centre of the current slice, backward-hop carry
     {
@@ -578,10 +623,20 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
         U.load_nt(p, 0, i, u);   // U_0(t) is read by the K lanes of this site only
         tback_half(w, cen, u);
         const T dn2 = diag_minus_half(acc, cen, (T)a.diag);
+        // 48-bit staged builds keep the next centre's words as loaded, store
+        // them to LDS unchanged and decode the centre back from there, so the
+        // decoded centre is not held across the epilogue
+        constexpr bool kRaw = PREC == P_F48 && STAGE;
+        F48Code raw;
         {
             // forward time hop, subtracted with its factor -1/2 straight into v
             int y[4] = {t + 1 == L0 ? 0 : t + 1, x[1], x[2], x[3]};
-            in.load(1 - p, cb_index(g, y) + lo, cen);
+            if constexpr (kRaw) {
+                in.load_raw(1 - p, cb_index(g, y) + lo, raw);
+                f48_decode(raw, cen);
+            } else {
+                in.load(1 - p, cb_index(g, y) + lo, cen);
+            }
             cplx<T> f[4][3];
 #pragma unroll
             for (int s = 0; s < 4; s++)
@@ -597,8 +652,10 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
         if (STAGE) {
             // every thread has read this slice's copy: replace it by the next slice
             __syncthreads();
-            lp.store(threadIdx.x, cen);
+            if constexpr (kRaw) lp.store_raw(threadIdx.x, raw);
+            else lp.store(threadIdx.x, cen);
             __syncthreads();
+            if constexpr (kRaw) lp.load(threadIdx.x, cen);
         }
     }
     if (MODE == W_NORM || MODE == W_SNORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {

@@ -163,3 +163,15 @@ def load_golden(path):
     for r in rhs:
         r["vals"] = np.array(r["vals"])
     return dict(meta=meta, sites=sites, rhs=rhs)
+
+
+def r48(a):
+    """Each real of a complex128 array rounded to the 48-bit storage format:
+    the top 48 bits of its IEEE pattern after rounding the dropped 16 to
+    nearest, ties away from zero (adding half a unit of the kept part to the
+    magnitude bits); infinities and NaNs keep their top bits."""
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    x = a.view(np.uint64).copy()
+    special = (x & np.uint64(0x7FF0000000000000)) == np.uint64(0x7FF0000000000000)
+    y = np.where(special, x, x + np.uint64(0x8000)) & np.uint64(0xFFFFFFFFFFFF0000)
+    return y.view(np.complex128).reshape(a.shape)

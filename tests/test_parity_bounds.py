@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from parity import f16s_stencil_check, field_check, stencil_check
+from parity import f16s_stencil_check, field_check, r48, stencil_check
 
 M0 = -1.6
 DIMS = (4, 4, 6, 4)
@@ -93,3 +93,22 @@ def test_field_check_spread_error_passes_single_site_fails(field):
     bad = got.copy()
     bad[5, 0, 0] += 1e-6 * np.abs(ref).max()
     assert field_check(bad, ref, DIMS, 1e-10)[0] > 1.0
+
+
+def test_r48_definition_on_hand_values():
+    """The 48-bit rounding emulation of the GPU tests, on values whose
+    rounding is known by hand."""
+    def d(bits):
+        return np.array([bits], dtype=np.uint64).view(np.float64)[0]
+    one = 0x3FF0000000000000
+    cases = [
+        (one | 0x7FFF, one),                       # below half an ulp: down
+        (one | 0x8000, one | 0x10000),             # a tie: away from zero
+        (one | 0x18000, one | 0x20000),            # a tie above an odd unit: away from zero
+        (0x3FFFFFFFFFFF8000, 0x4000000000000000),  # the carry moves into the exponent
+        (0xBFF0000000008000, 0xBFF0000000010000),  # negative tie: larger magnitude
+        (0x7FF0000000000000, 0x7FF0000000000000),  # infinity stays
+    ]
+    for src, want in cases:
+        got = r48(np.array([complex(d(src), 0.0)]))[0].real
+        assert np.array([got]).view(np.uint64)[0] == want, (hex(src), got)

@@ -533,7 +533,7 @@ OVL_API size_t ovl_workspace_bytes(const ovl_lattice *lat, int32_t op, int32_t p
                            int32_t nshift, const ovl_solver_params *prm);
 
 /* Defaults: tol 1e-10, maxiter 2000, FP64 mode, reliable_delta 0.1,
- * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 1e-5,
+ * check_every 10, refine 1, verify 0, profile 0, block 0, sloppy_below 3e-5,
  * block_f64 0, rhs_group 0, deflation NULL, sloppy_f16 0, even_odd 0, store48 1. */
 OVL_API void ovl_default_params(ovl_solver_params *prm);
 

@@ -386,7 +386,7 @@ void ovl_default_params(ovl_solver_params *p)
     p->verify = 0;
     p->profile = 0;
     p->block = 0;
-    p->sloppy_below = 1e-5;
+    p->sloppy_below = 3e-5;
     p->block_f64 = 0;
     p->rhs_group = 0;
     p->deflation = nullptr;

@@ -300,3 +300,23 @@ def test_even_odd_wilson_solve_fields(ovl):
         assert lib.ovl_overlap_solve_workspace_bytes(lat.ref, 12, ctypes.byref(q)) == 0
     q = ovl.default_outer_params(precondition=1, prec_m0=-0.5, prec_even_odd=1)
     assert lib.ovl_overlap_solve_workspace_bytes(lat.ref, 12, ctypes.byref(q)) > 0
+
+
+def test_store48_field_and_f48_sizes(ovl):
+    """store48 in {0, 1} (default 1, hand-over default 3e-5); a 48-bit field
+    takes 3/4 of an FP64 one; the mixed workspace with 48-bit storage is sized
+    for either form of the FP64 phase (it falls back to FP64 storage without
+    an unshifted base), so it is at least the FP64-storage size."""
+    lat = ovl.Lattice((8, 4, 4, 8))
+    lib = ovl._lib
+    p = ovl.default_params()
+    assert p.store48 == 1 and p.sloppy_below == 3e-5
+    assert lib.ovl_spinor_bytes(lat.ref, ovl.F48) * 4 == lib.ovl_spinor_bytes(lat.ref, ovl.F64) * 3
+    assert lib.ovl_gauge_bytes(lat.ref, ovl.F48) == 0    # links exist in F64, F32 and F16 only
+    ws = {s: lib.ovl_workspace_bytes(lat.ref, ovl.OP_MSCG, ovl.F64, 1, 20,
+                                     ctypes.byref(ovl.default_params(mode=ovl.SOLVE_MIXED, store48=s)))
+          for s in (0, 1)}
+    assert ws[0] > 0 and ws[1] >= ws[0]
+    for bad in (2, -1):
+        q = ovl.default_params(mode=ovl.SOLVE_MIXED, store48=bad)
+        assert lib.ovl_workspace_bytes(lat.ref, ovl.OP_MSCG, ovl.F64, 1, 20, ctypes.byref(q)) == 0

@@ -241,9 +241,12 @@ typedef struct {
                                 shifted directions p_j) in 48 bits per real
                                 (OVL_F48: rounded to nearest at 36 stored
                                 mantissa bits, relative error <= 2^-37), with
-                                FP64 links and arithmetic; that rounding enters
-                                the residuals some 1e-11 below their size,
-                                under the 1e-10 target.  It needs the phase's
+                                FP64 links and arithmetic.  The rounding opens
+                                a gap of about 1e-12 |b| between recursive and
+                                true residuals, which the verification does not
+                                see, so the solve then aims at 0.9 tol (the
+                                reported residuals are then <= 0.9 tol).  It
+                                needs the phase's
                                 unshifted base system (positive caller shifts,
                                 fewer than OVL_MAX_SHIFTS of them) and falls
                                 back to FP64 storage without it.  0: FP64 */

@@ -168,6 +168,19 @@ static int mixed_solve(const Lat &L, const ovl_gauge *U, double m0, int nshift, 
     // 48-bit storage of the FP64 phase's vectors needs the unshifted base
     const bool s48 = f64_phase && prm->store48 && *std::min_element(shifts, shifts + nshift) == 0.0;
     const size_t w64 = f64_phase ? align256(phase64_ws_bytes(L, R, nshift, m64, prm->store48 != 0)) : 0;
+    // The 48-bit rounding of the FP64 phase (2^-37 relative, made while |r| is
+    // still of the order of |b|) opens a gap between the recursive and the true
+    // residuals, about 1e-12 |b| in a CPU simulation of the format on an 8^4
+    // field, that neither the residuals recorded for shifts frozen in that phase
+    // nor the verification of the others (which starts from the hand-over
+    // residual) sees.  The solve then aims at 0.9 tol, so that the true
+    // residuals stay within tol with a tenth of it to spare.
+    ovl_solver_params p48;
+    if (s48) {
+        p48 = *prm;
+        p48.tol = 0.9 * prm->tol;
+        prm = &p48;
+    }
     char *sws = ws + c.off;
     char *swb = sws + w64;
     const size_t swb_bytes = ws_bytes - c.off - w64;

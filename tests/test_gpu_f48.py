@@ -11,8 +11,9 @@ bounds the terms summed at x; the output rounding is at most 2^-37 of the
 component, and a CPU emulation of the format, Q^2 included, stays at 0.15 of
 that bound).  The mixed solver with 48-bit storage must meet the FP64
 storage's bar: every shifted system's FP64 true residual <= 1e-10 (library
-verification), D_ov within 1e-8 of the oracle, and within 1e-9 of the
-FP64-storage form, with the same iteration count up to one.
+verification, which aims at 0.9e-10 with 48-bit storage), D_ov within 1e-8 of
+the oracle, and within 1e-9 of the FP64-storage form, with the same iteration
+count up to one.
 """
 import sys
 
@@ -171,8 +172,10 @@ def test_mixed_store48_matches_fp64_storage_and_oracle(ovl, dims, nrhs, sloppy_b
     got48, st48 = overlap(ovl, lat, G, s, w, b, nrhs, sloppy_below=sloppy_below, store48=1)
     got64, st64 = overlap(ovl, lat, G, s, w, b, nrhs, sloppy_below=sloppy_below, store48=0)
     for r in range(nrhs):
+        # with 48-bit storage the solve aims at 0.9 tol (the rounding's gap
+        # between recursive and true residuals stays below the tenth left)
         tr = np.array(st48["true_residual"][r])
-        assert (tr > 0).all() and (tr <= 1e-10).all(), (r, tr)
+        assert (tr > 0).all() and (tr <= 0.9e-10 * (1 + 1e-9)).all(), (r, tr)
         assert abs(st48["iterations"][r] - st64["iterations"][r]) <= 1, (st48["iterations"], st64["iterations"])
         ratio, _ = field_check(got48[r], got64[r], dims, 1e-9)
         assert ratio <= 1.0, ("vs FP64 storage", r, ratio)

@@ -275,7 +275,9 @@ struct RingPtrs {
 // iteration in the block).  The block's shifts all lie below xzero.
 // The 48-bit 16-slot build is held to three waves per SIMD (its residuals
 // take 6 registers a slot; left alone it takes 173 and two waves, 3.25 ms a
-// pass at 32^3x64 against 3.02 ms at three waves with a 28-byte spill).
+// pass at 32^3x64 against 2.94-3.02 ms at three waves with a 28-byte spill;
+// the low words of the residuals kept in LDS instead fit 149 registers
+// without spilling but took 3.11 ms).
 template <int PS, int MBT, bool PIN48 = false>
 __global__ __launch_bounds__(kBlock, PS == P_F48 && MBT <= 16 ? 3 : 1) void k_blk_pass(Geom g, int nb, const MState *st, const Blk *bk, RingPtrs ring,
                                                      ShiftWeights w, void *pfv, double2 *xf, double2 *y, int nrhs,

@@ -57,14 +57,17 @@ __global__ __launch_bounds__(kBlock) void k_ms_alpha(MState *st, const double *p
         if (j < NS) st->act_cur[r][j] = 0;
         return;
     }
+    // |t|^2 + s0 |p|^2; an unshifted base needs no |p|^2 (its t stencil writes
+    // only the first set of partials)
+    const double s0 = st->s0r[r];
     double a = 0.0, b = 0.0;
     for (int k = threadIdx.x; k < cnt; k += kBlock) {
         a += partials[(size_t)r * nblk + k];
-        b += partials[(size_t)(nr + r) * nblk + k];
+        if (s0 != 0.0) b += partials[(size_t)(nr + r) * nblk + k];
     }
     const double tt = block_sum_all(a, lds);
     const double pp = block_sum_all(b, lds + 4);
-    const double pq = tt + st->s0r[r] * pp;
+    const double pq = tt + s0 * pp;
     const double alpha = st->rr[r] / pq;
     if (!isfinite(alpha) || !(pq > 0.0)) {
         if (j < st->nshift) st->act_cur[r][j] = 0;

@@ -20,7 +20,8 @@ enum WMode {
     W_RESNORM = 4,   // partial |rin - (Gamma_5 D in + shift * p)|^2, nothing stored
     W_RUPDATE0 = 5,  // r  -= alpha_r Gamma_5 D in (an unshifted system: p is not read);
                      // partial |r|^2
-    W_SNORM = 6,     // out = Gamma_5 D in + shift * p; partials |out|^2, |in(x)|^2
+    W_SNORM = 6,     // out = Gamma_5 D in + shift * p; partial |out|^2 (t = Q r + beta t of an
+                     // unshifted base, whose alpha needs no |p|^2)
 };
 
 struct WArgs {
@@ -371,7 +372,6 @@ __device__ __forceinline__ void site_out(const WArgs &a, int r, int rb, int lo, 
 #pragma unroll
             for (int c = 0; c < 3; c++) n0 += norm2(o[s][c]);
         q0 += live ? (double)n0 : 0.0;
-        q1 += live ? (double)dn2 : 0.0;
     }
     if (MODE == W_RUPDATE || MODE == W_RUPDATE0) {
         cplx<T> rv[4][3];
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(WArgs a)
     if (MODE == W_NORM || MODE == W_SNORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
         double t0 = block_sum(q0, lds);
         if (threadIdx.x == 0) a.partials[(size_t)r * nb + lb] = t0;
-        if (MODE == W_NORM || MODE == W_SNORM) {
+        if (MODE == W_NORM) {
             double t1 = block_sum(q1, lds + 4);
             if (threadIdx.x == 0) a.partials[(size_t)(a.nrhs + r) * nb + lb] = t1;
         }
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(NT, WPE) void k_wilson_ts(WArgs a)
         }
     }
     if (MODE == W_NORM || MODE == W_SNORM || MODE == W_RUPDATE || MODE == W_RUPDATE0 || MODE == W_RESNORM) {
-        constexpr int nq = MODE == W_NORM || MODE == W_SNORM ? 2 : 1;
+        constexpr int nq = MODE == W_NORM ? 2 : 1;
         double t0s = block_sum_k<NT / 64>(q0, lds, kr);
         double t1s = nq == 2 ? block_sum_k<NT / 64>(q1, lds + (NT / 64) * 8, kr) : 0.0;
         // thread q of the first K holds RHS rt*K + q's sums; the zeroed slots

@@ -192,8 +192,11 @@ typedef struct {
                                 those above tol (1) or only report (0) */
     int32_t verify;          /* FP64 mode: also compute every shift's FP64 true
                                 residual into stats (2 FP64 stencils per shift) */
-    int32_t profile;         /* bracket the solver's kernels with HIP events on
-                                the call's stream and fill the kernel_* stats */
+    int32_t profile;         /* time the solver's kernels with HIP events on
+                                the call's stream and fill the kernel_* stats:
+                                1 every class, 2 the stencils only (each timed
+                                kernel costs a little; 2 keeps the cost to the
+                                dominant class); 0 (default) none */
     int32_t block;           /* FP64 mode: 0 updates every shifted vector in every
                                 iteration; m = 1..OVL_MAX_BLOCK keeps the last m residuals
                                 and updates each shifted vector once per m

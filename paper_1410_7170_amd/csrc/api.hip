@@ -103,7 +103,7 @@ bool params_ok(const ovl_solver_params *p)
            p->reliable_delta > 0.0 &&
            p->reliable_delta < 1.0 && p->block >= 0 && p->block <= OVL_MAX_BLOCK && p->block_f64 >= 0 && p->block_f64 <= OVL_MAX_BLOCK && p->sloppy_below >= 0.0 &&
            p->sloppy_below < 1.0 && p->rhs_group >= 0 && (p->sloppy_f16 == 0 || p->sloppy_f16 == 1) && (p->store48 == 0 || p->store48 == 1) &&
-           (p->even_odd == 0 || p->even_odd == 1);
+           (p->even_odd == 0 || p->even_odd == 1) && p->profile >= 0 && p->profile <= 2;
 }
 
 bool defl_ok(const ovl_deflation *D)

@@ -447,17 +447,18 @@ __global__ __launch_bounds__(kBlock, PS == P_F48 && MBT <= 16 ? 3 : 1) void k_bl
 // The block pass build for the block length (16 residuals in registers, or
 // MB) and, in FP32, for the precision of the p_j of a continued FP64 solve.
 template <int PS, typename... A>
-static void launch_blk_pass(int m, bool pin48, dim3 grid, hipStream_t st, A... a)
+static void launch_blk_pass(int m, bool pin48, dim3 grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A... a)
 {
+    const dim3 b(kBlock);
     if constexpr (PS == P_F32) {
         if (pin48) {
-            if (m <= 16) k_blk_pass<PS, 16, true><<<grid, kBlock, 0, st>>>(a...);
-            else k_blk_pass<PS, MB, true><<<grid, kBlock, 0, st>>>(a...);
+            if (m <= 16) launch_k(k_blk_pass<PS, 16, true>, grid, b, st, e0, e1, a...);
+            else launch_k(k_blk_pass<PS, MB, true>, grid, b, st, e0, e1, a...);
             return;
         }
     }
-    if (m <= 16) k_blk_pass<PS, 16><<<grid, kBlock, 0, st>>>(a...);
-    else k_blk_pass<PS, MB><<<grid, kBlock, 0, st>>>(a...);
+    if (m <= 16) launch_k(k_blk_pass<PS, 16>, grid, b, st, e0, e1, a...);
+    else launch_k(k_blk_pass<PS, MB>, grid, b, st, e0, e1, a...);
 }
 
 // ring slot 0 = b, p0 = b (precision PS), and y = 0 or x_j = 0 (FP64).  The
@@ -673,6 +674,7 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
 
     Prof prof;
     prof.on = prm->profile != 0 && stats;
+    prof.stencil_only = prm->profile == 2;
     prof.st = st;
     long k = 0;
     int passes = 0, replacements = 0;
@@ -691,61 +693,64 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             hipError_t h = launch_convert(L, f, o.f16, st);
             return h == hipSuccess ? launch_convert(L, o.f16, f, st) : h;
         };
+        // each timed kernel records its own start and end (prof.pair)
+        hipEvent_t v0, v1;
         for (int q = 0; q < batch; q++, k++) {
-            int e0 = prof.mark();
+            prof.pair(OVL_K_STENCIL, &v0, &v1);
             if (trec && k > 0 && !(PS == P_F32 && q == 0)) {
                 // t = Q r_k + beta t (in place; beta of the previous iteration)
                 WArgs At = A;
                 At.in = slot(k);
                 At.p = t.d;
                 At.shiftv = S->beta;
-                OVL_HIP(launch_wilson(L, PS, W_SNORM, true, At, st));
+                OVL_HIP(launch_wilson(L, PS, W_SNORM, true, At, st, v0, v1));
             } else if (trec) {
                 // t = Q p0 directly: p0 = r0 at the start of a fresh solve, the
                 // handed-over p0 at the start of a resumed one, p_j0 at a block start
                 WArgs At = A;
                 if (k > 0) At.in = pj0.d;
                 else if (!o.resume) At.in = slot(0);
-                OVL_HIP(launch_wilson(L, PS, W_NORM, true, At, st));
+                OVL_HIP(launch_wilson(L, PS, W_NORM, true, At, st, v0, v1));
             } else {
-                OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st));
+                OVL_HIP(launch_wilson(L, PS, W_NORM, true, A, st, v0, v1));
             }
             if (f16) OVL_HIP(round16(t.d));
-            int e1 = prof.mark();
-            k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
-            int e2 = prof.mark();
+            prof.pair(OVL_K_SCALAR, &v0, &v1);
+            launch_k(k_ms_alpha, dim3(R), dim3(kBlock), st, v0, v1, S, (const double *)partials, nblk, npart);
             B.rin = slot(k);
             B.out = slot(k + 1);
-            OVL_HIP(launch_wilson(L, PS, rmode, true, B, st));
+            prof.pair(OVL_K_STENCIL, &v0, &v1);
+            OVL_HIP(launch_wilson(L, PS, rmode, true, B, st, v0, v1));
             if (f16) OVL_HIP(round16(slot(k + 1)));
-            int e3 = prof.mark();
-            k_blk_beta<<<R, kBlock, 0, st>>>(S, BK, partials, nblk, npart, sw2);
-            int e4 = prof.mark();
-            if (!trec) k_base_p<PS><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, slot(k + 1), p0.d);
+            prof.pair(OVL_K_SCALAR, &v0, &v1);
+            launch_k(k_blk_beta, dim3(R), dim3(kBlock), st, v0, v1, S, BK, (const double *)partials, nblk, npart, sw2);
+            if (!trec) {
+                prof.pair(OVL_K_UPDATE, &v0, &v1);
+                launch_k(k_base_p<PS>, sgrid, dim3(kBlock), st, v0, v1, L.g, L.nb, (const MState *)S,
+                         (const void *)slot(k + 1), p0.d);
+            }
             if (f16) OVL_HIP(round16(p0.d));
-            int e5 = prof.mark();
             OVL_HIP(hipGetLastError());
-            prof.span(e0, e1, OVL_K_STENCIL);
-            prof.span(e2, e3, OVL_K_STENCIL);
-            prof.span(e1, e2, OVL_K_SCALAR);
-            prof.span(e3, e4, OVL_K_SCALAR);
-            prof.span(e4, e5, OVL_K_UPDATE);
+            // the previous block's times, read while this iteration runs
+            if (q == 0) {
+                int prc = prof.collect(stats);
+                if (prc) return prc;
+            }
         }
         // block pass over the residuals r^{k0+1..k0+T} (slots k0+1 .. k0+batch)
         RingPtrs rp;
         for (int i = 0; i <= MB; i++) rp.slot[i] = slot((k - batch + i + (m + 1)) % (m + 1));
-        int e6 = prof.mark();
         // blocks of up to 16 take the build that holds 16 residuals in
         // registers (more waves per SIMD)
         const int first = !o.resume && passes == 0;
         const void *pin = PS == P_F32 && o.resume && passes == 0 ? o.resume->pj.d : nullptr;
         const bool pin48 = pin && o.resume->pj.prec == P_F48;
         const int xzero = passes == 0 ? o.x_zero_shifts : 0;
-        launch_blk_pass<PS>(m, pin48, sgrid, st, L.g, L.nb, S, BK, rp, sw, pj.d, xf, y, R, first, pin, xzero);
-        int e7 = prof.mark();
+        prof.pair(OVL_K_UPDATE, &v0, &v1);
+        launch_blk_pass<PS>(m, pin48, sgrid, st, v0, v1, L.g, L.nb, (const MState *)S, (const Blk *)BK, rp, sw, pj.d,
+                            xf, y, R, first, pin, xzero);
         k_blk_reset<<<R, NS, 0, st>>>(BK, S, R, nshift);
         OVL_HIP(hipGetLastError());
-        prof.span(e6, e7, OVL_K_UPDATE);
         passes++;
         OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
         OVL_HIP(hipStreamSynchronize(st));
@@ -791,6 +796,10 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             prof.span(e8, e9, OVL_K_OTHER);
             replacements++;
         }
+        int prc = prof.rotate(stats);
+        if (prc) return prc;
+    }
+    {
         int prc = prof.flush(stats);
         if (prc) return prc;
     }

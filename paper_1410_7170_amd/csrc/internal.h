@@ -1,6 +1,7 @@
 // Host-side declarations shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "../../include/ovl.h"
@@ -62,7 +63,19 @@ inline Fld sub(const Fld &f, int64_t V, int first, int count)
 }
 
 // ---- launchers (return hipError_t of the launch)
-hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hipStream_t st);
+// e0, e1 (optional): events the launch records at the stencil's start and end
+hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
+
+// A kernel launch that, given events, has its own dispatch record them at the
+// kernel's start and end (no marker packets in the queue); args must have the
+// kernel's parameter types.
+template <typename F, typename... A>
+inline void launch_k(F kern, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A... args)
+{
+    if (e0) hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0, e1, 0, args...);
+    else hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
+}
 // FP32 D_W (or Gamma_5 D_W) on the matrix cores (wilson_mfma.hip); a.g set
 hipError_t launch_wilson_mfma(const Lat &L, bool g5, const WArgs &a, hipStream_t st);
 hipError_t launch_pack_spinor(const Lat &L, const void *canon, Fld out, hipStream_t st);

@@ -1,6 +1,7 @@
 // Multishift CG state and kernels shared by the FP64 and mixed solvers.
 #pragma once
 
+#include <map>
 #include <vector>
 
 #include "internal.h"
@@ -130,53 +131,129 @@ int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld 
 // mark() records an event and returns its index; span(a, b, cls) charges the
 // interval between two marks to a kernel class; flush() synchronises and
 // adds the elapsed times to the stats.
+// Events of the profiling spans, kept for reuse across solves (per device:
+// an event belongs to the device current at its creation).
+inline std::vector<hipEvent_t> &event_cache(int dev)
+{
+    static thread_local std::map<int, std::vector<hipEvent_t>> c;
+    return c[dev];
+}
+
 struct Prof {
     bool on = false;
+    bool stencil_only = false;   // time only OVL_K_STENCIL (params.profile 2)
     hipStream_t st = nullptr;
-    std::vector<hipEvent_t> ev;
-    int n = 0;
+    int dev = -1;
     struct Span {
         int a, b, cls;
     };
-    std::vector<Span> spans;
+    // Two banks of events: a block records into one while the spans of the
+    // block before it, in the other, wait to be read (collect) until the new
+    // block's first launches are queued, so those event queries overlap GPU
+    // work instead of leaving the GPU idle at every block end.
+    std::vector<hipEvent_t> ev[2];
+    std::vector<Span> spans[2];
+    int used[2] = {0, 0};
+    int cur = 0, n = 0;
+    bool pending = false;
+    // the next event of the current bank (from the cache, else new)
+    hipEvent_t take()
+    {
+        std::vector<hipEvent_t> &e = ev[cur];
+        if (n == (int)e.size()) {
+            if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return nullptr;
+            std::vector<hipEvent_t> &c = event_cache(dev);
+            hipEvent_t x = nullptr;
+            if (!c.empty()) {
+                x = c.back();
+                c.pop_back();
+            } else if (hipEventCreate(&x) != hipSuccess) {
+                return nullptr;
+            }
+            e.push_back(x);
+        }
+        return e[n++];
+    }
+    // an event recorded here, in stream order (a span of class OVL_K_OTHER
+    // or OVL_K_UPDATE will follow); its index, or -1
     int mark()
     {
-        if (!on) return -1;
-        if (n == (int)ev.size()) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return -1;
-            ev.push_back(e);
-        }
-        if (hipEventRecord(ev[n], st) != hipSuccess) return -1;
-        return n++;
+        if (!on || stencil_only) return -1;
+        hipEvent_t e = take();
+        if (!e || hipEventRecord(e, st) != hipSuccess) return -1;
+        return n - 1;
+    }
+    // two events for a launch to record at its kernel's start and end
+    // (launch_k, launch_wilson), timed as one span of class cls; null when off
+    void pair(int cls, hipEvent_t *e0, hipEvent_t *e1)
+    {
+        *e0 = *e1 = nullptr;
+        if (!on || (stencil_only && cls != OVL_K_STENCIL)) return;
+        hipEvent_t a = take(), b = a ? take() : nullptr;
+        if (!a || !b) return;
+        *e0 = a;
+        *e1 = b;
+        spans[cur].push_back({n - 2, n - 1, cls});
     }
     void span(int a, int b, int cls)
     {
-        if (on && a >= 0 && b >= 0) spans.push_back({a, b, cls});
+        if (on && a >= 0 && b >= 0) spans[cur].push_back({a, b, cls});
     }
-    int flush(ovl_solver_stats *s)
+    // add the times of one bank's spans to the stats
+    int read(int bank, ovl_solver_stats *s)
     {
-        if (!on) return OVL_OK;
-        if (n > 0) {
-            hipError_t e = hipEventSynchronize(ev[n - 1]);
+        if (used[bank] > 0) {
+            hipError_t e = hipEventSynchronize(ev[bank][used[bank] - 1]);
             if (e != hipSuccess) return hip_fail(e);
         }
-        for (auto &sp : spans) {
+        for (auto &sp : spans[bank]) {
             float ms = 0.f;
-            hipError_t e = hipEventElapsedTime(&ms, ev[sp.a], ev[sp.b]);
+            hipError_t e = hipEventElapsedTime(&ms, ev[bank][sp.a], ev[bank][sp.b]);
             if (e != hipSuccess) return hip_fail(e);
             if (s) {
                 s->kernel_seconds[sp.cls] += 1e-3 * ms;
                 s->kernel_launches[sp.cls] += 1;
             }
         }
-        spans.clear();
+        spans[bank].clear();
+        used[bank] = 0;
+        return OVL_OK;
+    }
+    // read the spans left waiting by rotate
+    int collect(ovl_solver_stats *s)
+    {
+        if (!on || !pending) return OVL_OK;
+        pending = false;
+        return read(1 - cur, s);
+    }
+    // end of a block: its spans wait while the next block records into the
+    // other bank (read first whatever still waits there)
+    int rotate(ovl_solver_stats *s)
+    {
+        if (!on) return OVL_OK;
+        int rc = collect(s);
+        if (rc) return rc;
+        used[cur] = n;
+        pending = true;
+        cur = 1 - cur;
         n = 0;
         return OVL_OK;
     }
+    // read everything recorded so far
+    int flush(ovl_solver_stats *s)
+    {
+        if (!on) return OVL_OK;
+        int rc = collect(s);
+        if (rc) return rc;
+        used[cur] = n;
+        n = 0;
+        return read(cur, s);
+    }
     ~Prof()
     {
-        for (auto e : ev) (void)hipEventDestroy(e);
+        if (dev < 0) return;
+        std::vector<hipEvent_t> &c = event_cache(dev);
+        for (auto &b : ev) c.insert(c.end(), b.begin(), b.end());
     }
 };
 

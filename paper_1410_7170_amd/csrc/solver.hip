@@ -337,27 +337,25 @@ int mscg_f64(const Lat &L, const void *U64, double m0, int nshift, const double 
     bool done = false;
     Prof prof;
     prof.on = prm->profile != 0 && stats;
+    prof.stencil_only = prm->profile == 2;
     prof.st = st;
     while (it < prm->maxiter && !done) {
         int batch = std::min(check, prm->maxiter - it);
+        // each timed kernel records its own start and end (prof.pair)
+        hipEvent_t v0, v1;
         for (int k = 0; k < batch; k++) {
-            int e0 = prof.mark();
-            OVL_HIP(launch_wilson(L, P_F64, W_NORM, true, A, st));
-            int e1 = prof.mark();
-            k_ms_alpha<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
-            int e2 = prof.mark();
-            OVL_HIP(launch_wilson(L, P_F64, W_RUPDATE, true, B, st));
-            int e3 = prof.mark();
-            k_ms_beta<<<R, kBlock, 0, st>>>(S, partials, nblk, npart);
-            int e4 = prof.mark();
-            k_ms_update<P_F64><<<sgrid, kBlock, 0, st>>>(L.g, L.nb, S, r.d, nullptr, pfl.d, nullptr, x.d, nullptr, R);
-            int e5 = prof.mark();
+            prof.pair(OVL_K_STENCIL, &v0, &v1);
+            OVL_HIP(launch_wilson(L, P_F64, W_NORM, true, A, st, v0, v1));
+            prof.pair(OVL_K_SCALAR, &v0, &v1);
+            launch_k(k_ms_alpha, dim3(R), dim3(kBlock), st, v0, v1, S, (const double *)partials, nblk, npart);
+            prof.pair(OVL_K_STENCIL, &v0, &v1);
+            OVL_HIP(launch_wilson(L, P_F64, W_RUPDATE, true, B, st, v0, v1));
+            prof.pair(OVL_K_SCALAR, &v0, &v1);
+            launch_k(k_ms_beta, dim3(R), dim3(kBlock), st, v0, v1, S, (const double *)partials, nblk, npart);
+            prof.pair(OVL_K_UPDATE, &v0, &v1);
+            launch_k(k_ms_update<P_F64>, sgrid, dim3(kBlock), st, v0, v1, L.g, L.nb, (const MState *)S,
+                     (const void *)r.d, (const float *)nullptr, pfl.d, (float *)nullptr, x.d, (float *)nullptr, R);
             OVL_HIP(hipGetLastError());
-            prof.span(e0, e1, OVL_K_STENCIL);
-            prof.span(e2, e3, OVL_K_STENCIL);
-            prof.span(e1, e2, OVL_K_SCALAR);
-            prof.span(e3, e4, OVL_K_SCALAR);
-            prof.span(e4, e5, OVL_K_UPDATE);
             stencils += 2;
         }
         int prc = prof.flush(stats);

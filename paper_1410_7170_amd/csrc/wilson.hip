@@ -6,20 +6,26 @@
 namespace ovl {
 
 template <int PREC, int WPE, bool STAGE, int NT = kBlock, bool TILED = false>
-static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
+static void wilson_ts_dispatch_s(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st, hipEvent_t e0,
+                                 hipEvent_t e1)
 {
+    const dim3 b(NT);
     if (g5) {
         switch (mode) {
-        case W_PLAIN: k_wilson_ts<PREC, W_PLAIN, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
-        case W_NORM: k_wilson_ts<PREC, W_NORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
-        case W_SHIFT: k_wilson_ts<PREC, W_SHIFT, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
-        case W_RUPDATE: k_wilson_ts<PREC, W_RUPDATE, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
-        case W_RUPDATE0: k_wilson_ts<PREC, W_RUPDATE0, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
-        case W_SNORM: k_wilson_ts<PREC, W_SNORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
-        default: k_wilson_ts<PREC, W_RESNORM, true, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a); break;
+        case W_PLAIN: launch_k(k_wilson_ts<PREC, W_PLAIN, true, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a); break;
+        case W_NORM: launch_k(k_wilson_ts<PREC, W_NORM, true, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a); break;
+        case W_SHIFT: launch_k(k_wilson_ts<PREC, W_SHIFT, true, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a); break;
+        case W_RUPDATE:
+            launch_k(k_wilson_ts<PREC, W_RUPDATE, true, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a);
+            break;
+        case W_RUPDATE0:
+            launch_k(k_wilson_ts<PREC, W_RUPDATE0, true, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a);
+            break;
+        case W_SNORM: launch_k(k_wilson_ts<PREC, W_SNORM, true, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a); break;
+        default: launch_k(k_wilson_ts<PREC, W_RESNORM, true, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a); break;
         }
     } else {
-        k_wilson_ts<PREC, W_PLAIN, false, WPE, STAGE, NT, TILED><<<grid, NT, 0, st>>>(a);
+        launch_k(k_wilson_ts<PREC, W_PLAIN, false, WPE, STAGE, NT, TILED>, grid, b, st, e0, e1, a);
     }
 }
 
@@ -38,7 +44,8 @@ static bool staged_rows(const Geom &g, int sites)
 }
 
 template <int PREC>
-static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, int nt, const WArgs &a, hipStream_t st)
+static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, int nt, const WArgs &a, hipStream_t st, hipEvent_t e0,
+                               hipEvent_t e1)
 {
     // 192-thread blocks (three waves) in FP64 take the build capped at two
     // waves per SIMD: the one-wave build needs more than 256 registers, so a
@@ -48,21 +55,21 @@ static void wilson_ts_dispatch(int mode, bool g5, dim3 grid, int nt, const WArgs
     constexpr int W192 = PREC == P_F64 || PREC == P_F48 ? 2 : 1;
     if (a.kr > 0) {
         // RHS tiles: staged builds only (stencil_shape guarantees whole rows)
-        if (nt == 192) wilson_ts_dispatch_s<PREC, W192, true, 192, true>(mode, g5, grid, a, st);
-        else wilson_ts_dispatch_s<PREC, 1, true, kBlock, true>(mode, g5, grid, a, st);
+        if (nt == 192) wilson_ts_dispatch_s<PREC, W192, true, 192, true>(mode, g5, grid, a, st, e0, e1);
+        else wilson_ts_dispatch_s<PREC, 1, true, kBlock, true>(mode, g5, grid, a, st, e0, e1);
         return;
     }
     if (nt == 192) {
-        wilson_ts_dispatch_s<PREC, W192, true, 192>(mode, g5, grid, a, st);
+        wilson_ts_dispatch_s<PREC, W192, true, 192>(mode, g5, grid, a, st, e0, e1);
         return;
     }
     if (staged_rows(a.g, nt)) {
-        if (PREC == P_F48 && grid.x > 256) wilson_ts_dispatch_s<PREC, 2, true>(mode, g5, grid, a, st);
-        else wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st);
+        if (PREC == P_F48 && grid.x > 256) wilson_ts_dispatch_s<PREC, 2, true>(mode, g5, grid, a, st, e0, e1);
+        else wilson_ts_dispatch_s<PREC, 1, true>(mode, g5, grid, a, st, e0, e1);
     } else if (grid.x <= 512) {
-        wilson_ts_dispatch_s<PREC, 1, false>(mode, g5, grid, a, st);
+        wilson_ts_dispatch_s<PREC, 1, false>(mode, g5, grid, a, st, e0, e1);
     } else {
-        wilson_ts_dispatch_s<PREC, 2, false>(mode, g5, grid, a, st);
+        wilson_ts_dispatch_s<PREC, 2, false>(mode, g5, grid, a, st, e0, e1);
     }
 }
 
@@ -103,29 +110,40 @@ StencilShape stencil_shape(const Lat &L, int prec, int nrhs)
 }
 
 template <int PREC>
-static void wilson_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st)
+static void wilson_dispatch(int mode, bool g5, dim3 grid, const WArgs &a, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
+    const dim3 b(kBlock);
     if (g5) {
         switch (mode) {
-        case W_PLAIN: k_wilson<PREC, W_PLAIN, true><<<grid, kBlock, 0, st>>>(a); break;
-        case W_NORM: k_wilson<PREC, W_NORM, true><<<grid, kBlock, 0, st>>>(a); break;
-        case W_SHIFT: k_wilson<PREC, W_SHIFT, true><<<grid, kBlock, 0, st>>>(a); break;
-        case W_RUPDATE: k_wilson<PREC, W_RUPDATE, true><<<grid, kBlock, 0, st>>>(a); break;
-        case W_RUPDATE0: k_wilson<PREC, W_RUPDATE0, true><<<grid, kBlock, 0, st>>>(a); break;
-        case W_SNORM: k_wilson<PREC, W_SNORM, true><<<grid, kBlock, 0, st>>>(a); break;
-        default: k_wilson<PREC, W_RESNORM, true><<<grid, kBlock, 0, st>>>(a); break;
+        case W_PLAIN: launch_k(k_wilson<PREC, W_PLAIN, true>, grid, b, st, e0, e1, a); break;
+        case W_NORM: launch_k(k_wilson<PREC, W_NORM, true>, grid, b, st, e0, e1, a); break;
+        case W_SHIFT: launch_k(k_wilson<PREC, W_SHIFT, true>, grid, b, st, e0, e1, a); break;
+        case W_RUPDATE: launch_k(k_wilson<PREC, W_RUPDATE, true>, grid, b, st, e0, e1, a); break;
+        case W_RUPDATE0: launch_k(k_wilson<PREC, W_RUPDATE0, true>, grid, b, st, e0, e1, a); break;
+        case W_SNORM: launch_k(k_wilson<PREC, W_SNORM, true>, grid, b, st, e0, e1, a); break;
+        default: launch_k(k_wilson<PREC, W_RESNORM, true>, grid, b, st, e0, e1, a); break;
         }
     } else {
-        k_wilson<PREC, W_PLAIN, false><<<grid, kBlock, 0, st>>>(a);
+        launch_k(k_wilson<PREC, W_PLAIN, false>, grid, b, st, e0, e1, a);
     }
 }
 
-hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hipStream_t st)
+hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1)
 {
     a.g = L.g;
     a.nblk = 2 * L.nb;
     a.kr = 0;
-    if (prec == P_F32 && mode == W_PLAIN && L.g.Mfma && a.nrhs >= 2) return launch_wilson_mfma(L, g5, a, st);
+    if (prec == P_F32 && mode == W_PLAIN && L.g.Mfma && a.nrhs >= 2) {
+        // the matrix-core form: events as markers around its launch
+        if (e0) {
+            const hipError_t h0 = hipEventRecord(e0, st);
+            if (h0 != hipSuccess) return h0;
+        }
+        const hipError_t h = launch_wilson_mfma(L, g5, a, st);
+        if (h == hipSuccess && e1) return hipEventRecord(e1, st);
+        return h;
+    }
     const StencilShape sh = stencil_shape(L, prec, a.nrhs);
     if (sh.ts > 0) {
         // time-streaming form (FP64, 48-bit, FP32): blocks_per_tile blocks per RHS
@@ -135,16 +153,16 @@ hipError_t launch_wilson(const Lat &L, int prec, int mode, bool g5, WArgs a, hip
         a.kr = sh.kr;
         if (prec == P_F48) a.g.Ts64 = sh.ts;   // the kernel reads its length from there
         dim3 grid((unsigned)sh.blocks_per_tile * sh.ntile);
-        if (prec == P_F64) wilson_ts_dispatch<P_F64>(mode, g5, grid, sh.nt, a, st);
-        else if (prec == P_F48) wilson_ts_dispatch<P_F48>(mode, g5, grid, sh.nt, a, st);
-        else wilson_ts_dispatch<P_F32>(mode, g5, grid, sh.nt, a, st);
+        if (prec == P_F64) wilson_ts_dispatch<P_F64>(mode, g5, grid, sh.nt, a, st, e0, e1);
+        else if (prec == P_F48) wilson_ts_dispatch<P_F48>(mode, g5, grid, sh.nt, a, st, e0, e1);
+        else wilson_ts_dispatch<P_F32>(mode, g5, grid, sh.nt, a, st, e0, e1);
         return hipGetLastError();
     }
     dim3 grid(2 * L.nb * a.nrhs);
-    if (prec == P_F64) wilson_dispatch<P_F64>(mode, g5, grid, a, st);
-    else if (prec == P_F48) wilson_dispatch<P_F48>(mode, g5, grid, a, st);
-    else if (prec == P_F32) wilson_dispatch<P_F32>(mode, g5, grid, a, st);
-    else wilson_dispatch<P_F16S>(mode, g5, grid, a, st);
+    if (prec == P_F64) wilson_dispatch<P_F64>(mode, g5, grid, a, st, e0, e1);
+    else if (prec == P_F48) wilson_dispatch<P_F48>(mode, g5, grid, a, st, e0, e1);
+    else if (prec == P_F32) wilson_dispatch<P_F32>(mode, g5, grid, a, st, e0, e1);
+    else wilson_dispatch<P_F16S>(mode, g5, grid, a, st, e0, e1);
     return hipGetLastError();
 }
 

@@ -342,3 +342,40 @@ def test_rhs_groups_match_whole_batch(ovl, mode):
     else:
         assert np.array_equal(g1, g2)
         assert st1["iterations"] == st2["iterations"] and st1["shift_iters"] == st2["shift_iters"]
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp64_blocked", "mixed"])
+def test_profile_stats_are_consistent(ovl, mode):
+    """profile = 1 times the solver's kernels with HIP events: one stencil
+    span per stencil launched in the iterations, one scalar span each for
+    alpha and beta, block passes (or the plain form's shift updates) as update
+    spans, every class timed; profile = 2 times the same stencil launches and
+    nothing else; the result equals the unprofiled one bit for bit."""
+    dims = (8, 4, 4, 8)
+    note(f"profile stats {mode} {dims}")
+    U = synth.gauge(dims, 0.3, 41, n_stout=2)
+    lat, olat, G, (s, w, d, lo, hi), _ = both_sides(ovl, dims, U)
+    b = synth.gaussian_spinor(lat.V, 42)[0]
+    B = ovl.Spinor.from_canonical(lat, dev(b), 0)
+    kw = dict(tol=1e-10, maxiter=5000, block=0 if mode == "fp64" else 8)
+    if mode == "mixed":
+        kw["mode"] = ovl.SOLVE_MIXED
+    out = {}
+    for prof in (0, 1, 2):
+        O = ovl.Spinor(lat, 0)
+        st = ovl.overlap_apply(lat, G, RHO, s, w, B, O, ovl.default_params(profile=prof, **kw))
+        out[prof] = (O.to_canonical().cpu().numpy(), st)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][0], out[2][0])
+    st = out[1][1]
+    launches, secs = st["kernel_launches"], st["kernel_seconds"]
+    assert launches[0] > 0 and launches[0] % 2 == 0
+    assert launches[2] == launches[0]                 # alpha and beta per pair of stencils
+    assert launches[1] >= 1                          # block passes
+    assert all(t > 0 for t in secs[:3])
+    if mode != "mixed":
+        # every stencil but the overlap's final D_W (no residual replacements)
+        assert launches[0] == st["stencil_applies"] - 1
+    assert out[0][1]["kernel_launches"] == [0, 0, 0, 0]
+    light = out[2][1]
+    assert light["kernel_launches"] == [launches[0], 0, 0, 0]
+    assert light["kernel_seconds"][0] > 0 and light["kernel_seconds"][1:] == [0.0, 0.0, 0.0]

@@ -683,8 +683,16 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
     const double sw2 = o.switch_rel * o.switch_rel;
     long it_left = prm->maxiter;
     for (int q = 0; q < R; q++) it_left = std::min<long>(it_left, prm->maxiter - it0[q]);
+    // the next block's length (below); |r|^2 at the last block end
+    int next_batch = m;
+    double rr_prev[NR];
+    bool rr_known = false;
+    if (o.resume) {
+        for (int q = 0; q < R; q++) rr_prev[q] = h.rr[q];
+        rr_known = true;
+    }
     while (k < it_left && !done && !switched) {
-        int batch = (int)std::min<long>(m, it_left - k);
+        int batch = (int)std::min<long>(next_batch, it_left - k);
         // FP16 storage of the Krylov vectors (measurement mode): each new
         // vector is rounded through the FP16S set and back after its kernel
         const bool f16 = PS == P_F32 && o.f16.d;
@@ -767,6 +775,35 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             if (!fin && !h.paused[q]) switched = false;
         }
         switched = switched && !done;
+        // The next block's length: the iterations the slowest system still
+        // needs (the base, which freezes last, or the hand-over level),
+        // predicted from the fall of |r| over this block with a quarter and
+        // two iterations to spare.  Launches past an RHS's end exit at once
+        // but still cost a launch and a gap each; a block cut short costs
+        // one more block pass.
+        next_batch = m;
+        if (rr_known) {
+            int need = 0;
+            bool ok = true;
+            for (int q = 0; q < R && ok; q++) {
+                if (h.skip[q]) continue;
+                const double target = std::max(h.tol2r[q], sw2) * h.bb[q];
+                const double r0 = rr_prev[q], r1 = h.rr[q];
+                if (!(r1 > target)) {
+                    need = std::max(need, 2);
+                    continue;
+                }
+                if (!(r1 > 0.0 && r0 > r1)) {
+                    ok = false;
+                    break;
+                }
+                const double per = std::log(r1 / r0) / batch;
+                need = std::max(need, (int)std::ceil(1.25 * std::log(target / r1) / per) + 2);
+            }
+            if (ok && need > 0) next_batch = std::min(m, need);
+        }
+        for (int q = 0; q < R; q++) rr_prev[q] = h.rr[q];
+        rr_known = true;
         if (o.reliable && want && !done && !switched) {
             // residual replacement: r = b - (Q^2 + s0) x_0 in FP64
             int e8 = prof.mark();

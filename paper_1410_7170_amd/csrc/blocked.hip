@@ -627,8 +627,13 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         if (PS != P_F32) OVL_HIP(launch_convert(L, rs.pj, pj, st));
         k_resume<<<1, 64, 0, st>>>(S, R);
         OVL_HIP(hipGetLastError());
-        OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
-        OVL_HIP(hipStreamSynchronize(st));
+        if (rs.host) {
+            // the caller's copy has what the host needs (no wait for the GPU)
+            h = *rs.host;
+        } else {
+            OVL_HIP(hipMemcpyAsync(&h, S, sizeof(MState), hipMemcpyDeviceToHost, st));
+            OVL_HIP(hipStreamSynchronize(st));
+        }
         for (int q = 0; q < R; q++) it0[q] = h.iter[q];
     } else {
         int rc = mscg_init_state(L, S, partials, red, b, nshift, shifts, prm, &j0, st, o.rhs_shift, o.rhs_tol);
@@ -805,7 +810,9 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
         for (int q = 0; q < R; q++) rr_prev[q] = h.rr[q];
         rr_known = true;
         if (o.reliable && want && !done && !switched) {
-            // residual replacement: r = b - (Q^2 + s0) x_0 in FP64
+            // residual replacement: r = b - (Q^2 + s0) x_0 in FP64: s1 = Q x0,
+            // then the residual-update stencil r = b - 1 * (Q s1 + s0 x0) with
+            // its partials of |r|^2 (the unshifted base reads no x0)
             int e8 = prof.mark();
             Fld x0 = sub(xs, L.V, j0 * R, R);
             WArgs Q1{};
@@ -820,10 +827,11 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
             Q2.in = s1.d;
             Q2.p = x0.d;
             Q2.shiftv = S->s0r;
+            Q2.rin = b.d;
             Q2.out = s2.d;
-            OVL_HIP(launch_wilson(L, P_F64, W_SHIFT, true, Q2, st));
-            OVL_HIP(launch_axpby(L, 1.0, b, -1.0, s2, st));
-            OVL_HIP(launch_norm2(L, s2, partials, st));
+            Q2.alpha = S->one;
+            Q2.partials = partials;
+            OVL_HIP(launch_wilson(L, P_F64, rmode, true, Q2, st));
             OVL_HIP(launch_reduce(partials, 1, R, nblk, red, st));
             Fld cur{slot(k), nullptr, PS, R};
             OVL_HIP(launch_convert(L, s2, cur, st));
@@ -902,7 +910,8 @@ int mscg_blocked_t(const Lat &L, const ovl_gauge *U, double m0, int nshift, cons
                     !fresh && PS == P_F32 ? (double)field_bytes(o.resume->pj.prec, L.V) - Fs : 0.0;
                 if (np > 0) pass += pj_io * Fs + wide + (o.keep_x ? 2.0 * np * F8 : 0.0);
             }
-        double other = replacements * (R * (2 * 768.0 * L.V + 6 * F8) + R * Fs);
+        // replacement: Q x0 (768 B per site), the update stencil, the rounding into the ring
+        double other = replacements * R * ((768.0 + (rmode == W_RUPDATE0 ? 960.0 : 1152.0)) * L.V + F8 + Fs);
         stats->kernel_bytes[OVL_K_STENCIL] += sten;
         stats->kernel_bytes[OVL_K_UPDATE] += upd + pass;
         stats->kernel_bytes[OVL_K_OTHER] += other;

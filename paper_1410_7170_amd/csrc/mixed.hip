@@ -239,6 +239,7 @@ static int mixed_solve(const Lat &L, const ovl_gauge *U, double m0, int nshift, 
         if (h64.r.prec == P_F64) OVL_HIP(hipMemcpyAsync(R0.d, h64.r.d, F * R, hipMemcpyDeviceToDevice, st));
         else OVL_HIP(launch_convert(L, h64.r, R0, st));
         r0 = R0;
+        h64.host = &hs;
         o.resume = &h64;
         o.x_zero_shifts = nz;   // the increments dx_j (j < nz) start at zero
         // dx_j take over the FP64 p_j, which the first pass reads in place;

@@ -68,6 +68,7 @@ struct MState {
     // continues its recurrences clears both
     int paused[NR];
     int run_c[NR];         // the iteration's p0 update is due (set by K_b, cleared by K_a)
+    double one[NR];        // 1 per RHS: the alpha of a residual replacement's update stencil
 };
 
 struct ShiftWeights {
@@ -112,6 +113,9 @@ struct MsScratch {
     MState *S = nullptr;
     Fld r{}, p0{}, pj{};
     int j0 = 0;
+    // a host copy of S taken after the switch (optional): a solve continuing
+    // these recurrences reads its iteration counts and |r|^2 from there
+    const MState *host = nullptr;
     // a switched y-mode solve with 48-bit storage: room for nrhs*nshift FP64
     // fields over its dead ring, p0 and t, where a solve continuing it keeps x_j
     void *xlend = nullptr;

@@ -263,6 +263,7 @@ int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld 
         h.s0r[r] = rhs_shift ? rhs_shift[r] : shifts[j0];
         double t = rhs_tol ? rhs_tol[r] : prm->tol;
         h.tol2r[r] = t * t;
+        h.one[r] = 1.0;
     }
     h.nrhs = R;
     h.nshift = nshift;

@@ -131,10 +131,6 @@ int mscg_init_state(const Lat &L, MState *S, double *partials, double *red, Fld 
                     const ovl_solver_params *prm, int *j0_out, hipStream_t st, const double *rhs_shift,
                     const double *rhs_tol);
 
-// Optional event timing of the solver's kernels, on the solver's stream.
-// mark() records an event and returns its index; span(a, b, cls) charges the
-// interval between two marks to a kernel class; flush() synchronises and
-// adds the elapsed times to the stats.
 // Events of the profiling spans, kept for reuse across solves (per device:
 // an event belongs to the device current at its creation).
 inline std::vector<hipEvent_t> &event_cache(int dev)
@@ -143,6 +139,12 @@ inline std::vector<hipEvent_t> &event_cache(int dev)
     return c[dev];
 }
 
+// Optional event timing of the solver's kernels, on the solver's stream.
+// pair(cls, &e0, &e1) hands out two events for a launch to record at its
+// kernel's start and end and charges that span to a kernel class; mark()
+// records an event in stream order and span(a, b, cls) charges the interval
+// between two marks.  rotate() ends a block, collect() adds the previous
+// block's times to the stats, flush() everything recorded so far.
 struct Prof {
     bool on = false;
     bool stencil_only = false;   // time only OVL_K_STENCIL (params.profile 2)
